@@ -1,0 +1,118 @@
+"""Pins of the oracle's march (Eq. (3) applied volume after volume, Section 3)
+and of its tallies, against closed forms that do not use the march:
+
+* a uniform multi-cell slab crossed along its axis has the one-volume closed
+  form I_exit = I_in exp(-kappa L) + B (1 - exp(-kappa L)) for the whole
+  length L, i.e. transmissivity exp(-kappa L) (composition over cells must
+  reproduce it);
+* kappa = 0: nothing absorbed or emitted, every ray leaves as it entered;
+* optically thick: the exit intensity is the Planck function of the last cell;
+* energy balance: entering + emitted = absorbed + escaped (exact per ray);
+* thin uniform medium: emitted power = 4 pi kappa B V dnu per spectral point
+  (mean chord 4V/S), which fixes the ray weight pi A dnu / N.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_cs_0703028_amd import inputs as I
+
+U = 1 << 21
+
+
+def _uniform_row(nx, h_m, T, x, p, T_wall, lines):
+    g = I.Grid(nx, 1, 1, h_m, np.full(nx, T), np.full(nx, x), np.full(nx, p), T_wall)
+    return g
+
+
+def _lines(n_nu=400, S_scale=1.0, seed=1):
+    L = I.line_list(60, 1000.0, 1004.0, seed=seed, n_nu=n_nu, cutoff=1.0)
+    L.S = L.S * S_scale
+    return L
+
+
+def test_uniform_slab_closed_form():
+    L = _lines(S_scale=0.01)
+    g = _uniform_row(10, 0.1, 900.0, 0.1, 1.0, 1500.0, L)
+    kap = O.kappa(g, L)
+    B = O.planck_rows(g, L)
+    O_ = np.array([[0, U // 2 + 1, U // 2 + 1]], np.int64)
+    D_ = np.array([[1 << 20, 0, 0]], np.int64)
+    _, _, bal, exit_I = O.march(g, L, O_, D_, 1.0, kap, B, want_exit=True)
+    Lcm = 10 * 0.1 * 100.0
+    nu = L.nu0 + np.arange(L.n_nu) * L.dnu
+    Bw = np.array([O.planck(v, 1500.0) for v in nu])
+    t = np.exp(-kap[0] * Lcm)
+    expect = Bw * t + B[0] * (1.0 - t)
+    np.testing.assert_allclose(exit_I[0], expect, rtol=1e-12, atol=0)
+    # transmissivity of the slab: (I_exit - B)/(I_in - B) = exp(-kappa L)
+    sel = t > 1e-4  # where I_exit - B is not itself a cancellation
+    assert sel.sum() > 50
+    np.testing.assert_allclose(((exit_I[0] - B[0]) / (Bw - B[0]))[sel], t[sel], rtol=1e-9)
+    assert kap[0].min() > 0 and (kap[0] * Lcm).max() > 1.0 and (kap[0] * Lcm).min() < 0.1
+
+
+def test_transparent_medium():
+    L = _lines()
+    g = I.small_ragged().grid
+    g.x = np.zeros(g.n_cells)
+    g.T_wall = 1300.0
+    kap = O.kappa(g, L)
+    assert (kap == 0).all()
+    B = O.planck_rows(g, L)
+    Os, Ds, _ = O.rays(4, 0, 50, g.nx, g.ny, g.nz)
+    a, e, bal, exit_I = O.march(g, L, Os, Ds, 0.5, kap, B, want_exit=True)
+    assert (a == 0).all() and (e == 0).all()
+    nu = L.nu0 + np.arange(L.n_nu) * L.dnu
+    Bw = np.array([O.planck(v, 1300.0) for v in nu])
+    assert (exit_I == Bw[None, :]).all()
+    assert bal[0] == bal[3] and bal[1] == 0 and bal[2] == 0
+
+
+def test_thick_limit_exit_is_last_cell_planck():
+    L = _lines(S_scale=1e6)
+    g = I.linear_T_grid(6, 0.2, ny=1, nz=1, T_wall=0.0)
+    kap = O.kappa(g, L)
+    B = O.planck_rows(g, L)
+    assert (kap * 20.0).min() > 60.0
+    O_ = np.array([[0, U // 2 + 1, U // 2 + 1], [6 * U, U // 2 - 1, U // 2 + 3]], np.int64)
+    D_ = np.array([[1 << 20, 3, 0], [-(1 << 20), 0, -1]], np.int64)
+    _, _, _, exit_I = O.march(g, L, O_, D_, 1.0, kap, B, want_exit=True)
+    np.testing.assert_allclose(exit_I[0], B[5], rtol=1e-12)
+    np.testing.assert_allclose(exit_I[1], B[0], rtol=1e-12)
+
+
+@pytest.mark.parametrize("T_wall", [0.0, 1250.0])
+def test_energy_balance(T_wall):
+    w = I.small_ragged()
+    w.grid.T_wall = T_wall
+    res = O.run(w.grid, w.lines, w.n_rays, seed=w.seed)
+    ent, emi, ab, esc = res["balance"]
+    assert abs((ent + emi) - (ab + esc)) <= 1e-12 * (ent + emi)
+    assert emi == pytest.approx(res["emitted"].sum(), rel=1e-12)
+    assert ab == pytest.approx(res["absorbed"].sum(), rel=1e-12)
+    if T_wall == 0.0:
+        assert ent == 0.0
+    assert (res["absorbed"] >= 0).all() and (res["emitted"] > 0).all()
+
+
+def test_thin_medium_emission_and_ray_weight():
+    # tiny kappa: emitted = sum w B kappa l  ->  4 pi kappa B V dnu per point
+    n, h = 3, 0.2
+    L = _lines(n_nu=64, S_scale=1e-7)
+    g = I.Grid(n, n, n, h, np.full(n ** 3, 1100.0), np.full(n ** 3, 0.1), np.full(n ** 3, 1.0), 0.0)
+    N = 20000
+    res = O.run(g, L, N, seed=9)
+    kap = res["kappa"][0]
+    B = res["planck"][0]
+    assert (kap * h * 100 * math.sqrt(3) * n).max() < 1e-4
+    V = (n * h) ** 3
+    expect = (4 * math.pi * (kap * 100.0) * B * V * L.dnu).sum()
+    got = res["balance"][1]
+    # statistical: chord std / mean ~ 0.5 for a cube
+    assert abs(got / expect - 1.0) < 4 * 0.5 / math.sqrt(N)
+    # the same rays with a known weight give a deterministic scale check
+    w = O.ray_weight(g, L, N)
+    assert w == pytest.approx(math.pi * 6 * (n * h) ** 2 * L.dnu / N, rel=1e-15)
