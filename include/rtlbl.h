@@ -1,0 +1,170 @@
+/*
+ * rtlbl.h -- C ABI of the MI355X (gfx950) line-by-line Monte-Carlo radiative
+ * ray tracer.
+ *
+ * The calls follow the problem as the paper states it (Collange, Daumas,
+ * Defour, "Graphic processors to speed-up simulations for the design of high
+ * performance solar receptors", Section 3): a finite-volume code holds per
+ * volume the temperature, pressure and density of absorbing gas; line-by-line
+ * spectra give each volume its absorption coefficient (Eqs. (1)-(2));
+ * Monte-Carlo rays are marched volume after volume with Beer-Lambert
+ * attenuation and Planck emission (Eqs. (3)-(4)); the power exchanged,
+ * a sum of I_in - I_out, is returned to the host.
+ *
+ * Conventions shared by every call
+ *   - Units: wavenumbers and half widths in cm^-1, line strengths in
+ *     cm/molecule, temperatures in K, pressures in atm, cell edge in m,
+ *     kappa in cm^-1, radiance in W m^-2 sr^-1 (cm^-1)^-1, power in W.
+ *   - Cells are indexed c = ix + nx*(iy + ny*iz).
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     may free them afterwards.
+ *   - Device buffers passed in (kappa, Planck table) stay owned by the
+ *     caller and must stay alive until every call that reads them has
+ *     completed on the stream.
+ *   - All device work is ordered on the stream given at creation; only
+ *     rt_tally, rt_debug_segments, rt_get_stats and rt_destroy synchronise.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *   - Every call returns RT_OK or a negative rt_status; it never aborts.
+ *     rt_last_error gives the message of the last failure on the handle.
+ */
+#ifndef RTLBL_H
+#define RTLBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rt_ctx_s* rt_ctx;
+
+typedef enum {
+  RT_OK = 0,
+  RT_EINVAL = -1,       /* an argument is out of range, NULL or not finite */
+  RT_ENOMEM = -2,       /* a device or host allocation failed              */
+  RT_EDEVICE = -3,      /* a HIP call failed                               */
+  RT_ESTATE = -4,       /* calls made out of order                         */
+  RT_EUNSUPPORTED = -5  /* mode not available in this build                */
+} rt_status;
+
+typedef enum {
+  RT_KAPPA_PLAIN = 0,       /* FP32 line sum                                */
+  RT_KAPPA_COMPENSATED = 1  /* FP32 line sum with compensated summation     */
+} rt_kappa_mode;
+
+typedef enum {
+  RT_TALLY_F32 = 0,  /* per-wavefront partial sums in FP32, FP64 accumulators */
+  RT_TALLY_F64 = 1   /* partial sums in FP64 as well (precision form)         */
+} rt_tally_prec;
+
+typedef struct {
+  double line_evals;        /* in-window (cell, line, nu) triples evaluated by
+                               rt_compute_kappa since the last reset          */
+  double kappa_ms;          /* device time of the line-sum kernels since then */
+  double updates;           /* ray-cell-nu updates since the last reset       */
+  double segments;          /* ray-cell segments since the last reset         */
+  double trace_ms;          /* device time of rt_trace_rays since the reset   */
+  double march_ms;          /* of which in the march kernel                    */
+  double rays;              /* rays traced since the last reset               */
+  double march_launches;    /* march kernel launches since the last reset     */
+} rt_stats;
+
+/* Create a handle bound to HIP device `hip_device` and the borrowed stream
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  The stream is not
+ * owned: it must outlive the handle. */
+rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream);
+
+/* Synchronise the stream and free everything the handle owns. */
+rt_status rt_destroy(rt_ctx ctx);
+
+/* Message of the last failed call on `ctx` (or of rt_create when ctx is
+ * NULL); valid until the next call on the handle. */
+const char* rt_last_error(rt_ctx ctx);
+
+/* The finite-volume grid (Section 3: isothermal homogeneous volumes).
+ * nx, ny, nz >= 1, nx*ny*nz < 2^31, each <= 2^20; cubic cells of edge
+ * cell_m > 0 metres; T_K > 0, 0 <= x_h2o <= 1, p_atm > 0 per cell (host
+ * arrays of nx*ny*nz doubles, copied); T_wall_K >= 0 is the temperature of
+ * the black walls (0: cold walls, nothing enters).  Resets the tallies and
+ * invalidates a previous rt_compute_kappa. */
+rt_status rt_setup_grid(rt_ctx ctx, int nx, int ny, int nz, double cell_m,
+                        const double* T_K, const double* x_h2o,
+                        const double* p_atm, double T_wall_K);
+
+/* The line list (Eqs. (1)-(2)) and the spectral grid nu_j = nu0_cm + j*dnu_cm,
+ * 0 <= j < n_nu.  Per line: centre nu_cm, strength S_ref at T_ref_K [cm per
+ * molecule] (>= 0), Lorentz half width gamma_ref_cm at T_ref and 1 atm (> 0),
+ * half-width temperature exponent n_T, lower-state energy E_lower_cm (>= 0;
+ * NULL: the strength is taken as temperature independent, Eq. (1) ratio 1).
+ * Each line is evaluated on the points with |nu_j - nu_line| <= cutoff_cm;
+ * cutoff_cm/dnu_cm must be an integer (to 1e-9 relative).  n_lines >= 0,
+ * n_nu >= 1, dnu_cm > 0.  Host arrays are copied.  Invalidates a previous
+ * rt_compute_kappa. */
+rt_status rt_setup_lines(rt_ctx ctx, int n_lines, const double* nu_cm,
+                         const double* S_ref, const double* gamma_ref_cm,
+                         const double* n_T, const double* E_lower_cm,
+                         double T_ref_K, double cutoff_cm, double nu0_cm,
+                         double dnu_cm, int n_nu);
+
+/* Smallest admissible row pitch (in floats) of the kappa and Planck tables
+ * for the current spectral grid: n_nu rounded up to the march chunk. */
+int64_t rt_required_pitch(rt_ctx ctx);
+
+/* Eq. (2) with Eq. (1) per cell: kappa_dev[c*ld + j] = kappa_c(nu_j) in
+ * cm^-1, and Eq. (4): planck_dev[c*ld + j] = B(nu_j, T_c).  Both are caller
+ * allocated device buffers of nx*ny*nz rows of `ld` floats, ld >=
+ * rt_required_pitch (columns n_nu .. ld-1 are written with zeros).  The
+ * handle keeps both pointers for rt_trace_rays.  mode: rt_kappa_mode. */
+rt_status rt_compute_kappa(rt_ctx ctx, int mode, float* kappa_dev,
+                           float* planck_dev, int64_t ld);
+
+/* Monte-Carlo rays (Section 3: the host directs the rays and averages their
+ * effect).  Traces rays ray_begin .. ray_begin+ray_count-1 of a set of
+ * n_rays_total rays drawn with `seed`: a uniform point on the boundary and
+ * a cosine-weighted inward direction from a Philox4x64-10 stream, exact
+ * integer traversal, then Eq. (3) cell after cell for every nu_j with ray
+ * weight pi * A_boundary * dnu / n_rays_total.  Adds to the per-cell
+ * absorbed/emitted power and to the energy balance; ranges may be traced in
+ * any order and any split (tallies add).  tally_prec: rt_tally_prec.
+ * Requires rt_compute_kappa. */
+rt_status rt_trace_rays(rt_ctx ctx, uint64_t seed, uint64_t n_rays_total,
+                        uint64_t ray_begin, uint64_t ray_count,
+                        int tally_prec);
+
+/* Rays given explicitly in the fixed-point frame (one cell edge = 2^21
+ * units): origin O[3*r..] on the boundary, inward integer direction
+ * D[3*r..] (|D_k| <= 2^21), host arrays, n_rays >= 1, with the given
+ * weight.  For closed-form checks (slabs, axis-normal rays).  If exit_I is
+ * not NULL it is a host array of n_rays*n_nu doubles receiving the
+ * radiance at exit.  Synchronises when exit_I is given. */
+rt_status rt_trace_explicit(rt_ctx ctx, int n_rays, const int64_t* O,
+                            const int64_t* D, double weight, int tally_prec,
+                            double* exit_I);
+
+/* Copies the tallies to the host (synchronises): absorbed_W[c] and
+ * emitted_W[c] (host arrays of nx*ny*nz doubles, each may be NULL) and
+ * balance[4] = {entering, emitted, absorbed, escaped} in W (may be NULL). */
+rt_status rt_tally(rt_ctx ctx, double* absorbed_W, double* emitted_W,
+                   double* balance);
+
+/* Zeroes the tallies, the work counters and the timers (may synchronise). */
+rt_status rt_reset_tally(rt_ctx ctx);
+
+/* Traversal of rays ray_begin .. ray_begin+count-1 (as rt_trace_rays draws
+ * them) for bit-exact checks: counts[r] segments, cells[r*max_segs + k] and
+ * len_cm[r*max_segs + k]; host arrays; max_segs >= nx+ny+nz.  Also returns
+ * the integer origin O[3r..] and direction D[3r..] when those are not NULL.
+ * Synchronises. */
+rt_status rt_debug_segments(rt_ctx ctx, uint64_t seed, uint64_t ray_begin,
+                            uint64_t count, int max_segs, int32_t* counts,
+                            int32_t* cells, float* len_cm, int64_t* O,
+                            int64_t* D);
+
+/* Work counters and device times (synchronises). */
+rt_status rt_get_stats(rt_ctx ctx, rt_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTLBL_H */

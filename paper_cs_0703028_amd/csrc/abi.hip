@@ -1,0 +1,577 @@
+// abi.hip -- host side of the C ABI declared in include/rtlbl.h: argument
+// validation, device memory owned by the handle, launch sequencing on the
+// borrowed stream, timing with HIP events.  Every failure is reported as a
+// status code plus a message; nothing aborts.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+rt_status fail(rt_ctx c, rt_status s, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return s;
+}
+
+rt_status hip_fail(rt_ctx c, hipError_t e, const char* what) {
+  return fail(c, (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? RT_ENOMEM : RT_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define RT_HIP(ctx, call)                                   \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);  \
+  } while (0)
+
+template <class T>
+hipError_t dev_alloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+template <class T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+bool finite_all(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+void free_lines(rt_ctx c) {
+  rt::LineSet& L = c->lines;
+  dev_free(L.m); dev_free(L.phi); dev_free(L.wlo); dev_free(L.whi); dev_free(L.S);
+  dev_free(L.E2); dev_free(L.nu); dev_free(L.gamma); dev_free(L.nexp);
+  L.n = 0;
+}
+
+void free_cells(rt_ctx c) {
+  rt::CellSet& C = c->cells;
+  dev_free(C.G); dev_free(C.beta); dev_free(C.theta); dev_free(C.lam2); dev_free(C.P);
+}
+
+void free_events(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+  for (auto& e : v) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  v.clear();
+}
+
+rt_status record_begin(rt_ctx c, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+  hipEvent_t a, b;
+  RT_HIP(c, hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  if (e != hipSuccess) { (void)hipEventDestroy(a); return hip_fail(c, e, "hipEventCreate"); }
+  v.emplace_back(a, b);
+  RT_HIP(c, hipEventRecord(a, c->stream));
+  return RT_OK;
+}
+
+rt_status record_end(rt_ctx c, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+  RT_HIP(c, hipEventRecord(v.back().second, c->stream));
+  return RT_OK;
+}
+
+// Sum of elapsed times of completed event pairs (ms); the list is emptied.
+rt_status drain_events(rt_ctx c, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double* ms) {
+  double t = 0;
+  for (auto& e : v) {
+    RT_HIP(c, hipEventSynchronize(e.second));
+    float f = 0;
+    RT_HIP(c, hipEventElapsedTime(&f, e.first, e.second));
+    t += f;
+  }
+  free_events(v);
+  *ms += t;
+  return RT_OK;
+}
+
+rt_status set_device(rt_ctx c) {
+  RT_HIP(c, hipSetDevice(c->device));
+  return RT_OK;
+}
+
+// Ray scratch: per-ray segment lists for one batch of rays.
+rt_status ensure_batch(rt_ctx c) {
+  const int max_segs = c->nx + c->ny + c->nz;
+  // at most ~96 MB of segments per batch, at least 4096 rays
+  int64_t want = std::max<int64_t>(4096, (int64_t)(96ll << 20) / (8ll * max_segs));
+  want = std::min<int64_t>(want, 1 << 18);
+  if (c->d_segs && c->max_segs == max_segs && c->batch_rays == want) return RT_OK;
+  dev_free(c->d_segs);
+  dev_free(c->d_counts);
+  c->max_segs = max_segs;
+  c->batch_rays = want;
+  RT_HIP(c, dev_alloc(&c->d_segs, (size_t)want * max_segs));
+  RT_HIP(c, dev_alloc(&c->d_counts, (size_t)want));
+  return RT_OK;
+}
+
+double ray_weight(rt_ctx c, double n_rays_total) {
+  const double h = c->cell_m;
+  const double area = 2.0 * h * h *
+                      ((double)c->nx * c->ny + (double)c->ny * c->nz + (double)c->nz * c->nx);
+  return M_PI * area * c->dnu / n_rays_total;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream) {
+  if (!out) return fail(nullptr, RT_EINVAL, "rt_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0)
+    return fail(nullptr, RT_EDEVICE, std::string("rt_create: no HIP device: ") + hipGetErrorString(e));
+  if (hip_device < 0 || hip_device >= n)
+    return fail(nullptr, RT_EINVAL, "rt_create: device index out of range");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, hip_device);
+  if (e != hipSuccess) return fail(nullptr, RT_EDEVICE, "rt_create: hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, RT_EUNSUPPORTED,
+                std::string("rt_create: built for gfx950 only, device is ") + prop.gcnArchName);
+  rt_ctx c = new (std::nothrow) rt_ctx_s();
+  if (!c) return fail(nullptr, RT_ENOMEM, "rt_create: out of host memory");
+  c->device = hip_device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  e = hipSetDevice(hip_device);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_slots), 2 * rt::kSlots * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_balance), 4 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_segcount), sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    rt_destroy(c);
+    return fail(nullptr, RT_ENOMEM, std::string("rt_create: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return RT_OK;
+}
+
+rt_status rt_destroy(rt_ctx c) {
+  if (!c) return RT_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  free_lines(c);
+  free_cells(c);
+  dev_free(c->d_T); dev_free(c->d_x); dev_free(c->d_p);
+  dev_free(c->d_bwall);
+  dev_free(c->d_abs); dev_free(c->d_emi); dev_free(c->d_slots); dev_free(c->d_balance);
+  dev_free(c->d_segcount);
+  dev_free(c->d_segs); dev_free(c->d_counts); dev_free(c->d_rays_explicit); dev_free(c->d_exit);
+  free_events(c->trace_events); free_events(c->march_events); free_events(c->kappa_events);
+  delete c;
+  return RT_OK;
+}
+
+const char* rt_last_error(rt_ctx c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const double* T,
+                        const double* x, const double* p, double T_wall) {
+  if (!c) return fail(c, RT_EINVAL, "rt_setup_grid: NULL handle");
+  if (nx < 1 || ny < 1 || nz < 1 || nx > rt::kMaxAxis || ny > rt::kMaxAxis || nz > rt::kMaxAxis)
+    return fail(c, RT_EINVAL, "rt_setup_grid: each of nx, ny, nz must be in [1, 2^20]");
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (n >= (int64_t(1) << 31)) return fail(c, RT_EINVAL, "rt_setup_grid: nx*ny*nz must be < 2^31");
+  if (!(cell_m > 0) || !std::isfinite(cell_m)) return fail(c, RT_EINVAL, "rt_setup_grid: cell_m must be > 0");
+  if (!T || !x || !p) return fail(c, RT_EINVAL, "rt_setup_grid: NULL array");
+  if (!(T_wall >= 0) || !std::isfinite(T_wall)) return fail(c, RT_EINVAL, "rt_setup_grid: T_wall must be >= 0");
+  if (!finite_all(T, n) || !finite_all(x, n) || !finite_all(p, n))
+    return fail(c, RT_EINVAL, "rt_setup_grid: non-finite cell value");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(T[i] > 0)) return fail(c, RT_EINVAL, "rt_setup_grid: T must be > 0");
+    if (!(x[i] >= 0 && x[i] <= 1)) return fail(c, RT_EINVAL, "rt_setup_grid: x_h2o must be in [0, 1]");
+    if (!(p[i] > 0)) return fail(c, RT_EINVAL, "rt_setup_grid: p must be > 0");
+  }
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, hipStreamSynchronize(c->stream));
+  dev_free(c->d_T); dev_free(c->d_x); dev_free(c->d_p);
+  dev_free(c->d_abs); dev_free(c->d_emi);
+  free_cells(c);
+  c->have_grid = false;
+  c->have_kappa = false;
+  c->cells_valid = false;
+  RT_HIP(c, dev_alloc(&c->d_T, n));
+  RT_HIP(c, dev_alloc(&c->d_x, n));
+  RT_HIP(c, dev_alloc(&c->d_p, n));
+  RT_HIP(c, dev_alloc(&c->d_abs, n));
+  RT_HIP(c, dev_alloc(&c->d_emi, n));
+  RT_HIP(c, dev_alloc(&c->cells.G, n));
+  RT_HIP(c, dev_alloc(&c->cells.beta, n));
+  RT_HIP(c, dev_alloc(&c->cells.theta, n));
+  RT_HIP(c, dev_alloc(&c->cells.lam2, n));
+  RT_HIP(c, dev_alloc(&c->cells.P, n));
+  RT_HIP(c, hipMemcpyAsync(c->d_T, T, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  RT_HIP(c, hipMemcpyAsync(c->d_x, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  RT_HIP(c, hipMemcpyAsync(c->d_p, p, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  RT_HIP(c, hipStreamSynchronize(c->stream));  // host arrays may be freed on return
+  c->nx = nx; c->ny = ny; c->nz = nz;
+  c->n_cells = n;
+  c->cell_m = cell_m;
+  c->T_wall = T_wall;
+  c->have_grid = true;
+  c->stats = rt::Stats();
+  RT_HIP(c, rt::launch_zero(c));
+  return RT_OK;
+}
+
+rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* S,
+                         const double* gamma, const double* n_T, const double* E,
+                         double T_ref, double cutoff, double nu0, double dnu, int n_nu) {
+  if (!c) return fail(c, RT_EINVAL, "rt_setup_lines: NULL handle");
+  if (n_lines < 0) return fail(c, RT_EINVAL, "rt_setup_lines: n_lines must be >= 0");
+  if (n_nu < 1) return fail(c, RT_EINVAL, "rt_setup_lines: n_nu must be >= 1");
+  if (!(dnu > 0) || !std::isfinite(dnu) || !std::isfinite(nu0))
+    return fail(c, RT_EINVAL, "rt_setup_lines: dnu must be > 0 and nu0 finite");
+  if (!(T_ref > 0) || !std::isfinite(T_ref)) return fail(c, RT_EINVAL, "rt_setup_lines: T_ref must be > 0");
+  if (!(cutoff >= 0) || !std::isfinite(cutoff)) return fail(c, RT_EINVAL, "rt_setup_lines: cutoff must be >= 0");
+  const double Kd = cutoff / dnu;
+  const double Kr = std::floor(Kd + 0.5);
+  if (std::fabs(Kd - Kr) > 1e-9 * std::max(Kr, 1.0))
+    return fail(c, RT_EINVAL, "rt_setup_lines: cutoff/dnu must be an integer");
+  if ((double)n_nu + 2.0 * Kr + 2.0 >= 16777216.0)
+    return fail(c, RT_EINVAL, "rt_setup_lines: n_nu + 2*cutoff/dnu must stay below 2^24");
+  if (n_lines > 0 && (!nu || !S || !gamma || !n_T))
+    return fail(c, RT_EINVAL, "rt_setup_lines: NULL line array");
+  if (n_lines > 0) {
+    if (!finite_all(nu, n_lines) || !finite_all(S, n_lines) || !finite_all(gamma, n_lines) ||
+        !finite_all(n_T, n_lines) || (E && !finite_all(E, n_lines)))
+      return fail(c, RT_EINVAL, "rt_setup_lines: non-finite line parameter");
+    for (int i = 0; i < n_lines; ++i) {
+      if (!(S[i] >= 0)) return fail(c, RT_EINVAL, "rt_setup_lines: S_ref must be >= 0");
+      if (!(gamma[i] > 0)) return fail(c, RT_EINVAL, "rt_setup_lines: gamma_ref must be > 0");
+      if (E && !(E[i] >= 0)) return fail(c, RT_EINVAL, "rt_setup_lines: E_lower must be >= 0");
+    }
+  }
+  const int K = (int)Kr;
+  const double c2 = rt::second_radiation_cm_K();
+
+  // grid coordinate r = (nu - nu0)/dnu = m + phi; keep the lines whose
+  // window [m - K + [phi > 0], m + K] meets [0, n_nu - 1]; sort by r.
+  struct Rec { double r; int64_t m; double phi; int src; };
+  std::vector<Rec> recs;
+  recs.reserve(n_lines);
+  double evals = 0;
+  for (int i = 0; i < n_lines; ++i) {
+    const double r = (nu[i] - nu0) / dnu;
+    const double fm = std::floor(r);
+    if (!(std::fabs(fm) < 4.0e15)) continue;
+    const int64_t m = (int64_t)fm;
+    const double phi = r - fm;
+    const int64_t lo = m - K + (phi > 0 ? 1 : 0), hi = m + K;
+    if (hi < 0 || lo > n_nu - 1) continue;
+    recs.push_back({r, m, phi, i});
+    evals += (double)(std::min<int64_t>(hi, n_nu - 1) - std::max<int64_t>(lo, 0) + 1);
+  }
+  std::stable_sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) { return a.r < b.r; });
+  const int nl = (int)recs.size();
+  std::vector<int32_t> hm(nl), hwlo(nl), hwhi(nl);
+  std::vector<float> hphi(nl), hS(nl), hg(nl), hn(nl);
+  std::vector<double> hE2(nl), hnu(nl);
+  for (int k = 0; k < nl; ++k) {
+    const Rec& q = recs[k];
+    const int i = q.src;
+    hm[k] = (int32_t)q.m;
+    hphi[k] = (float)q.phi;
+    hwlo[k] = (int32_t)(q.m - K + (q.phi > 0 ? 1 : 0));
+    hwhi[k] = (int32_t)(q.m + K);
+    // with energies, S / (1 - exp(-c2 nu / T_ref)) (the reference-state
+    // stimulated-emission factor of Eq. (1) is a per-line constant)
+    hS[k] = (float)(E ? S[i] / (-std::expm1(-c2 * nu[i] / T_ref)) : S[i]);
+    hE2[k] = E ? c2 * E[i] : 0.0;
+    hnu[k] = nu[i];
+    hg[k] = (float)gamma[i];
+    hn[k] = (float)n_T[i];
+  }
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, hipStreamSynchronize(c->stream));
+  free_lines(c);
+  c->have_lines = false;
+  c->have_kappa = false;
+  c->cells_valid = false;
+  rt::LineSet& L = c->lines;
+  RT_HIP(c, dev_alloc(&L.m, nl));
+  RT_HIP(c, dev_alloc(&L.phi, nl));
+  RT_HIP(c, dev_alloc(&L.wlo, nl));
+  RT_HIP(c, dev_alloc(&L.whi, nl));
+  RT_HIP(c, dev_alloc(&L.S, nl));
+  RT_HIP(c, dev_alloc(&L.E2, nl));
+  RT_HIP(c, dev_alloc(&L.nu, nl));
+  RT_HIP(c, dev_alloc(&L.gamma, nl));
+  RT_HIP(c, dev_alloc(&L.nexp, nl));
+  if (nl > 0) {
+    RT_HIP(c, hipMemcpy(L.m, hm.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.phi, hphi.data(), nl * sizeof(float), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.wlo, hwlo.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.whi, hwhi.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.S, hS.data(), nl * sizeof(float), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.E2, hE2.data(), nl * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.nu, hnu.data(), nl * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.gamma, hg.data(), nl * sizeof(float), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.nexp, hn.data(), nl * sizeof(float), hipMemcpyHostToDevice));
+  }
+  L.n = nl;
+  c->have_E = E != nullptr;
+  c->n_nu = n_nu;
+  c->K = K;
+  c->nu0 = nu0;
+  c->dnu = dnu;
+  c->T_ref = T_ref;
+  c->line_evals_per_cell = evals;
+  c->have_lines = true;
+  return RT_OK;
+}
+
+int64_t rt_required_pitch(rt_ctx c) {
+  if (!c || !c->have_lines) return -1;
+  return ((int64_t)c->n_nu + rt::kChunk - 1) / rt::kChunk * rt::kChunk;
+}
+
+rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_dev, int64_t ld) {
+  if (!c) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL handle");
+  if (!c->have_grid || !c->have_lines)
+    return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_setup_grid and rt_setup_lines first");
+  if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED)
+    return fail(c, RT_EINVAL, "rt_compute_kappa: unknown mode");
+  if (!kappa_dev || !planck_dev) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL buffer");
+  if (ld < rt_required_pitch(c) || ld % rt::kChunk != 0)
+    return fail(c, RT_EINVAL, "rt_compute_kappa: ld must be a multiple of 256 and >= rt_required_pitch");
+  if ((reinterpret_cast<uintptr_t>(kappa_dev) | reinterpret_cast<uintptr_t>(planck_dev)) & 15)
+    return fail(c, RT_EINVAL, "rt_compute_kappa: buffers must be 16-byte aligned");
+  if (rt_status s = set_device(c)) return s;
+  c->have_kappa = false;
+  if (c->bwall_len < ld) {
+    dev_free(c->d_bwall);
+    RT_HIP(c, dev_alloc(&c->d_bwall, (size_t)ld));
+    c->bwall_len = ld;
+  }
+  c->kappa = kappa_dev;
+  c->planck = planck_dev;
+  c->ld = ld;
+  if (rt_status s = record_begin(c, c->kappa_events)) return s;
+  if (!c->cells_valid) {
+    RT_HIP(c, rt::launch_cell_params(c));
+    c->cells_valid = true;
+  }
+  RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
+  if (rt_status s = record_end(c, c->kappa_events)) return s;
+  RT_HIP(c, rt::launch_planck(c));
+  c->stats.line_evals += c->line_evals_per_cell * (double)c->n_cells;
+  c->have_kappa = true;
+  return RT_OK;
+}
+
+static rt_status trace_batches(rt_ctx c, uint64_t seed, uint64_t begin, uint64_t count,
+                               double weight, bool f64, bool explicit_rays, float* exit_dev) {
+  if (rt_status s = ensure_batch(c)) return s;
+  if (rt_status s = record_begin(c, c->trace_events)) return s;
+  for (uint64_t off = 0; off < count; off += (uint64_t)c->batch_rays) {
+    const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)c->batch_rays, count - off);
+    if (explicit_rays && off > 0) return fail(c, RT_EINVAL, "explicit rays exceed one batch");
+    RT_HIP(c, rt::launch_raygen(c, seed, begin + off, n, explicit_rays, nullptr, true));
+    if (rt_status s = record_begin(c, c->march_events)) return s;
+    RT_HIP(c, rt::launch_march(c, n, weight, f64, exit_dev));
+    if (rt_status s = record_end(c, c->march_events)) return s;
+    c->stats.march_launches += 1;
+  }
+  if (rt_status s = record_end(c, c->trace_events)) return s;
+  c->stats.rays += (double)count;
+  return RT_OK;
+}
+
+rt_status rt_trace_rays(rt_ctx c, uint64_t seed, uint64_t n_rays_total, uint64_t ray_begin,
+                        uint64_t ray_count, int tally_prec) {
+  if (!c) return fail(c, RT_EINVAL, "rt_trace_rays: NULL handle");
+  if (!c->have_kappa) return fail(c, RT_ESTATE, "rt_trace_rays: call rt_compute_kappa first");
+  if (n_rays_total == 0) return fail(c, RT_EINVAL, "rt_trace_rays: n_rays_total must be >= 1");
+  if (ray_begin > n_rays_total || ray_count > n_rays_total - ray_begin)
+    return fail(c, RT_EINVAL, "rt_trace_rays: ray range outside [0, n_rays_total)");
+  if (tally_prec != RT_TALLY_F32 && tally_prec != RT_TALLY_F64)
+    return fail(c, RT_EINVAL, "rt_trace_rays: unknown tally precision");
+  if (ray_count == 0) return RT_OK;
+  if (rt_status s = set_device(c)) return s;
+  return trace_batches(c, seed, ray_begin, ray_count, ray_weight(c, (double)n_rays_total),
+                       tally_prec == RT_TALLY_F64, false, nullptr);
+}
+
+rt_status rt_trace_explicit(rt_ctx c, int n_rays, const int64_t* O, const int64_t* D,
+                            double weight, int tally_prec, double* exit_I) {
+  if (!c) return fail(c, RT_EINVAL, "rt_trace_explicit: NULL handle");
+  if (!c->have_kappa) return fail(c, RT_ESTATE, "rt_trace_explicit: call rt_compute_kappa first");
+  if (n_rays < 1 || !O || !D) return fail(c, RT_EINVAL, "rt_trace_explicit: bad ray arrays");
+  if (!std::isfinite(weight)) return fail(c, RT_EINVAL, "rt_trace_explicit: weight not finite");
+  if (tally_prec != RT_TALLY_F32 && tally_prec != RT_TALLY_F64)
+    return fail(c, RT_EINVAL, "rt_trace_explicit: unknown tally precision");
+  if (rt_status s = ensure_batch(c)) return s;
+  if (n_rays > c->batch_rays) return fail(c, RT_EINVAL, "rt_trace_explicit: too many rays");
+  const int64_t lim[3] = {c->nx * rt::kCellUnits, c->ny * rt::kCellUnits, c->nz * rt::kCellUnits};
+  std::vector<int64_t> buf((size_t)n_rays * 6);
+  for (int r = 0; r < n_rays; ++r) {
+    bool on_face = false, inward = false, any = false;
+    for (int k = 0; k < 3; ++k) {
+      const int64_t o = O[3 * r + k], d = D[3 * r + k];
+      if (o < 0 || o > lim[k]) return fail(c, RT_EINVAL, "rt_trace_explicit: origin outside the box");
+      if (d < -rt::kCellUnits || d > rt::kCellUnits)
+        return fail(c, RT_EINVAL, "rt_trace_explicit: |D| components must be <= 2^21");
+      if (d != 0) any = true;
+      if (o == 0 || o == lim[k]) {
+        on_face = true;
+        if ((o == 0 && d > 0) || (o == lim[k] && d < 0)) inward = true;
+      }
+      buf[6 * r + k] = o;
+      buf[6 * r + 3 + k] = d;
+    }
+    if (!any || !on_face || !inward)
+      return fail(c, RT_EINVAL, "rt_trace_explicit: rays must start on a face and point inward");
+    for (int k = 0; k < 3; ++k) {
+      const int64_t o = O[3 * r + k], d = D[3 * r + k];
+      if ((o == 0 && d < 0) || (o == lim[k] && d > 0))
+        return fail(c, RT_EINVAL, "rt_trace_explicit: ray leaves through its own face");
+    }
+  }
+  if (rt_status s = set_device(c)) return s;
+  if (c->explicit_cap < n_rays) {
+    dev_free(c->d_rays_explicit);
+    RT_HIP(c, dev_alloc(&c->d_rays_explicit, (size_t)n_rays * 6));
+    c->explicit_cap = n_rays;
+  }
+  RT_HIP(c, hipMemcpyAsync(c->d_rays_explicit, buf.data(), buf.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, c->stream));
+  float* exit_dev = nullptr;
+  if (exit_I) {
+    const int64_t need = (int64_t)n_rays * c->ld;
+    if (c->exit_cap < need) {
+      dev_free(c->d_exit);
+      RT_HIP(c, dev_alloc(&c->d_exit, (size_t)need));
+      c->exit_cap = need;
+    }
+    exit_dev = c->d_exit;
+  }
+  if (rt_status s = trace_batches(c, 0, 0, (uint64_t)n_rays, weight, tally_prec == RT_TALLY_F64,
+                                  true, exit_dev))
+    return s;
+  RT_HIP(c, hipStreamSynchronize(c->stream));  // the host ray buffer goes out of scope
+  if (exit_I) {
+    std::vector<float> tmp((size_t)n_rays * c->ld);
+    RT_HIP(c, hipMemcpy(tmp.data(), exit_dev, tmp.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int r = 0; r < n_rays; ++r)
+      for (int j = 0; j < c->n_nu; ++j) exit_I[(size_t)r * c->n_nu + j] = tmp[(size_t)r * c->ld + j];
+  }
+  return RT_OK;
+}
+
+rt_status rt_tally(rt_ctx c, double* absorbed, double* emitted, double* balance) {
+  if (!c) return fail(c, RT_EINVAL, "rt_tally: NULL handle");
+  if (!c->have_grid) return fail(c, RT_ESTATE, "rt_tally: call rt_setup_grid first");
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, rt::launch_tally(c));
+  if (absorbed)
+    RT_HIP(c, hipMemcpyAsync(absorbed, c->d_abs, c->n_cells * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (emitted)
+    RT_HIP(c, hipMemcpyAsync(emitted, c->d_emi, c->n_cells * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  double bal[4];
+  RT_HIP(c, hipMemcpyAsync(bal, c->d_balance, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  RT_HIP(c, hipStreamSynchronize(c->stream));
+  if (balance) std::memcpy(balance, bal, sizeof(bal));
+  return RT_OK;
+}
+
+rt_status rt_reset_tally(rt_ctx c) {
+  if (!c) return fail(c, RT_EINVAL, "rt_reset_tally: NULL handle");
+  if (!c->have_grid) return fail(c, RT_ESTATE, "rt_reset_tally: call rt_setup_grid first");
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, rt::launch_zero(c));
+  double tmp = 0;
+  if (rt_status s = drain_events(c, c->trace_events, &tmp)) return s;
+  if (rt_status s = drain_events(c, c->march_events, &tmp)) return s;
+  if (rt_status s = drain_events(c, c->kappa_events, &tmp)) return s;
+  c->stats.kappa_ms = 0;
+  c->stats.line_evals = 0;
+  c->stats.trace_ms = 0;
+  c->stats.march_ms = 0;
+  c->stats.rays = 0;
+  c->stats.march_launches = 0;
+  return RT_OK;
+}
+
+rt_status rt_debug_segments(rt_ctx c, uint64_t seed, uint64_t ray_begin, uint64_t count,
+                            int max_segs, int32_t* counts, int32_t* cells, float* len_cm,
+                            int64_t* O, int64_t* D) {
+  if (!c) return fail(c, RT_EINVAL, "rt_debug_segments: NULL handle");
+  if (!c->have_grid) return fail(c, RT_ESTATE, "rt_debug_segments: call rt_setup_grid first");
+  if (!counts || !cells || !len_cm) return fail(c, RT_EINVAL, "rt_debug_segments: NULL output");
+  if (max_segs < c->nx + c->ny + c->nz) return fail(c, RT_EINVAL, "rt_debug_segments: max_segs < nx+ny+nz");
+  if (rt_status s = set_device(c)) return s;
+  if (rt_status s = ensure_batch(c)) return s;
+  if (c->explicit_cap < c->batch_rays) {
+    dev_free(c->d_rays_explicit);
+    RT_HIP(c, dev_alloc(&c->d_rays_explicit, (size_t)c->batch_rays * 6));
+    c->explicit_cap = c->batch_rays;
+  }
+  std::vector<int2> seg;
+  std::vector<int32_t> cnt;
+  std::vector<int64_t> rays;
+  for (uint64_t off = 0; off < count; off += (uint64_t)c->batch_rays) {
+    const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)c->batch_rays, count - off);
+    RT_HIP(c, rt::launch_raygen(c, seed, ray_begin + off, n, false, c->d_rays_explicit, false));
+    seg.resize((size_t)n * c->max_segs);
+    cnt.resize((size_t)n);
+    rays.resize((size_t)n * 6);
+    RT_HIP(c, hipMemcpyAsync(seg.data(), c->d_segs, seg.size() * sizeof(int2), hipMemcpyDeviceToHost, c->stream));
+    RT_HIP(c, hipMemcpyAsync(cnt.data(), c->d_counts, cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    RT_HIP(c, hipMemcpyAsync(rays.data(), c->d_rays_explicit, rays.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    RT_HIP(c, hipStreamSynchronize(c->stream));
+    for (int64_t r = 0; r < n; ++r) {
+      const int64_t g = (int64_t)off + r;
+      counts[g] = cnt[r];
+      for (int k = 0; k < cnt[r]; ++k) {
+        cells[g * max_segs + k] = seg[r * c->max_segs + k].x;
+        int bits = seg[r * c->max_segs + k].y;
+        std::memcpy(&len_cm[g * max_segs + k], &bits, sizeof(float));
+      }
+      for (int k = 0; k < 3; ++k) {
+        if (O) O[3 * g + k] = rays[6 * r + k];
+        if (D) D[3 * g + k] = rays[6 * r + 3 + k];
+      }
+    }
+  }
+  return RT_OK;
+}
+
+rt_status rt_get_stats(rt_ctx c, rt_stats* out) {
+  if (!c || !out) return fail(c, RT_EINVAL, "rt_get_stats: NULL argument");
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, hipStreamSynchronize(c->stream));
+  if (rt_status s = drain_events(c, c->kappa_events, &c->stats.kappa_ms)) return s;
+  if (rt_status s = drain_events(c, c->trace_events, &c->stats.trace_ms)) return s;
+  if (rt_status s = drain_events(c, c->march_events, &c->stats.march_ms)) return s;
+  unsigned long long segs = 0;
+  if (c->d_segcount)
+    RT_HIP(c, hipMemcpy(&segs, c->d_segcount, sizeof(segs), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->line_evals = c->stats.line_evals;
+  out->kappa_ms = c->stats.kappa_ms;
+  out->segments = (double)segs;
+  out->updates = (double)segs * (double)c->n_nu;
+  out->trace_ms = c->stats.trace_ms;
+  out->march_ms = c->stats.march_ms;
+  out->rays = c->stats.rays;
+  out->march_launches = c->stats.march_launches;
+  return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// rt_internal.h -- state and device helpers shared by the translation units
+// of librtlbl (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rtlbl.h"
+
+namespace rt {
+
+// Fixed-point traversal frame: one cell edge is 2^21 integer units.
+constexpr int64_t kCellUnits = int64_t(1) << 21;
+constexpr int kChunk = 256;       // march: nu points per wavefront (64 lanes x 4)
+constexpr int kMaxAxis = 1 << 20; // largest admissible cells per axis
+
+// Physical constants (SI 2019 exact values).
+constexpr double kPlanckH = 6.62607015e-34;
+constexpr double kLightC = 299792458.0;
+constexpr double kBoltzmann = 1.380649e-23;
+constexpr double kAtm = 101325.0;
+inline double second_radiation_cm_K() { return kPlanckH * kLightC / kBoltzmann * 100.0; }
+inline double first_radiation_wavenumber() { return 2.0 * kPlanckH * kLightC * kLightC * 1e8; }
+
+// Per-line data after sorting by centre (device, structure of arrays).
+struct LineSet {
+  int n = 0;              // lines kept (window meets the grid)
+  int32_t* m = nullptr;   // floor((nu - nu0)/dnu)
+  float* phi = nullptr;   // (nu - nu0)/dnu - m, rounded to float
+  int32_t* wlo = nullptr; // first grid point of the window: m - K + [phi > 0]
+  int32_t* whi = nullptr; // last grid point of the window:  m + K
+  float* S = nullptr;     // S_ref, divided by (1 - exp(-c2 nu/T_ref)) with energies
+  double* E2 = nullptr;   // c2 * E_lower  (0 without energies)
+  double* nu = nullptr;   // centre, cm^-1
+  float* gamma = nullptr; // half width at T_ref, 1 atm
+  float* nexp = nullptr;  // half-width temperature exponent
+};
+
+// Per-cell derived parameters (device), from FP64 on the device.
+struct CellSet {
+  float* G = nullptr;       // u q / (pi dnu): density x partition ratio, grid scale
+  double* beta = nullptr;   // 1/T_ref - 1/T
+  double* theta = nullptr;  // c2 / T
+  float* lam2 = nullptr;    // log2(T_ref / T)
+  float* P = nullptr;       // p / dnu
+};
+
+struct Stats {
+  double line_evals = 0;
+  double kappa_ms = 0;
+  double trace_ms = 0;
+  double march_ms = 0;
+  double rays = 0;
+  double march_launches = 0;
+};
+
+}  // namespace rt
+
+struct rt_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // grid
+  bool have_grid = false;
+  int nx = 0, ny = 0, nz = 0;
+  int64_t n_cells = 0;
+  double cell_m = 0, T_wall = 0;
+  double* d_T = nullptr;
+  double* d_x = nullptr;
+  double* d_p = nullptr;
+
+  // lines + spectral grid
+  bool have_lines = false;
+  bool have_E = false;
+  int n_nu = 0;
+  int K = 0;
+  double nu0 = 0, dnu = 0, T_ref = 0;
+  rt::LineSet lines;
+  double line_evals_per_cell = 0;
+
+  // derived per-cell parameters and tables
+  rt::CellSet cells;
+  bool cells_valid = false;
+  bool have_kappa = false;
+  float* kappa = nullptr;   // caller owned
+  float* planck = nullptr;  // caller owned
+  int64_t ld = 0;
+  float* d_bwall = nullptr; // B(nu_j, T_wall), ld floats (owned)
+  int64_t bwall_len = 0;
+
+  // tallies (owned)
+  double* d_abs = nullptr;
+  double* d_emi = nullptr;
+  double* d_slots = nullptr;  // [2][kSlots]: entering, escaped partials
+  double* d_balance = nullptr;
+  unsigned long long* d_segcount = nullptr;
+
+  // ray batch scratch (owned)
+  int64_t batch_rays = 0;
+  int max_segs = 0;
+  int2* d_segs = nullptr;
+  int32_t* d_counts = nullptr;
+  int64_t* d_rays_explicit = nullptr;  // [n][6]: O(3), D(3)
+  int64_t explicit_cap = 0;
+  float* d_exit = nullptr;
+  int64_t exit_cap = 0;
+
+  rt::Stats stats;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> trace_events, march_events, kappa_events;
+};
+
+namespace rt {
+constexpr int kSlots = 1024;
+
+// kernel launchers (defined in the .hip files)
+hipError_t launch_cell_params(rt_ctx c);
+hipError_t launch_kappa(rt_ctx c, bool compensated);
+hipError_t launch_planck(rt_ctx c);
+hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,
+                         int64_t* rays_out, bool count_work);
+hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool f64, float* exit_dev);
+hipError_t launch_tally(rt_ctx c);
+hipError_t launch_zero(rt_ctx c);
+}  // namespace rt

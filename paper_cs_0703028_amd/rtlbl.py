@@ -1,0 +1,219 @@
+"""Python binding of the C ABI in include/rtlbl.h (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``librtlbl.so``; this module only
+converts numpy arrays and torch tensors to pointers and status codes to
+exceptions.  PyTorch supplies device memory and streams.  torch is imported
+before the library is loaded so that the library binds the same HIP runtime
+as torch.
+
+If ``librtlbl.so`` has not been built, importing this module raises
+ImportError: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (HIP runtime first)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtlbl.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+KAPPA_PLAIN, KAPPA_COMPENSATED = 0, 1
+TALLY_F32, TALLY_F64 = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_cs_0703028_amd.build`")
+
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+
+
+class RtStats(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "line_evals", "kappa_ms", "updates", "segments", "trace_ms", "march_ms", "rays",
+        "march_launches")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def _load():
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.rt_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.rt_destroy.argtypes = [vp]
+    L.rt_last_error.argtypes = [vp]
+    L.rt_last_error.restype = C.c_char_p
+    L.rt_setup_grid.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, _f64p, _f64p, _f64p,
+                                C.c_double]
+    L.rt_setup_lines.argtypes = [vp, C.c_int, _f64p, _f64p, _f64p, _f64p, vp, C.c_double,
+                                 C.c_double, C.c_double, C.c_double, C.c_int]
+    L.rt_required_pitch.argtypes = [vp]
+    L.rt_required_pitch.restype = C.c_int64
+    L.rt_compute_kappa.argtypes = [vp, C.c_int, vp, vp, C.c_int64]
+    L.rt_trace_rays.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int]
+    L.rt_trace_explicit.argtypes = [vp, C.c_int, _i64p, _i64p, C.c_double, C.c_int, vp]
+    L.rt_tally.argtypes = [vp, vp, vp, vp]
+    L.rt_reset_tally.argtypes = [vp]
+    L.rt_debug_segments.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, _i32p,
+                                    _i32p, _f32p, vp, vp]
+    L.rt_get_stats.argtypes = [vp, C.POINTER(RtStats)]
+    for f in ("rt_create", "rt_destroy", "rt_setup_grid", "rt_setup_lines", "rt_compute_kappa",
+              "rt_trace_rays", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
+              "rt_debug_segments", "rt_get_stats"):
+        getattr(L, f).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, np.float64)
+
+
+class Tracer:
+    """One rt_ctx handle bound to a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream: "torch.cuda.Stream | None" = None):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        s = lib.rt_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if s != RT_OK:
+            raise RtError(s, lib.rt_last_error(None).decode())
+        self._h = h
+        self.grid = None
+        self.lines = None
+        self._tables = None
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, s):
+        if s != RT_OK:
+            raise RtError(s, lib.rt_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.rt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------- the ABI
+    def setup_grid(self, grid):
+        n = grid.nx * grid.ny * grid.nz
+        T, x, p = _f64(grid.T), _f64(grid.x), _f64(grid.p)
+        if T.size != n or x.size != n or p.size != n:
+            raise ValueError("grid arrays must have nx*ny*nz entries")
+        self._check(lib.rt_setup_grid(self._h, grid.nx, grid.ny, grid.nz, grid.cell_m, T, x, p,
+                                      grid.T_wall))
+        self.grid = grid
+
+    def setup_lines(self, lines):
+        n = len(lines.nu)
+        E = None if lines.E_lower is None else _f64(lines.E_lower)
+        self._check(lib.rt_setup_lines(self._h, n, _f64(lines.nu), _f64(lines.S),
+                                       _f64(lines.gamma), _f64(lines.n_T), _ptr(E), lines.T_ref,
+                                       lines.cutoff, lines.nu0, lines.dnu, lines.n_nu))
+        self.lines = lines
+
+    def required_pitch(self) -> int:
+        ld = lib.rt_required_pitch(self._h)
+        if ld < 0:
+            raise RtError(RT_ESTATE, "setup_lines first")
+        return int(ld)
+
+    def alloc_tables(self):
+        """(kappa, planck) float32 device tensors [n_cells][ld] (caller owned)."""
+        ld = self.required_pitch()
+        n = self.grid.nx * self.grid.ny * self.grid.nz
+        dev = torch.device("cuda", self.device)
+        return (torch.empty((n, ld), dtype=torch.float32, device=dev),
+                torch.empty((n, ld), dtype=torch.float32, device=dev))
+
+    def compute_kappa(self, mode=KAPPA_PLAIN, kappa=None, planck=None):
+        if kappa is None or planck is None:
+            kappa, planck = self.alloc_tables()
+        for t in (kappa, planck):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
+                raise ValueError("tables must be contiguous 2-D float32 device tensors")
+        self._check(lib.rt_compute_kappa(self._h, mode, C.c_void_p(kappa.data_ptr()),
+                                         C.c_void_p(planck.data_ptr()), kappa.shape[1]))
+        self._tables = (kappa, planck)  # keep the caller's buffers alive
+        return kappa, planck
+
+    def trace_rays(self, seed, n_rays_total, begin=0, count=None, prec=TALLY_F32):
+        if count is None:
+            count = n_rays_total - begin
+        self._check(lib.rt_trace_rays(self._h, seed, n_rays_total, begin, count, prec))
+
+    def trace_explicit(self, O, D, weight, prec=TALLY_F32, want_exit=False):
+        O = np.ascontiguousarray(O, np.int64).reshape(-1, 3)
+        D = np.ascontiguousarray(D, np.int64).reshape(-1, 3)
+        n = O.shape[0]
+        out = np.zeros((n, self.lines.n_nu), np.float64) if want_exit else None
+        self._check(lib.rt_trace_explicit(self._h, n, O.ravel(), D.ravel(), weight, prec,
+                                          _ptr(out)))
+        return out
+
+    def tally(self):
+        n = self.grid.nx * self.grid.ny * self.grid.nz
+        a = np.zeros(n, np.float64)
+        e = np.zeros(n, np.float64)
+        b = np.zeros(4, np.float64)
+        self._check(lib.rt_tally(self._h, _ptr(a), _ptr(e), _ptr(b)))
+        return a, e, b
+
+    def reset_tally(self):
+        self._check(lib.rt_reset_tally(self._h))
+
+    def debug_segments(self, seed, begin, count):
+        g = self.grid
+        ms = g.nx + g.ny + g.nz
+        counts = np.zeros(count, np.int32)
+        cells = np.full((count, ms), -1, np.int32)
+        lens = np.zeros((count, ms), np.float32)
+        O = np.zeros((count, 3), np.int64)
+        D = np.zeros((count, 3), np.int64)
+        self._check(lib.rt_debug_segments(self._h, seed, begin, count, ms, counts, cells.ravel(),
+                                          lens.ravel(), _ptr(O), _ptr(D)))
+        return counts, cells, lens, O, D
+
+    def stats(self):
+        s = RtStats()
+        self._check(lib.rt_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    # ------------------------------------------------------------- helpers
+    def raw_status(self, name, *args):
+        """Call an rt_* entry point and return its status (error-path tests)."""
+        return getattr(lib, name)(self._h, *args)
+
+    def last_error(self) -> str:
+        return lib.rt_last_error(self._h).decode()
+

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (stated per result):
+* traversal (integer work): cells, segment counts, origins and directions
+  bit-exact; lengths equal to the oracle's FP64 length rounded to FP32;
+* kappa and Planck tables: 1e-5 relative per element, exact zeros where the
+  oracle has zeros (window membership is integer work);
+* per-cell absorbed and emitted power and the energy balance: 1e-5 relative
+  (the floating-point tolerance of the method's FP32 path); cells the oracle
+  leaves at exactly zero must be exactly zero.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_cs_0703028_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+U = 1 << 21
+
+
+@pytest.fixture(scope="module")
+def rt():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_cs_0703028_amd import rtlbl
+    return rtlbl
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+def _tracer(rt, w):
+    t = rt.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(w.lines)
+    return t
+
+
+def _rel(g, o):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    nz = o != 0
+    assert (g[~nz] == 0).all(), "GPU nonzero where the oracle is exactly zero"
+    return np.abs(g[nz] - o[nz]) / np.abs(o[nz])
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# ----------------------------------------------------------------- traversal
+@pytest.mark.parametrize("wl", ["small_ragged", "plain_8cube", "plain_32cube"])
+def test_segments_bit_exact(rt, O, wl):
+    w = getattr(I, wl)()
+    t = _tracer(rt, w)
+    g = w.grid
+    rng = np.random.default_rng(5)
+    begins = [0, int(rng.integers(0, max(w.n_rays - 600, 1)))]
+    for b in begins:
+        _say(f"segments {wl} rays [{b}, {b + 600})")
+        counts, cells, lens, Og, Dg = t.debug_segments(w.seed, b, 600)
+        Oo, Do, _ = O.rays(w.seed, b, 600, g.nx, g.ny, g.nz)
+        assert (Og == Oo).all() and (Dg == Do).all()
+        for r in range(600):
+            c_o, l_o = O.segments(g.nx, g.ny, g.nz, g.cell_m * 100.0, Oo[r], Do[r])
+            assert counts[r] == len(c_o)
+            assert (cells[r, :counts[r]] == c_o).all()
+            np.testing.assert_array_equal(lens[r, :counts[r]], l_o.astype(np.float32))
+    t.close()
+
+
+# ------------------------------------------------------------- kappa, Planck
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("wl", ["small_ragged", "plain_8cube"])
+def test_kappa_and_planck_tables(rt, O, wl, mode):
+    w = getattr(I, wl)()
+    t = _tracer(rt, w)
+    _say(f"kappa {wl} mode {mode}")
+    kap, B = t.compute_kappa(mode)
+    ld = t.required_pitch()
+    assert ld % 256 == 0 and ld >= w.lines.n_nu
+    kg = kap.cpu().numpy()
+    bg = B.cpu().numpy()
+    ko = O.kappa(w.grid, w.lines)
+    bo = O.planck_rows(w.grid, w.lines)
+    assert (kg[:, w.lines.n_nu:] == 0).all() and (bg[:, w.lines.n_nu:] == 0).all()
+    rk = _rel(kg[:, :w.lines.n_nu], ko)
+    rb = _rel(bg[:, :w.lines.n_nu], bo)
+    _say(f"  kappa rel err max {rk.max():.3e} median {np.median(rk):.3e}; planck {rb.max():.3e}")
+    assert rk.max() <= REL
+    assert rb.max() <= 2e-7
+    st = t.stats()
+    assert st["line_evals"] > 0
+    t.close()
+
+
+# --------------------------------------------------------------------- march
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("wl,T_wall", [("plain_8cube", 0.0), ("small_ragged", 1250.0)])
+def test_tallies_match_oracle(rt, O, wl, T_wall, prec):
+    w = getattr(I, wl)()
+    w.grid.T_wall = T_wall
+    t = _tracer(rt, w)
+    mode = 1 if prec == 1 else 0
+    _say(f"tallies {wl} T_wall {T_wall} prec {prec}")
+    t.compute_kappa(mode)
+    t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, prec)
+    ag, eg, bg = t.tally()
+    res = O.run(w.grid, w.lines, w.n_rays, seed=w.seed)
+    ra = _rel(ag, res["absorbed"])
+    re = _rel(eg, res["emitted"])
+    rbal = np.abs(bg - res["balance"]) / np.maximum(np.abs(res["balance"]), 1e-300)
+    _say(f"  absorbed max {ra.max():.3e} median {np.median(ra):.3e}; emitted max {re.max():.3e};"
+         f" balance {rbal}")
+    assert ra.max() <= REL and re.max() <= REL
+    for k in range(4):
+        if res["balance"][k] == 0:
+            assert bg[k] == 0
+        else:
+            assert rbal[k] <= REL
+    ent, emi, ab, esc = bg
+    assert abs(ent + emi - ab - esc) <= 1e-5 * (ent + emi)
+    st = t.stats()
+    assert st["rays"] == w.n_rays and st["updates"] == st["segments"] * w.lines.n_nu
+    t.close()
+
+
+def test_ray_ranges_add_up(rt, O):
+    """Tracing [0, n) in pieces gives the tallies of one call (same rays)."""
+    w = I.small_ragged()
+    t = _tracer(rt, w)
+    t.compute_kappa(0)
+    t.trace_rays(w.seed, w.n_rays, 0, w.n_rays)
+    a1, e1, b1 = t.tally()
+    t.reset_tally()
+    for b, c in ((300, 400), (0, 100), (100, 200)):
+        t.trace_rays(w.seed, w.n_rays, b, c)
+    a2, e2, b2 = t.tally()
+    np.testing.assert_allclose(a2, a1, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(e2, e1, rtol=1e-12, atol=0)
+    t.close()
+
+
+def test_slab_axis_normal_closed_form(rt, O):
+    """1-cell slab, L = 1 m, walls at 1500 K: I_exit = I_w e^{-kL} + B (1 - e^{-kL})."""
+    w = I.slab_1cell()
+    t = _tracer(rt, w)
+    t.compute_kappa(1)
+    Os = np.array([[0, U // 2 + 1, U // 2 + 1], [U, 3, U - 5], [7, 0, U // 3 * 2 + 1]], np.int64)
+    Ds = np.array([[1 << 20, 0, 0], [-(1 << 20), 0, 0], [0, 1 << 20, 0]], np.int64)
+    _say("slab explicit rays")
+    ex = t.trace_explicit(Os, Ds, 1.0, prec=1, want_exit=True)
+    kap = O.kappa(w.grid, w.lines)[0]
+    B = O.planck_rows(w.grid, w.lines)[0]
+    nu = w.lines.nu0 + np.arange(w.lines.n_nu) * w.lines.dnu
+    Bw = np.array([O.planck(v, 1500.0) for v in nu])
+    tr = np.exp(-kap * 100.0)
+    expect = Bw * tr + B * (1.0 - tr)
+    for r in range(3):
+        err = np.abs(ex[r] - expect) / expect
+        assert err.max() <= REL
+    t.close()
+
+
+def test_abi_errors(rt):
+    w = I.small_ragged()
+    t = rt.Tracer(0)
+    # call order
+    with pytest.raises(rt.RtError) as e:
+        t.trace_rays(0, 10)
+    assert e.value.status == rt.RT_ESTATE
+    t.setup_grid(w.grid)
+    # kappa before the line list
+    assert t.raw_status("rt_compute_kappa", 0, None, None, 256) == rt.RT_ESTATE
+    # invalid values
+    bad = I.small_ragged().grid
+    bad.T = bad.T.copy()
+    bad.T[3] = -1.0
+    with pytest.raises(rt.RtError) as e:
+        t.setup_grid(bad)
+    assert e.value.status == rt.RT_EINVAL and "T" in t.last_error()
+    L = I.small_ragged().lines
+    L.cutoff = 5.005
+    with pytest.raises(rt.RtError) as e:
+        t.setup_lines(L)
+    assert e.value.status == rt.RT_EINVAL and "integer" in t.last_error()
+    t.setup_lines(w.lines)
+    kap, B = t.alloc_tables()
+    assert t.raw_status("rt_compute_kappa", 0, kap.data_ptr(), B.data_ptr(), 100) == rt.RT_EINVAL
+    assert t.raw_status("rt_compute_kappa", 7, kap.data_ptr(), B.data_ptr(), kap.shape[1]) == rt.RT_EINVAL
+    t.compute_kappa(0, kap, B)
+    assert t.raw_status("rt_trace_rays", 0, 10, 5, 6, 0) == rt.RT_EINVAL
+    assert t.raw_status("rt_trace_rays", 0, 0, 0, 0, 0) == rt.RT_EINVAL
+    assert t.raw_status("rt_trace_rays", 0, 10, 0, 5, 3) == rt.RT_EINVAL
+    # a ray that does not start on the boundary
+    with pytest.raises(rt.RtError):
+        t.trace_explicit(np.array([[5, 5, 5]]), np.array([[1, 0, 0]]), 1.0)
+    t.close()
+
+
+# ------------------------------------------------------------- full size
+@pytest.mark.slow
+def test_full_size_32cube_sampled(rt, O):
+    """The 32^3 / 20,000-line / 50,000-point workload at full size on the GPU:
+    kappa of sampled cells and the tallies of a sampled ray range against the
+    oracle (which computes only the cells those rays visit)."""
+    w = I.plain_32cube()
+    t = _tracer(rt, w)
+    _say("full-size 32^3 compute_kappa (plain)")
+    kap, B = t.compute_kappa(0)
+    rng = np.random.default_rng(11)
+    cells = np.sort(rng.choice(w.grid.n_cells, 12, replace=False)).astype(np.int32)
+    kg = kap[cells.tolist()].cpu().numpy()[:, :w.lines.n_nu]
+    ko = O.kappa(w.grid, w.lines, cells)
+    rk = _rel(kg, ko)
+    _say(f"  kappa sampled max rel {rk.max():.3e}")
+    assert rk.max() <= REL
+    begin, count = 777_000, 6
+    _say(f"full-size 32^3 trace rays [{begin}, {begin + count}) of 2^20")
+    t.trace_rays(w.seed, w.n_rays, begin, count, 0)
+    ag, eg, bg = t.tally()
+    res = O.run(w.grid, w.lines, w.n_rays, seed=w.seed, begin=begin, count=count,
+                cells_needed_only=True)
+    ra = _rel(ag, res["absorbed"])
+    re = _rel(eg, res["emitted"])
+    _say(f"  absorbed max rel {ra.max():.3e}, emitted {re.max():.3e}")
+    assert ra.max() <= REL and re.max() <= REL
+    t.close()
