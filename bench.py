@@ -24,16 +24,18 @@ sys.path.insert(0, ROOT)
 METRIC = ("ray·cell·nu updates/s + line evals/s; "
           "surrogate vs plain at ≤1e-3 rel power")
 
-# Algorithmic work per ray-cell-nu update of Eq. (3): x = kappa * (-l log2 e),
-# t = 2^x, a = 1 - t, d = I - B, I -= d a, absorbed += I a, emitted += B a:
-# 9 FP32 flops (an FMA counts 2) and one transcendental; 6 full-rate VALU
-# issue slots plus the exponential.
+# Algorithmic work per ray-cell-nu update of Eq. (3) with the Planck value
+# read once per (cell, nu) from a table: x = kappa * (-l log2 e), t = 2^x,
+# a = 1 - t, d = I - B, I -= d a, absorbed += I a, emitted += B a:
+# 9 FP32 flops (an FMA counts 2) in 6 full-rate VALU issue slots, plus one
+# base-2 exponential.
 MARCH_FLOPS_PER_UPDATE = 9.0
 MARCH_SLOTS_PER_UPDATE = 6.0
 # MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz = 39.32e12 lane-slots/s (packed
-# FP32 is not used).  The exponential is issued at quarter rate (4 slots).
+# FP32 is not used).  The hardware exponential issues at half rate on gfx950
+# (2 slots), as measured by paper_cs_0703028_amd/probe/alu_rates.hip.
 LANE_SLOTS_PER_S = 256 * 64 * 2.4e9
-TRANS_SLOTS = 4.0
+TRANS_SLOTS = 2.0
 
 
 def march_peak_updates_per_s():
@@ -154,8 +156,8 @@ def main():
         "roofline": {
             "bound": "alu",
             "kernel": "march_kernel",
-            "achieved": march_rate * (MARCH_FLOPS_PER_UPDATE + 1) / 1e12,
-            "peak": peak * (MARCH_FLOPS_PER_UPDATE + 1) / 1e12,
+            "achieved": march_rate * MARCH_FLOPS_PER_UPDATE / 1e12,
+            "peak": peak * MARCH_FLOPS_PER_UPDATE / 1e12,
             "unit": "TFLOP/s",
             "frac": march_rate / peak,
             "traffic": None,

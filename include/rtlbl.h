@@ -52,9 +52,16 @@ typedef enum {
   RT_KAPPA_COMPENSATED = 1  /* FP32 line sum with compensated summation     */
 } rt_kappa_mode;
 
+/* Form of the march (Eq. (3)); per-cell accumulators are FP64 in both.
+ *   RT_TALLY_F32: plain form.  Planck values evaluated in registers (FP32),
+ *     1 - exp(-tau) from the hardware exponential with a degree-3 series
+ *     below tau = 1/16, per-wavefront partial sums in FP32.
+ *   RT_TALLY_F64: precision form.  Planck values read from the FP64-derived
+ *     table of rt_compute_kappa (required), degree-5 series below tau = 1/4,
+ *     partial sums in FP64. */
 typedef enum {
-  RT_TALLY_F32 = 0,  /* per-wavefront partial sums in FP32, FP64 accumulators */
-  RT_TALLY_F64 = 1   /* partial sums in FP64 as well (precision form)         */
+  RT_TALLY_F32 = 0,
+  RT_TALLY_F64 = 1
 } rt_tally_prec;
 
 typedef struct {
@@ -99,7 +106,7 @@ rt_status rt_setup_grid(rt_ctx ctx, int nx, int ny, int nz, double cell_m,
  * Each line is evaluated on the points with |nu_j - nu_line| <= cutoff_cm;
  * cutoff_cm/dnu_cm must be an integer (to 1e-9 relative).  n_lines >= 0,
  * n_nu >= 1, dnu_cm > 0.  Host arrays are copied.  Invalidates a previous
- * rt_compute_kappa. */
+ * rt_compute_kappa.  nu0_cm > 0. */
 rt_status rt_setup_lines(rt_ctx ctx, int n_lines, const double* nu_cm,
                          const double* S_ref, const double* gamma_ref_cm,
                          const double* n_T, const double* E_lower_cm,
@@ -107,14 +114,18 @@ rt_status rt_setup_lines(rt_ctx ctx, int n_lines, const double* nu_cm,
                          double dnu_cm, int n_nu);
 
 /* Smallest admissible row pitch (in floats) of the kappa and Planck tables
- * for the current spectral grid: n_nu rounded up to the march chunk. */
+ * for the current spectral grid: n_nu rounded up to the march chunk (512);
+ * -1 before rt_setup_lines. */
 int64_t rt_required_pitch(rt_ctx ctx);
 
 /* Eq. (2) with Eq. (1) per cell: kappa_dev[c*ld + j] = kappa_c(nu_j) in
- * cm^-1, and Eq. (4): planck_dev[c*ld + j] = B(nu_j, T_c).  Both are caller
- * allocated device buffers of nx*ny*nz rows of `ld` floats, ld >=
- * rt_required_pitch (columns n_nu .. ld-1 are written with zeros).  The
- * handle keeps both pointers for rt_trace_rays.  mode: rt_kappa_mode. */
+ * cm^-1, and, when planck_dev is not NULL, Eq. (4): planck_dev[c*ld + j] =
+ * B(nu_j, T_c) evaluated in FP64 and stored in FP32.  Both are caller
+ * allocated, 16-byte aligned device buffers of nx*ny*nz rows of `ld` floats,
+ * ld a multiple of 512 and >= rt_required_pitch (columns n_nu .. ld-1 are
+ * written with zeros).  The handle keeps both pointers for rt_trace_rays;
+ * the Planck table is needed by the precision form of the march only.
+ * mode: rt_kappa_mode. */
 rt_status rt_compute_kappa(rt_ctx ctx, int mode, float* kappa_dev,
                            float* planck_dev, int64_t ld);
 

@@ -22,7 +22,11 @@ DEVICE_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    # a single lane issues each accumulator atomic; no wave-level rewrite
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
+PROBE_SRC = os.path.join(HERE, "probe", "alu_rates.hip")
+PROBE_BIN = os.path.join(HERE, "probe", "alu_rates.bin")
 
 
 def sources():
@@ -52,6 +56,11 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    r = subprocess.run([HIPCC, *DEVICE_FLAGS, "-o", PROBE_BIN + ".tmp", PROBE_SRC],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(PROBE_BIN + ".tmp", PROBE_BIN)
     return OUT
 
 

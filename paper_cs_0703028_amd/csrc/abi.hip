@@ -61,6 +61,7 @@ void free_lines(rt_ctx c) {
 void free_cells(rt_ctx c) {
   rt::CellSet& C = c->cells;
   dev_free(C.G); dev_free(C.beta); dev_free(C.theta); dev_free(C.lam2); dev_free(C.P);
+  dev_free(C.theta2);
 }
 
 void free_events(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
@@ -215,6 +216,7 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   RT_HIP(c, dev_alloc(&c->cells.theta, n));
   RT_HIP(c, dev_alloc(&c->cells.lam2, n));
   RT_HIP(c, dev_alloc(&c->cells.P, n));
+  RT_HIP(c, dev_alloc(&c->cells.theta2, n));
   RT_HIP(c, hipMemcpyAsync(c->d_T, T, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   RT_HIP(c, hipMemcpyAsync(c->d_x, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   RT_HIP(c, hipMemcpyAsync(c->d_p, p, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -235,8 +237,8 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
   if (!c) return fail(c, RT_EINVAL, "rt_setup_lines: NULL handle");
   if (n_lines < 0) return fail(c, RT_EINVAL, "rt_setup_lines: n_lines must be >= 0");
   if (n_nu < 1) return fail(c, RT_EINVAL, "rt_setup_lines: n_nu must be >= 1");
-  if (!(dnu > 0) || !std::isfinite(dnu) || !std::isfinite(nu0))
-    return fail(c, RT_EINVAL, "rt_setup_lines: dnu must be > 0 and nu0 finite");
+  if (!(dnu > 0) || !std::isfinite(dnu) || !(nu0 > 0) || !std::isfinite(nu0))
+    return fail(c, RT_EINVAL, "rt_setup_lines: dnu and nu0 must be finite and > 0");
   if (!(T_ref > 0) || !std::isfinite(T_ref)) return fail(c, RT_EINVAL, "rt_setup_lines: T_ref must be > 0");
   if (!(cutoff >= 0) || !std::isfinite(cutoff)) return fail(c, RT_EINVAL, "rt_setup_lines: cutoff must be >= 0");
   const double Kd = cutoff / dnu;
@@ -347,9 +349,9 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_setup_grid and rt_setup_lines first");
   if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED)
     return fail(c, RT_EINVAL, "rt_compute_kappa: unknown mode");
-  if (!kappa_dev || !planck_dev) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL buffer");
+  if (!kappa_dev) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL kappa buffer");
   if (ld < rt_required_pitch(c) || ld % rt::kChunk != 0)
-    return fail(c, RT_EINVAL, "rt_compute_kappa: ld must be a multiple of 256 and >= rt_required_pitch");
+    return fail(c, RT_EINVAL, "rt_compute_kappa: ld must be a multiple of 512 and >= rt_required_pitch");
   if ((reinterpret_cast<uintptr_t>(kappa_dev) | reinterpret_cast<uintptr_t>(planck_dev)) & 15)
     return fail(c, RT_EINVAL, "rt_compute_kappa: buffers must be 16-byte aligned");
   if (rt_status s = set_device(c)) return s;
@@ -369,7 +371,7 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   }
   RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
   if (rt_status s = record_end(c, c->kappa_events)) return s;
-  RT_HIP(c, rt::launch_planck(c));
+  RT_HIP(c, rt::launch_planck(c));  // wall row always; cell table if requested
   c->stats.line_evals += c->line_evals_per_cell * (double)c->n_cells;
   c->have_kappa = true;
   return RT_OK;
@@ -402,6 +404,9 @@ rt_status rt_trace_rays(rt_ctx c, uint64_t seed, uint64_t n_rays_total, uint64_t
     return fail(c, RT_EINVAL, "rt_trace_rays: ray range outside [0, n_rays_total)");
   if (tally_prec != RT_TALLY_F32 && tally_prec != RT_TALLY_F64)
     return fail(c, RT_EINVAL, "rt_trace_rays: unknown tally precision");
+  if (tally_prec == RT_TALLY_F64 && !c->planck)
+    return fail(c, RT_ESTATE, "rt_trace_rays: the precision form needs the Planck table "
+                              "(pass planck_dev to rt_compute_kappa)");
   if (ray_count == 0) return RT_OK;
   if (rt_status s = set_device(c)) return s;
   return trace_batches(c, seed, ray_begin, ray_count, ray_weight(c, (double)n_rays_total),
@@ -416,6 +421,8 @@ rt_status rt_trace_explicit(rt_ctx c, int n_rays, const int64_t* O, const int64_
   if (!std::isfinite(weight)) return fail(c, RT_EINVAL, "rt_trace_explicit: weight not finite");
   if (tally_prec != RT_TALLY_F32 && tally_prec != RT_TALLY_F64)
     return fail(c, RT_EINVAL, "rt_trace_explicit: unknown tally precision");
+  if (tally_prec == RT_TALLY_F64 && !c->planck)
+    return fail(c, RT_ESTATE, "rt_trace_explicit: the precision form needs the Planck table");
   if (rt_status s = ensure_batch(c)) return s;
   if (n_rays > c->batch_rays) return fail(c, RT_EINVAL, "rt_trace_explicit: too many rays");
   const int64_t lim[3] = {c->nx * rt::kCellUnits, c->ny * rt::kCellUnits, c->nz * rt::kCellUnits};

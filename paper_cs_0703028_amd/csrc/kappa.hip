@@ -58,7 +58,7 @@ __global__ void cell_params_kernel(int64_t n, const double* __restrict__ T,
                                    const double* __restrict__ p, double T_ref,
                                    double dnu, double c2, int have_E,
                                    float* G, double* beta, double* theta,
-                                   float* lam2, float* P) {
+                                   float* lam2, float* P, float* theta2) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   double Tc = T[c];
@@ -69,6 +69,7 @@ __global__ void cell_params_kernel(int64_t n, const double* __restrict__ T,
   theta[c] = c2 / Tc;
   lam2[c] = (float)log2(T_ref / Tc);
   P[c] = (float)(p[c] / dnu);
+  theta2[c] = (float)(c2 / Tc * 1.4426950408889634074);
 }
 
 __device__ __forceinline__ int first_ge(const int32_t* a, int n, int v) {
@@ -293,7 +294,7 @@ hipError_t launch_cell_params(rt_ctx c) {
   hipLaunchKernelGGL(cell_params_kernel, dim3((unsigned)blocks), dim3(threads), 0, c->stream,
                      n, c->d_T, c->d_x, c->d_p, c->T_ref, c->dnu, second_radiation_cm_K(),
                      c->have_E ? 1 : 0, c->cells.G, c->cells.beta, c->cells.theta,
-                     c->cells.lam2, c->cells.P);
+                     c->cells.lam2, c->cells.P, c->cells.theta2);
   return hipGetLastError();
 }
 
@@ -324,13 +325,15 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
 hipError_t launch_planck(rt_ctx c) {
   const double c1 = first_radiation_wavenumber(), c2 = second_radiation_cm_K();
   const int tiles = (int)((c->ld + 255) / 256);
-  const int64_t blocks = c->n_cells * tiles;
-  const unsigned gx = (unsigned)std::min<int64_t>(blocks, 65536);
-  const unsigned gy = (unsigned)((blocks + gx - 1) / gx);
-  hipLaunchKernelGGL(planck_table_kernel, dim3(gx, gy), dim3(256), 0, c->stream, c->d_T,
-                     c->n_cells, c->n_nu, c->ld, tiles, c->nu0, c->dnu, c1, c2, c->planck);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (c->planck) {
+    const int64_t blocks = c->n_cells * tiles;
+    const unsigned gx = (unsigned)std::min<int64_t>(blocks, 65536);
+    const unsigned gy = (unsigned)((blocks + gx - 1) / gx);
+    hipLaunchKernelGGL(planck_table_kernel, dim3(gx, gy), dim3(256), 0, c->stream, c->d_T,
+                       c->n_cells, c->n_nu, c->ld, tiles, c->nu0, c->dnu, c1, c2, c->planck);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(wall_table_kernel, dim3((unsigned)((c->ld + 255) / 256)), dim3(256), 0,
                      c->stream, c->T_wall, c->n_nu, c->ld, c->nu0, c->dnu, c1, c2, c->d_bwall);
   return hipGetLastError();

@@ -4,8 +4,8 @@
 //                cosine-weighted inward direction) and exact integer
 //                traversal -> per-ray list of (cell, length) segments
 //   march      : Eq. (3) applied cell after cell for every nu point; each
-//                wavefront owns one ray and a 256-point spectral chunk
-//                (4 contiguous points per lane); per segment the absorbed
+//                wavefront owns one ray and a 512-point spectral chunk
+//                (8 contiguous points per lane); per segment the absorbed
 //                and emitted power of the chunk is combined across the
 //                wavefront with DPP reductions and added to the cell's FP64
 //                accumulator
@@ -211,24 +211,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return *reinterpret_cast<double*>(&r);
 }
 
-// a = 1 - e^{-tau} for tau >= 0.  Below tau = 1/4 the degree-5 Taylor
-// polynomial of (1 - e^{-tau})/tau (truncation < 5e-8 relative); above it
-// 1 - 2^{-tau log2 e} with the hardware base-2 exponential, as the paper's
-// listing folds 1/ln 2 into the per-volume scalar.
-__device__ __forceinline__ float one_minus_exp_neg(float tau, float x2) {
+// a = 1 - e^{-tau} for tau >= 0, two accuracy levels.
+//   precision form: degree-5 Taylor polynomial of (1 - e^{-tau})/tau below
+//     tau = 1/4 (truncation < 5e-8), 1 - 2^{-tau log2 e} above (<= 5e-7);
+//   plain form: degree-3 polynomial below tau = 1/16 (truncation < 1.3e-7),
+//     1 - 2^{-tau log2 e} above (<= 2e-6 just above the switch, falling as
+//     1/tau), and the polynomial is skipped by the whole wavefront when no
+//     lane needs it.
+// The exponent is folded into base 2 per segment, as the paper's listing
+// folds 1/ln 2 into the per-volume scalar.
+__device__ __forceinline__ float poly5(float tau) {
   float p = fmaf(tau, -1.0f / 720.0f, 1.0f / 120.0f);
   p = fmaf(tau, p, -1.0f / 24.0f);
   p = fmaf(tau, p, 1.0f / 6.0f);
   p = fmaf(tau, p, -0.5f);
   p = fmaf(tau, p, 1.0f);
-  const float small = tau * p;
-  const float big = 1.0f - __builtin_amdgcn_exp2f(x2);
-  return tau < 0.25f ? small : big;
+  return tau * p;
+}
+__device__ __forceinline__ float poly3(float tau) {
+  float p = fmaf(tau, -1.0f / 24.0f, 1.0f / 6.0f);
+  p = fmaf(tau, p, -0.5f);
+  p = fmaf(tau, p, 1.0f);
+  return tau * p;
 }
 
 struct MarchArgs {
   const float* kappa;
-  const float* planck;
+  const float* planck;   // precision form only
+  const float* theta2;   // plain form: c2 log2(e) / T per cell
   const float* bwall;
   int64_t ld;
   int n_chunks;
@@ -238,6 +248,7 @@ struct MarchArgs {
   int max_segs;
   int64_t n_rays;
   double weight;
+  double nu0, dnu, c1;
   double* acc_abs;
   double* acc_emi;
   double* slots;
@@ -249,11 +260,17 @@ struct Partial { using T = float; };
 template <>
 struct Partial<true> { using T = double; };
 
-// Block = 4 wavefronts = 4 consecutive rays on one 256-point chunk; blocks
-// run chunk-major so that the waves in flight share kappa[:, chunk].
-template <bool F64, bool EXIT>
+constexpr int kQ = kChunk / 64;  // contiguous nu points per lane
+
+// Block = 4 wavefronts = 4 consecutive rays on one spectral chunk; blocks run
+// chunk-major so that the waves in flight share kappa[:, chunk].  Each lane
+// owns kQ contiguous points.  PREC selects the precision form: Planck values
+// from the FP64-derived table, the degree-5 branch and FP64 partial sums;
+// otherwise B = c1 nu^3 / (2^{theta2 nu} - 1) is evaluated in registers,
+// which halves the table traffic of the march.
+template <bool PREC, bool EXIT>
 __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
-  using PT = typename Partial<F64>::T;
+  using PT = typename Partial<PREC>::T;
   const int64_t b = blockIdx.x;
   const int chunk = (int)(b / a.ray_blocks);
   const int64_t rb = b % a.ray_blocks;
@@ -261,10 +278,25 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t ray = rb * 4 + wave;
   if (ray >= a.n_rays) return;
-  const int64_t j = (int64_t)chunk * kChunk + lane * 4;
+  const int64_t j = (int64_t)chunk * kChunk + lane * kQ;
 
-  float4 I = *reinterpret_cast<const float4*>(a.bwall + j);
-  const float enter = (I.x + I.y) + (I.z + I.w);
+  float I[kQ], nu[kQ], c1nu3[kQ];
+#pragma unroll
+  for (int h = 0; h < kQ / 4; ++h) {
+    const float4 v = *reinterpret_cast<const float4*>(a.bwall + j + 4 * h);
+    I[4 * h] = v.x; I[4 * h + 1] = v.y; I[4 * h + 2] = v.z; I[4 * h + 3] = v.w;
+  }
+  if (!PREC) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const double v = a.nu0 + (double)(j + q) * a.dnu;
+      nu[q] = (float)v;
+      c1nu3[q] = (float)(a.c1 * v * v * v);
+    }
+  }
+  float enter = 0.f;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) enter += I[q];
   const int ns = a.counts[ray];
   const int2* sg = a.segs + ray * a.max_segs;
   const float nlog2e = -1.4426950408889634f;
@@ -273,19 +305,54 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
     const int64_t c = s.x;
     const float l = __int_as_float(s.y);
     const float xs = l * nlog2e;
-    const float4 kv = *reinterpret_cast<const float4*>(a.kappa + c * a.ld + j);
-    const float4 bv = *reinterpret_cast<const float4*>(a.planck + c * a.ld + j);
-    PT ab = 0, em = 0;
-#define RT_STEP(F)                                                  \
-    {                                                               \
-      const float tau = kv.F * l;                                   \
-      const float aa = one_minus_exp_neg(tau, kv.F * xs);           \
-      ab += (PT)(I.F * aa);                                         \
-      em += (PT)(bv.F * aa);                                        \
-      I.F = fmaf(-(I.F - bv.F), aa, I.F);                           \
+    float kv[kQ], bv[kQ];
+#pragma unroll
+    for (int h = 0; h < kQ / 4; ++h) {
+      const float4 v = *reinterpret_cast<const float4*>(a.kappa + c * a.ld + j + 4 * h);
+      kv[4 * h] = v.x; kv[4 * h + 1] = v.y; kv[4 * h + 2] = v.z; kv[4 * h + 3] = v.w;
     }
-    RT_STEP(x) RT_STEP(y) RT_STEP(z) RT_STEP(w)
-#undef RT_STEP
+    if (PREC) {
+#pragma unroll
+      for (int h = 0; h < kQ / 4; ++h) {
+        const float4 v = *reinterpret_cast<const float4*>(a.planck + c * a.ld + j + 4 * h);
+        bv[4 * h] = v.x; bv[4 * h + 1] = v.y; bv[4 * h + 2] = v.z; bv[4 * h + 3] = v.w;
+      }
+    } else {
+      const float th = a.theta2[c];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q)
+        bv[q] = c1nu3[q] * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(th * nu[q]) - 1.0f);
+    }
+    float av[kQ];
+    if (PREC) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const float tau = kv[q] * l;
+        const float big = 1.0f - __builtin_amdgcn_exp2f(kv[q] * xs);
+        av[q] = tau < 0.25f ? poly5(tau) : big;
+      }
+    } else {
+      float tmin = kv[0];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        av[q] = 1.0f - __builtin_amdgcn_exp2f(kv[q] * xs);
+        tmin = fminf(tmin, kv[q]);
+      }
+      if (__ballot(tmin * l < 0.0625f)) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          const float tau = kv[q] * l;
+          av[q] = tau < 0.0625f ? poly3(tau) : av[q];
+        }
+      }
+    }
+    PT ab = 0, em = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      ab += (PT)(I[q] * av[q]);
+      em += (PT)(bv[q] * av[q]);
+      I[q] = fmaf(-(I[q] - bv[q]), av[q], I[q]);
+    }
     const PT tab = wave_sum(ab);
     const PT tem = wave_sum(em);
     if (lane == 0) {
@@ -293,8 +360,15 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
       unsafeAtomicAdd(a.acc_emi + c, a.weight * (double)tem);
     }
   }
-  if (EXIT) *reinterpret_cast<float4*>(a.exit_I + ray * a.ld + j) = I;
-  const float esc = (I.x + I.y) + (I.z + I.w);
+  float esc = 0.f;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) esc += I[q];
+  if (EXIT) {
+#pragma unroll
+    for (int h = 0; h < kQ / 4; ++h)
+      *reinterpret_cast<float4*>(a.exit_I + ray * a.ld + j + 4 * h) =
+          make_float4(I[4 * h], I[4 * h + 1], I[4 * h + 2], I[4 * h + 3]);
+  }
   const PT te = wave_sum((PT)enter);
   const PT tx = wave_sum((PT)esc);
   if (lane == 0) {
@@ -349,10 +423,11 @@ hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count,
   return hipGetLastError();
 }
 
-hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool f64, float* exit_dev) {
+hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev) {
   MarchArgs a;
   a.kappa = c->kappa;
   a.planck = c->planck;
+  a.theta2 = c->cells.theta2;
   a.bwall = c->d_bwall;
   a.ld = c->ld;
   a.n_chunks = (int)(c->ld / kChunk);
@@ -362,6 +437,9 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool f64, float*
   a.max_segs = c->max_segs;
   a.n_rays = count;
   a.weight = weight;
+  a.nu0 = c->nu0;
+  a.dnu = c->dnu;
+  a.c1 = first_radiation_wavenumber();
   a.acc_abs = c->d_abs;
   a.acc_emi = c->d_emi;
   a.slots = c->d_slots;
@@ -369,7 +447,7 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool f64, float*
   const int64_t blocks = a.ray_blocks * a.n_chunks;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)blocks), t(256);
-  if (f64) {
+  if (prec) {
     if (exit_dev) hipLaunchKernelGGL((march_kernel<true, true>), g, t, 0, c->stream, a);
     else hipLaunchKernelGGL((march_kernel<true, false>), g, t, 0, c->stream, a);
   } else {

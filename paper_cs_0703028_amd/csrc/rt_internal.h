@@ -14,7 +14,7 @@ namespace rt {
 
 // Fixed-point traversal frame: one cell edge is 2^21 integer units.
 constexpr int64_t kCellUnits = int64_t(1) << 21;
-constexpr int kChunk = 256;       // march: nu points per wavefront (64 lanes x 4)
+constexpr int kChunk = 512;       // march: nu points per wavefront (64 lanes x 8)
 constexpr int kMaxAxis = 1 << 20; // largest admissible cells per axis
 
 // Physical constants (SI 2019 exact values).
@@ -46,6 +46,7 @@ struct CellSet {
   double* theta = nullptr;  // c2 / T
   float* lam2 = nullptr;    // log2(T_ref / T)
   float* P = nullptr;       // p / dnu
+  float* theta2 = nullptr;  // c2 log2(e) / T: Planck exponent in base 2 per cm^-1
 };
 
 struct Stats {
@@ -122,7 +123,7 @@ hipError_t launch_kappa(rt_ctx c, bool compensated);
 hipError_t launch_planck(rt_ctx c);
 hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,
                          int64_t* rays_out, bool count_work);
-hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool f64, float* exit_dev);
+hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev);
 hipError_t launch_tally(rt_ctx c);
 hipError_t launch_zero(rt_ctx c);
 }  // namespace rt
