@@ -114,7 +114,7 @@ rt_status rt_setup_lines(rt_ctx ctx, int n_lines, const double* nu_cm,
                          double dnu_cm, int n_nu);
 
 /* Smallest admissible row pitch (in floats) of the kappa and Planck tables
- * for the current spectral grid: n_nu rounded up to the march chunk (512);
+ * for the current spectral grid: n_nu rounded up to the march chunk (1024);
  * -1 before rt_setup_lines. */
 int64_t rt_required_pitch(rt_ctx ctx);
 
@@ -122,7 +122,7 @@ int64_t rt_required_pitch(rt_ctx ctx);
  * cm^-1, and, when planck_dev is not NULL, Eq. (4): planck_dev[c*ld + j] =
  * B(nu_j, T_c) evaluated in FP64 and stored in FP32.  Both are caller
  * allocated, 16-byte aligned device buffers of nx*ny*nz rows of `ld` floats,
- * ld a multiple of 512 and >= rt_required_pitch (columns n_nu .. ld-1 are
+ * ld a multiple of 1024 and >= rt_required_pitch (columns n_nu .. ld-1 are
  * written with zeros).  The handle keeps both pointers for rt_trace_rays;
  * the Planck table is needed by the precision form of the march only.
  * mode: rt_kappa_mode. */

@@ -351,7 +351,7 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     return fail(c, RT_EINVAL, "rt_compute_kappa: unknown mode");
   if (!kappa_dev) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL kappa buffer");
   if (ld < rt_required_pitch(c) || ld % rt::kChunk != 0)
-    return fail(c, RT_EINVAL, "rt_compute_kappa: ld must be a multiple of 512 and >= rt_required_pitch");
+    return fail(c, RT_EINVAL, "rt_compute_kappa: ld must be a multiple of the march chunk (rt_required_pitch) and >= it");
   if ((reinterpret_cast<uintptr_t>(kappa_dev) | reinterpret_cast<uintptr_t>(planck_dev)) & 15)
     return fail(c, RT_EINVAL, "rt_compute_kappa: buffers must be 16-byte aligned");
   if (rt_status s = set_device(c)) return s;

@@ -238,7 +238,7 @@ __device__ __forceinline__ float poly3(float tau) {
 struct MarchArgs {
   const float* kappa;
   const float* planck;   // precision form only
-  const float* theta2;   // plain form: c2 log2(e) / T per cell
+  const double* theta;   // plain form: c2 / T per cell
   const float* bwall;
   int64_t ld;
   int n_chunks;
@@ -266,8 +266,8 @@ constexpr int kQ = kChunk / 64;  // contiguous nu points per lane
 // chunk-major so that the waves in flight share kappa[:, chunk].  Each lane
 // owns kQ contiguous points.  PREC selects the precision form: Planck values
 // from the FP64-derived table, the degree-5 branch and FP64 partial sums;
-// otherwise B = c1 nu^3 / (2^{theta2 nu} - 1) is evaluated in registers,
-// which halves the table traffic of the march.
+// otherwise the Planck values are formed in registers (one exponential and
+// one reciprocal per lane and segment), which halves the table traffic.
 template <bool PREC, bool EXIT>
 __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
   using PT = typename Partial<PREC>::T;
@@ -280,19 +280,26 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
   if (ray >= a.n_rays) return;
   const int64_t j = (int64_t)chunk * kChunk + lane * kQ;
 
-  float I[kQ], nu[kQ], c1nu3[kQ];
+  float I[kQ];
 #pragma unroll
   for (int h = 0; h < kQ / 4; ++h) {
     const float4 v = *reinterpret_cast<const float4*>(a.bwall + j + 4 * h);
     I[4 * h] = v.x; I[4 * h + 1] = v.y; I[4 * h + 2] = v.z; I[4 * h + 3] = v.w;
   }
+  // plain form: Planck values of the lane's kQ points from one exact value
+  // at its first point nu_a and the second-order expansion of ln B:
+  //   B(nu_a + d) = B_a (1 + g1 d + (g1^2 + g2) d^2 / 2),
+  //   g1 = 3/nu - theta (1 + r),  g2 = -3/nu^2 + theta^2 r (1 + r),
+  //   theta = c2 / T,  r = 1 / (exp(theta nu) - 1);
+  // for d <= (kQ - 1) dnu the neglected terms are below 1e-9 relative.
+  double nu_a = 0.0;
+  float c1nu3 = 0.f, three_nu = 0.f, three_nu2 = 0.f;
+  const float dnu_f = (float)a.dnu;
   if (!PREC) {
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const double v = a.nu0 + (double)(j + q) * a.dnu;
-      nu[q] = (float)v;
-      c1nu3[q] = (float)(a.c1 * v * v * v);
-    }
+    nu_a = a.nu0 + (double)j * a.dnu;
+    c1nu3 = (float)(a.c1 * nu_a * nu_a * nu_a);
+    three_nu = (float)(3.0 / nu_a);
+    three_nu2 = (float)(3.0 / (nu_a * nu_a));
   }
   float enter = 0.f;
 #pragma unroll
@@ -318,10 +325,32 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
         bv[4 * h] = v.x; bv[4 * h + 1] = v.y; bv[4 * h + 2] = v.z; bv[4 * h + 3] = v.w;
       }
     } else {
-      const float th = a.theta2[c];
+      const double th = a.theta[c];  // c2 / T
+      // exp(theta nu_a) with FP64 range reduction: 2^n 2^f, |f| <= 1/2
+      const double z = th * 1.4426950408889634074 * nu_a;
+      const double n = rint(z);
+      const float f = (float)(z - n);
+      const float e = ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
+      float em1 = e - 1.0f;
+      if (__ballot(z < 0.36)) {  // theta nu < 1/4: expm1 by its series
+        const float x = (float)(th * nu_a);
+        float p = fmaf(x, 1.0f / 720.0f, 1.0f / 120.0f);
+        p = fmaf(x, p, 1.0f / 24.0f);
+        p = fmaf(x, p, 1.0f / 6.0f);
+        p = fmaf(x, p, 0.5f);
+        p = fmaf(x, p, 1.0f);
+        if (z < 0.36) em1 = x * p;
+      }
+      const float r = __builtin_amdgcn_rcpf(em1);
+      const float B0 = c1nu3 * r;
+      const float thf = (float)th;
+      const float t1 = 1.0f + r;
+      const float g1 = fmaf(-thf, t1, three_nu);
+      const float g2 = fmaf(thf * thf, r * t1, -three_nu2);
+      const float K1 = B0 * g1 * dnu_f;
+      const float K2 = 0.5f * B0 * fmaf(g1, g1, g2) * (dnu_f * dnu_f);
 #pragma unroll
-      for (int q = 0; q < kQ; ++q)
-        bv[q] = c1nu3[q] * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(th * nu[q]) - 1.0f);
+      for (int q = 0; q < kQ; ++q) bv[q] = fmaf(fmaf(K2, (float)q, K1), (float)q, B0);
     }
     float av[kQ];
     if (PREC) {
@@ -332,13 +361,13 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
         av[q] = tau < 0.25f ? poly5(tau) : big;
       }
     } else {
-      float tmin = kv[0];
+      float kmin = kv[0];
 #pragma unroll
       for (int q = 0; q < kQ; ++q) {
         av[q] = 1.0f - __builtin_amdgcn_exp2f(kv[q] * xs);
-        tmin = fminf(tmin, kv[q]);
+        kmin = fminf(kmin, kv[q]);
       }
-      if (__ballot(tmin * l < 0.0625f)) {
+      if (__ballot(kmin * l < 0.0625f)) {
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
           const float tau = kv[q] * l;
@@ -427,7 +456,7 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float
   MarchArgs a;
   a.kappa = c->kappa;
   a.planck = c->planck;
-  a.theta2 = c->cells.theta2;
+  a.theta = c->cells.theta;
   a.bwall = c->d_bwall;
   a.ld = c->ld;
   a.n_chunks = (int)(c->ld / kChunk);

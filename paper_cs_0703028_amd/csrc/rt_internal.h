@@ -14,7 +14,11 @@ namespace rt {
 
 // Fixed-point traversal frame: one cell edge is 2^21 integer units.
 constexpr int64_t kCellUnits = int64_t(1) << 21;
-constexpr int kChunk = 512;       // march: nu points per wavefront (64 lanes x 8)
+#ifndef RT_MARCH_POINTS_PER_LANE
+#define RT_MARCH_POINTS_PER_LANE 16
+#endif
+// march: nu points per wavefront (64 lanes x contiguous points per lane)
+constexpr int kChunk = 64 * RT_MARCH_POINTS_PER_LANE;
 constexpr int kMaxAxis = 1 << 20; // largest admissible cells per axis
 
 // Physical constants (SI 2019 exact values).
