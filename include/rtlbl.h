@@ -74,6 +74,9 @@ typedef struct {
   double march_ms;          /* of which in the march kernel                    */
   double rays;              /* rays traced since the last reset               */
   double march_launches;    /* march kernel launches since the last reset     */
+  double batch_line_evals;  /* line evaluations of the last batched launch    */
+  double batch_updates;     /* ray-cell-nu updates of the last batched launch */
+  double batch_ms;          /* device time of the last batched launch         */
 } rt_stats;
 
 /* Create a handle bound to HIP device `hip_device` and the borrowed stream
@@ -173,6 +176,76 @@ rt_status rt_debug_segments(rt_ctx ctx, uint64_t seed, uint64_t ray_begin,
 
 /* Work counters and device times (synchronises). */
 rt_status rt_get_stats(rt_ctx ctx, rt_stats* out);
+
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent receiver cases (each its own grid, wall
+ * temperature, ray count and seed) sharing the line list and spectral grid
+ * of rt_setup_lines, run as one persistent work-queue kernel captured in a
+ * HIP graph.  The line sum and the march are fused per (case, spectral
+ * chunk): the chunk's kappa is built into one of `slots` slabs and marched
+ * at once, so no full kappa table is ever stored.  Plain-form march
+ * (rt_tally_prec RT_TALLY_F32); kappa_mode as rt_compute_kappa.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int nx, ny, nz;        /* as rt_setup_grid                                */
+  double cell_m;
+  const double* T_K;     /* host, nx*ny*nz each; read by rt_batch_prepare   */
+  const double* x_h2o;
+  const double* p_atm;
+  double T_wall_K;
+  uint64_t seed;         /* Philox seed of the case's rays                  */
+  uint64_t n_rays;       /* >= 1                                            */
+} rt_case;
+
+typedef struct {
+  int chunk_points;   /* nu points per (case, chunk) pair, multiple of 1024 */
+  int kappa_groups;   /* groups of 4 cells per line-sum work item, >= 1     */
+  int march_rays;     /* rays per march work item, multiple of 4            */
+  int blocks_per_cu;  /* persistent blocks per compute unit, 1..8           */
+  int slots;          /* kappa slabs in flight, 2..8                        */
+} rt_batch_tuning;
+
+/* A tuning that is valid for any batch (2048, 16, 64, 2, 3). */
+rt_status rt_batch_default_tuning(rt_batch_tuning* out);
+
+/* Device workspace the batch needs with this tuning (tuning NULL: default):
+ * segments of every ray, `slots` kappa slabs of the largest case, per-case
+ * tables, accumulators and the work plan. */
+rt_status rt_batch_workspace_size(rt_ctx ctx, int n_cases, const rt_case* cases,
+                                  const rt_batch_tuning* tuning, int64_t* bytes);
+
+/* Validates the cases, copies their fields into the caller-owned device
+ * workspace (at least rt_batch_workspace_size bytes, 256-byte aligned),
+ * derives per-cell parameters and builds the work plan and its HIP graph.
+ * The workspace must stay alive until the last rt_batch_results. */
+rt_status rt_batch_prepare(rt_ctx ctx, int n_cases, const rt_case* cases,
+                           int kappa_mode, const rt_batch_tuning* tuning,
+                           void* workspace_dev, int64_t workspace_bytes);
+
+/* One launch of the prepared graph on the handle's stream (asynchronous):
+ * clears the accumulators, runs the persistent kernel over all cases and
+ * reduces the per-case balances.  May be repeated. */
+rt_status rt_batch_launch(rt_ctx ctx);
+
+/* Synchronises and copies the results of the last launch: absorbed_W and
+ * emitted_W concatenate the cases' cells in case order (host arrays of the
+ * total cell count, each may be NULL); balance holds 4 doubles per case
+ * {entering, emitted, absorbed, escaped} (may be NULL).  RT_EDEVICE if the
+ * persistent kernel reported a stalled dependency wait. */
+rt_status rt_batch_results(rt_ctx ctx, double* absorbed_W, double* emitted_W,
+                           double* balance);
+
+/* Picks chunk_points, kappa_groups, march_rays and blocks_per_cu by timing
+ * launches restricted to the first spectral chunks of every case (a sweep
+ * one parameter at a time from the default), and remembers the winner in a
+ * JSON file keyed by device architecture and a bucket of the batch shape
+ * (cache_path NULL: no file).  A cached entry is returned without timing.
+ * Leaves no batch prepared. */
+rt_status rt_batch_autotune(rt_ctx ctx, int n_cases, const rt_case* cases,
+                            int kappa_mode, void* workspace_dev,
+                            int64_t workspace_bytes, const char* cache_path,
+                            rt_batch_tuning* best);
 
 #ifdef __cplusplus
 }

@@ -61,7 +61,6 @@ void free_lines(rt_ctx c) {
 void free_cells(rt_ctx c) {
   rt::CellSet& C = c->cells;
   dev_free(C.G); dev_free(C.beta); dev_free(C.theta); dev_free(C.lam2); dev_free(C.P);
-  dev_free(C.theta2);
 }
 
 void free_events(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
@@ -173,6 +172,8 @@ rt_status rt_destroy(rt_ctx c) {
   dev_free(c->d_segcount);
   dev_free(c->d_segs); dev_free(c->d_counts); dev_free(c->d_rays_explicit); dev_free(c->d_exit);
   free_events(c->trace_events); free_events(c->march_events); free_events(c->kappa_events);
+  free_events(c->batch_events);
+  rt::destroy_batch(c);
   delete c;
   return RT_OK;
 }
@@ -216,7 +217,6 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   RT_HIP(c, dev_alloc(&c->cells.theta, n));
   RT_HIP(c, dev_alloc(&c->cells.lam2, n));
   RT_HIP(c, dev_alloc(&c->cells.P, n));
-  RT_HIP(c, dev_alloc(&c->cells.theta2, n));
   RT_HIP(c, hipMemcpyAsync(c->d_T, T, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   RT_HIP(c, hipMemcpyAsync(c->d_x, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   RT_HIP(c, hipMemcpyAsync(c->d_p, p, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -578,6 +578,9 @@ rt_status rt_get_stats(rt_ctx c, rt_stats* out) {
   out->march_ms = c->stats.march_ms;
   out->rays = c->stats.rays;
   out->march_launches = c->stats.march_launches;
+  out->batch_line_evals = c->stats.batch_line_evals;
+  out->batch_updates = c->stats.batch_updates;
+  out->batch_ms = c->stats.batch_ms;
   return RT_OK;
 }
 

@@ -1,0 +1,329 @@
+// batch.hip -- many independent receiver cases in one persistent launch.
+//
+// Work is a queue of items in a fixed order; every block pops the next item
+// with one atomic and runs it:
+//   RAYGEN (case, 256 rays)            rays and exact traversal -> segments
+//   KAPPA  (case, chunk, tile, groups) line sum of a spectral chunk for a
+//                                      range of cells into a kappa slab
+//   MARCH  (case, chunk, ray range)    Eq. (3) over the chunk for the rays,
+//                                      reading the slab
+// The stage order is RAYGEN for every case, then K(0) K(1) M(0) K(2) M(1)
+// ... over (case, chunk) pairs, so the line sum of the next pair overlaps
+// the march of the current one.  Pair p writes slab p % slots.  An item
+// only ever waits for items that precede it in the queue, and those are
+// held by running blocks, so every wait ends; each wait is also bounded by
+// a spin limit after which the item is skipped and an error flag is set,
+// so the grid always drains.
+//
+// Memory ordering: items that produce data read by other blocks (segments,
+// slabs) end with an agent-scope release by every thread before their
+// completion counter is bumped; a block acquires once per pair before its
+// first march item of that pair.  A march item only reads its slab, so its
+// completion (which frees the slot for reuse) is counted with a relaxed
+// atomic after its loads have returned.
+#include "device_common.h"
+#include "batch_plan.h"
+
+namespace rt {
+namespace {
+
+using namespace dev;
+
+struct BatchArgs {
+  const BatchStage* stages;
+  int n_stages;
+  int64_t total_items;
+  const BatchCase* cases;
+  LineSet L;
+  CellSet C;        // packed over all cases
+  int n_nu, K, have_E, comp;
+  float* slabs;     // [slots][max_cells][chunk_points]
+  int64_t slab_stride;
+  int chunk_points;
+  int tiles_per_chunk;
+  int kappa_groups;
+  int march_rays;
+  int slots;
+  int2* segs;
+  int32_t* counts;
+  const float* bwall;  // [case][bwall_ld]
+  int64_t bwall_ld;
+  double* acc_abs;
+  double* acc_emi;
+  double* case_slots;  // [case][2][kCaseSlots]
+  double nu0, dnu, c1;
+  unsigned long long* queue;
+  unsigned* rg_done;
+  unsigned* k_done;
+  unsigned* m_done;
+  unsigned* error;
+  unsigned spin_limit;
+};
+
+__device__ __forceinline__ int find_stage(const BatchStage* st, int n, int64_t item) {
+  int lo = 0, hi = n - 1;  // last stage with first <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st[mid].first <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Spin (thread 0 only) until *p >= target, relaxed loads; false on timeout.
+__device__ __forceinline__ bool wait_count(const unsigned* p, unsigned target, unsigned limit) {
+  unsigned it = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++it > limit) return false;
+    __builtin_amdgcn_s_sleep(4);
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
+  __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
+  __shared__ long long s_item;
+  __shared__ int s_ok;
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  int ready_pair = -1;  // pair whose segments and slab this block has acquired
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) {
+      s_item = (long long)atomicAdd(a.queue, 1ull);
+      s_ok = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    }
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= a.total_items) break;
+    const BatchStage st = a.stages[find_stage(a.stages, a.n_stages, item)];
+    const BatchCase cs = a.cases[st.cas];
+    const int64_t local = item - st.first;
+    if (!s_ok) continue;  // a wait timed out somewhere: drain the queue
+
+    if (st.kind == kStageRaygen) {
+      const int64_t r = local * 256 + tid;
+      if (r < cs.n_rays) {
+        int64_t O[3], D[3];
+        sample_ray(cs.seed, (uint64_t)r, cs.nx, cs.ny, cs.nz, O, D);
+        const int ns = traverse(cs.nx, cs.ny, cs.nz, cs.unit_cm, O, D, cs.max_segs,
+                                a.segs + cs.seg_off + r * cs.max_segs);
+        a.counts[cs.ray_off + r] = ns;
+      }
+      __atomic_thread_fence(__ATOMIC_RELEASE);  // agent scope: segments visible
+      __syncthreads();
+      if (tid == 0) __hip_atomic_fetch_add(a.rg_done + st.cas, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+
+    float* slab = a.slabs + (int64_t)st.slot * a.slab_stride;
+    if (st.kind == kStageKappa) {
+      if (st.wait_pair >= 0) {  // the slab's previous pair must be marched
+        if (tid == 0) {
+          const BatchStage& ms = a.stages[st.wait_stage];
+          if (!wait_count(a.m_done + st.wait_pair, (unsigned)ms.count, a.spin_limit)) {
+            atomicOr(a.error, 1u);
+            s_ok = 0;
+          }
+        }
+        __syncthreads();
+        if (!s_ok) continue;
+      }
+      KappaTile t;
+      t.L = a.L;
+      t.C.G = a.C.G + cs.cell_off;
+      t.C.beta = a.C.beta + cs.cell_off;
+      t.C.theta = a.C.theta + cs.cell_off;
+      t.C.lam2 = a.C.lam2 + cs.cell_off;
+      t.C.P = a.C.P + cs.cell_off;
+      t.n_cells = cs.n_cells;
+      t.n_nu = a.n_nu;
+      t.K = a.K;
+      t.have_E = a.have_E;
+      t.out = slab;
+      t.ld_out = a.chunk_points;
+      t.col0 = (int64_t)st.chunk * a.chunk_points;
+      t.col_end = t.col0 + a.chunk_points;
+      const int tile = (int)(local % a.tiles_per_chunk);
+      const int64_t gb = local / a.tiles_per_chunk;
+      const int64_t n_groups = (cs.n_cells + kKappaCells - 1) / kKappaCells;
+      const int j0 = (int)(t.col0 + (int64_t)tile * kKappaTilePoints);
+      const int64_t g_end = min((gb + 1) * a.kappa_groups, n_groups);
+      for (int64_t g = gb * a.kappa_groups; g < g_end; ++g) {
+        if (a.comp) kappa_tile<true>(t, j0, g * kKappaCells, lds);
+        else kappa_tile<false>(t, j0, g * kKappaCells, lds);
+      }
+      __atomic_thread_fence(__ATOMIC_RELEASE);  // agent scope: slab visible
+      __syncthreads();
+      if (tid == 0) __hip_atomic_fetch_add(a.k_done + st.pair, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+
+    // MARCH
+    if (ready_pair != st.pair) {
+      if (tid == 0) {
+        const BatchStage& ks = a.stages[st.wait_stage];
+        const BatchStage& rs = a.stages[st.raygen_stage];
+        bool ok = wait_count(a.rg_done + st.cas, (unsigned)rs.count, a.spin_limit) &&
+                  wait_count(a.k_done + st.pair, (unsigned)ks.count, a.spin_limit);
+        if (!ok) {
+          atomicOr(a.error, 1u);
+          s_ok = 0;
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);  // agent scope
+      }
+      __syncthreads();
+      if (!s_ok) continue;
+      ready_pair = st.pair;
+    }
+    MarchWave w;
+    w.kappa = slab;
+    w.planck = nullptr;
+    w.ld = a.chunk_points;
+    w.col0 = (int64_t)st.chunk * a.chunk_points;
+    w.theta = a.C.theta + cs.cell_off;
+    w.bwall = a.bwall + (int64_t)st.cas * a.bwall_ld;
+    w.nu0 = a.nu0;
+    w.dnu = a.dnu;
+    w.c1 = a.c1;
+    w.weight = cs.weight;
+    w.acc_abs = a.acc_abs + cs.cell_off;
+    w.acc_emi = a.acc_emi + cs.cell_off;
+    const int64_t r0 = local * a.march_rays;
+    const int64_t r1 = min(r0 + a.march_rays, cs.n_rays);
+    double* cslots = a.case_slots + (int64_t)st.cas * 2 * kCaseSlots;
+    for (int64_t r = r0 + wave; r < r1; r += 4) {
+      const int2* sg = a.segs + cs.seg_off + r * cs.max_segs;
+      const int ns = a.counts[cs.ray_off + r];
+      for (int sub = 0; sub < a.chunk_points / kChunk; ++sub) {
+        const int64_t j = w.col0 + (int64_t)sub * kChunk + lane * kQ;
+        float te, tx;
+        march_wave<false, false>(w, sg, ns, j, lane, nullptr, te, tx);
+        if (lane == 0) {
+          const int s = (int)(r % kCaseSlots);
+          unsafeAtomicAdd(cslots + s, w.weight * (double)te);
+          unsafeAtomicAdd(cslots + kCaseSlots + s, w.weight * (double)tx);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(a.m_done + st.pair, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// balance per case = {entering, sum emitted, sum absorbed, escaped}, FP64,
+// fixed order.
+__global__ __launch_bounds__(256) void case_tally_kernel(const BatchCase* cases,
+                                                         const double* __restrict__ abs_,
+                                                         const double* __restrict__ emi,
+                                                         const double* __restrict__ cslots,
+                                                         double* balance) {
+  __shared__ double red[4][256];
+  const BatchCase cs = cases[blockIdx.x];
+  const int t = threadIdx.x;
+  double sa = 0, se = 0, en = 0, ex = 0;
+  for (int64_t c = t; c < cs.n_cells; c += 256) {
+    sa += abs_[cs.cell_off + c];
+    se += emi[cs.cell_off + c];
+  }
+  const double* sl = cslots + (int64_t)blockIdx.x * 2 * kCaseSlots;
+  for (int s = t; s < kCaseSlots; s += 256) { en += sl[s]; ex += sl[kCaseSlots + s]; }
+  red[0][t] = en; red[1][t] = se; red[2][t] = sa; red[3][t] = ex;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off)
+      for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + off];
+    __syncthreads();
+  }
+  if (t < 4) balance[4 * blockIdx.x + t] = red[t][0];
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+__global__ void fill_f64_kernel(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// B(nu_j, T_wall) rows per case, FP64 evaluated, FP32 stored.
+__global__ void case_wall_kernel(const double* T_wall, int n_cases, int n_nu, int64_t ld,
+                                 double nu0, double dnu, double c1, double c2, float* bw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_cases * ld) return;
+  const int cs = (int)(i / ld);
+  const int64_t j = i % ld;
+  float v = 0.f;
+  if (j < n_nu && T_wall[cs] > 0.0) {
+    const double nu = nu0 + (double)j * dnu;
+    v = (float)(c1 * nu * nu * nu / expm1(c2 * nu / T_wall[cs]));
+  }
+  bw[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_batch_prep(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
+  const double c1 = first_radiation_wavenumber(), c2 = second_radiation_cm_K();
+  const int64_t nw = (int64_t)pl.n_cases * pl.bwall_ld;
+  hipLaunchKernelGGL(case_wall_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s,
+                     pl.d_T_wall, pl.n_cases, c->n_nu, pl.bwall_ld, c->nu0, c->dnu, c1, c2,
+                     pl.d_bwall);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
+  auto fill_u = [&](unsigned* p, int64_t n) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  };
+  auto fill_d = [&](double* p, int64_t n) {
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  };
+  fill_u(pl.d_counters, pl.n_counters);
+  fill_d(pl.d_abs, pl.total_cells);
+  fill_d(pl.d_emi, pl.total_cells);
+  fill_d(pl.d_case_slots, (int64_t)pl.n_cases * 2 * kCaseSlots);
+  BatchArgs a;
+  a.stages = pl.d_stages;
+  a.n_stages = pl.n_stages;
+  a.total_items = pl.total_items;
+  a.cases = pl.d_cases;
+  a.L = c->lines;
+  a.C = pl.cells;
+  a.n_nu = c->n_nu;
+  a.K = c->K;
+  a.have_E = c->have_E ? 1 : 0;
+  a.comp = pl.comp ? 1 : 0;
+  a.slabs = pl.d_slabs;
+  a.slab_stride = pl.slab_stride;
+  a.chunk_points = pl.tuning.chunk_points;
+  a.tiles_per_chunk = pl.tuning.chunk_points / dev::kKappaTilePoints;
+  a.kappa_groups = pl.tuning.kappa_groups;
+  a.march_rays = pl.tuning.march_rays;
+  a.slots = pl.tuning.slots;
+  a.segs = pl.d_segs;
+  a.counts = pl.d_counts;
+  a.bwall = pl.d_bwall;
+  a.bwall_ld = pl.bwall_ld;
+  a.acc_abs = pl.d_abs;
+  a.acc_emi = pl.d_emi;
+  a.case_slots = pl.d_case_slots;
+  a.nu0 = c->nu0;
+  a.dnu = c->dnu;
+  a.c1 = first_radiation_wavenumber();
+  a.queue = reinterpret_cast<unsigned long long*>(pl.d_counters);
+  a.error = pl.d_counters + 2;
+  a.rg_done = pl.d_counters + 4;
+  a.k_done = a.rg_done + pl.n_cases;
+  a.m_done = a.k_done + pl.n_pairs;
+  a.spin_limit = 1u << 24;
+  hipLaunchKernelGGL(batch_kernel, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(case_tally_kernel, dim3((unsigned)pl.n_cases), dim3(256), 0, s, pl.d_cases,
+                     pl.d_abs, pl.d_emi, pl.d_case_slots, pl.d_balance);
+  return hipGetLastError();
+}
+
+}  // namespace rt

@@ -50,7 +50,6 @@ struct CellSet {
   double* theta = nullptr;  // c2 / T
   float* lam2 = nullptr;    // log2(T_ref / T)
   float* P = nullptr;       // p / dnu
-  float* theta2 = nullptr;  // c2 log2(e) / T: Planck exponent in base 2 per cm^-1
 };
 
 struct Stats {
@@ -60,8 +59,12 @@ struct Stats {
   double march_ms = 0;
   double rays = 0;
   double march_launches = 0;
+  double batch_line_evals = 0;
+  double batch_updates = 0;
+  double batch_ms = 0;
 };
 
+struct BatchPlan;
 }  // namespace rt
 
 struct rt_ctx_s {
@@ -114,8 +117,11 @@ struct rt_ctx_s {
   float* d_exit = nullptr;
   int64_t exit_cap = 0;
 
+  rt::BatchPlan* batch = nullptr;  // prepared batched launch (owned)
+
   rt::Stats stats;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> trace_events, march_events, kappa_events;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> trace_events, march_events, kappa_events,
+      batch_events;
 };
 
 namespace rt {
@@ -130,4 +136,5 @@ hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count,
 hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev);
 hipError_t launch_tally(rt_ctx c);
 hipError_t launch_zero(rt_ctx c);
+void destroy_batch(rt_ctx c);
 }  // namespace rt

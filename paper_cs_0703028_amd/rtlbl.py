@@ -36,10 +36,28 @@ _f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
 class RtStats(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "line_evals", "kappa_ms", "updates", "segments", "trace_ms", "march_ms", "rays",
-        "march_launches")]
+        "march_launches", "batch_line_evals", "batch_updates", "batch_ms")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class RtCase(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("cell_m", C.c_double),
+                ("T_K", C.c_void_p), ("x_h2o", C.c_void_p), ("p_atm", C.c_void_p),
+                ("T_wall_K", C.c_double), ("seed", C.c_uint64), ("n_rays", C.c_uint64)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [(n, C.c_int) for n in ("chunk_points", "kappa_groups", "march_rays",
+                                        "blocks_per_cu", "slots")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{n: int(d[n]) for n, _ in cls._fields_})
 
 
 def _load():
@@ -63,9 +81,20 @@ def _load():
     L.rt_debug_segments.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, _i32p,
                                     _i32p, _f32p, vp, vp]
     L.rt_get_stats.argtypes = [vp, C.POINTER(RtStats)]
+    L.rt_batch_default_tuning.argtypes = [C.POINTER(BatchTuning)]
+    L.rt_batch_workspace_size.argtypes = [vp, C.c_int, C.POINTER(RtCase), C.POINTER(BatchTuning),
+                                          C.POINTER(C.c_int64)]
+    L.rt_batch_prepare.argtypes = [vp, C.c_int, C.POINTER(RtCase), C.c_int,
+                                   C.POINTER(BatchTuning), vp, C.c_int64]
+    L.rt_batch_launch.argtypes = [vp]
+    L.rt_batch_results.argtypes = [vp, vp, vp, vp]
+    L.rt_batch_autotune.argtypes = [vp, C.c_int, C.POINTER(RtCase), C.c_int, vp, C.c_int64,
+                                    C.c_char_p, C.POINTER(BatchTuning)]
     for f in ("rt_create", "rt_destroy", "rt_setup_grid", "rt_setup_lines", "rt_compute_kappa",
               "rt_trace_rays", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
-              "rt_debug_segments", "rt_get_stats"):
+              "rt_debug_segments", "rt_get_stats", "rt_batch_default_tuning",
+              "rt_batch_workspace_size", "rt_batch_prepare", "rt_batch_launch",
+              "rt_batch_results", "rt_batch_autotune"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -208,6 +237,72 @@ class Tracer:
         s = RtStats()
         self._check(lib.rt_get_stats(self._h, C.byref(s)))
         return s.as_dict()
+
+    # -------------------------------------------------------- batched form
+    @staticmethod
+    def _cases(workloads):
+        keep = []
+        arr = (RtCase * len(workloads))()
+        for k, w in enumerate(workloads):
+            g = w.grid
+            T, x, p = _f64(g.T), _f64(g.x), _f64(g.p)
+            keep += [T, x, p]
+            arr[k] = RtCase(g.nx, g.ny, g.nz, g.cell_m, T.ctypes.data, x.ctypes.data,
+                            p.ctypes.data, g.T_wall, w.seed, w.n_rays)
+        return arr, keep
+
+    @staticmethod
+    def default_tuning():
+        t = BatchTuning()
+        lib.rt_batch_default_tuning(C.byref(t))
+        return t
+
+    def batch_workspace_size(self, workloads, tuning=None):
+        arr, keep = self._cases(workloads)
+        n = C.c_int64()
+        self._check(lib.rt_batch_workspace_size(self._h, len(workloads), arr,
+                                                C.byref(tuning) if tuning else None, C.byref(n)))
+        return int(n.value)
+
+    def batch_prepare(self, workloads, kappa_mode=KAPPA_PLAIN, tuning=None, workspace=None):
+        """Copies the cases into a device workspace (a uint8 tensor, allocated
+        here if not given) and builds the launch graph; returns the workspace,
+        which must stay alive while the batch is used."""
+        nbytes = self.batch_workspace_size(workloads, tuning)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        arr, keep = self._cases(workloads)
+        self._check(lib.rt_batch_prepare(self._h, len(workloads), arr, kappa_mode,
+                                         C.byref(tuning) if tuning else None,
+                                         C.c_void_p(workspace.data_ptr()), workspace.numel()))
+        self._batch = ([w.grid.n_cells for w in workloads], workspace)
+        return workspace
+
+    def batch_launch(self):
+        self._check(lib.rt_batch_launch(self._h))
+
+    def batch_results(self):
+        """Per case: (absorbed [cells], emitted [cells], balance [4])."""
+        sizes, _ = self._batch
+        tot = int(sum(sizes))
+        a = np.zeros(tot, np.float64)
+        e = np.zeros(tot, np.float64)
+        b = np.zeros((len(sizes), 4), np.float64)
+        self._check(lib.rt_batch_results(self._h, _ptr(a), _ptr(e), _ptr(b)))
+        out, off = [], 0
+        for k, n in enumerate(sizes):
+            out.append((a[off:off + n], e[off:off + n], b[k]))
+            off += n
+        return out
+
+    def batch_autotune(self, workloads, kappa_mode=KAPPA_PLAIN, workspace=None, cache_path=None):
+        best = BatchTuning()
+        arr, keep = self._cases(workloads)
+        self._check(lib.rt_batch_autotune(self._h, len(workloads), arr, kappa_mode,
+                                          C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                          cache_path.encode() if cache_path else None,
+                                          C.byref(best)))
+        return best
 
     # ------------------------------------------------------------- helpers
     def raw_status(self, name, *args):

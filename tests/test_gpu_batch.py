@@ -1,0 +1,158 @@
+"""GPU tests of the batched form: many receiver cases in one persistent,
+graph-captured launch.
+
+* every case equals its own single-case run (same kernels, only the order
+  of the FP64 accumulations differs): 1e-9 relative per cell;
+* every case matches the FP64 oracle: 1e-5 relative per cell, exact zeros;
+* graph replays with host work in between reproduce the first launch;
+* the autotuner returns a valid tuning, stores it and serves it from the
+  cache, and that tuning reproduces the results.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_cs_0703028_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_cs_0703028_amd import rtlbl
+    return rtlbl
+
+
+def _cases():
+    """Uneven cases sharing one line list (ragged spectral length)."""
+    base = I.small_ragged()
+    L = base.lines
+    ws = []
+    specs = [((5, 6, 7), 0.1, 700, 0.0, 3), ((4, 4, 4), 0.25, 260, 1400.0, 11),
+             ((3, 2, 5), 0.05, 96, 900.0, 5), ((6, 3, 2), 0.15, 1000, 0.0, 8)]
+    for (nx, ny, nz), h, nr, Tw, seed in specs:
+        g = I.linear_T_grid(nx, h, ny=ny, nz=nz, T_lo=320.0 + seed, T_hi=1650.0, x=0.12, p=1.1,
+                            T_wall=Tw)
+        g.x = I.rng(seed, I.STREAM_XH2O).uniform(0.03, 0.25, g.n_cells)
+        ws.append(I.Workload(f"case_{nx}x{ny}x{nz}", g, L, nr, seed))
+    return ws
+
+
+def _rel(g, o):
+    nz = o != 0
+    assert (g[~nz] == 0).all()
+    return np.abs(g[nz] - o[nz]) / np.abs(o[nz])
+
+
+def _single(rt, w):
+    t = rt.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(w.lines)
+    kap, _ = t.alloc_tables()
+    t.compute_kappa(rt.KAPPA_PLAIN, kap, None)
+    t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, rt.TALLY_F32)
+    res = t.tally()
+    t.close()
+    return res
+
+
+def test_batch_matches_single_runs_and_oracle(rt):
+    from oracle import oracle as O
+    cases = _cases()
+    t = rt.Tracer(0)
+    t.setup_lines(cases[0].lines)
+    tun = rt.Tracer.default_tuning()
+    tun.chunk_points = 1024
+    tun.kappa_groups = 2
+    tun.march_rays = 16
+    print("batch prepare", [c.name for c in cases], flush=True)
+    ws = t.batch_prepare(cases, rt.KAPPA_PLAIN, tun)
+    t.batch_launch()
+    out = t.batch_results()
+    st = t.stats()
+    assert st["batch_updates"] > 0 and st["batch_line_evals"] > 0
+    for w, (a, e, b) in zip(cases, out):
+        print("  case", w.name, flush=True)
+        sa, se, sb = _single(rt, w)
+        assert _rel(a, sa).max() <= 1e-9 and _rel(e, se).max() <= 1e-9
+        ref = O.run(w.grid, w.lines, w.n_rays, seed=w.seed)
+        ra, re_ = _rel(a, ref["absorbed"]), _rel(e, ref["emitted"])
+        print(f"    oracle: absorbed max {ra.max():.3e}, emitted max {re_.max():.3e}", flush=True)
+        assert ra.max() <= 1e-5 and re_.max() <= 1e-5
+        for k in range(4):
+            if ref["balance"][k] == 0:
+                assert b[k] == 0
+            else:
+                assert abs(b[k] - ref["balance"][k]) <= 1e-5 * abs(ref["balance"][k])
+    t.close()
+    del ws
+
+
+def test_batch_graph_replays(rt):
+    cases = _cases()[:3]
+    t = rt.Tracer(0)
+    t.setup_lines(cases[0].lines)
+    ws = t.batch_prepare(cases)
+    t.batch_launch()
+    first = t.batch_results()
+    for rep in range(3):
+        # host work and an unrelated device op between replays
+        import torch
+        torch.ones(1000, device="cuda").sum().item()
+        t.batch_launch()
+        again = t.batch_results()
+        for (a0, e0, b0), (a1, e1, b1) in zip(first, again):
+            np.testing.assert_allclose(a1, a0, rtol=1e-12, atol=0)
+            np.testing.assert_allclose(e1, e0, rtol=1e-12, atol=0)
+            np.testing.assert_allclose(b1, b0, rtol=1e-12, atol=0)
+    t.close()
+    del ws
+
+
+def test_batch_autotune_and_cache(rt, tmp_path):
+    import torch
+    cases = _cases()
+    t = rt.Tracer(0)
+    t.setup_lines(cases[0].lines)
+    big = rt.Tracer.default_tuning()
+    big.chunk_points = 4096
+    big.blocks_per_cu = 4
+    nbytes = t.batch_workspace_size(cases, big)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    path = str(tmp_path / "tune.json")
+    print("autotune", flush=True)
+    best = t.batch_autotune(cases, rt.KAPPA_PLAIN, ws, path)
+    d = best.as_dict()
+    assert d["chunk_points"] % 1024 == 0 and d["march_rays"] % 4 == 0 and d["slots"] >= 2
+    assert os.path.exists(path) and '"' in open(path).read()
+    best2 = t.batch_autotune(cases, rt.KAPPA_PLAIN, ws, path)
+    assert best2.as_dict() == d
+    t.batch_prepare(cases, rt.KAPPA_PLAIN, best, ws)
+    t.batch_launch()
+    out = t.batch_results()
+    for w, (a, e, b) in zip(cases[:2], out[:2]):
+        sa, se, sb = _single(rt, w)
+        assert _rel(a, sa).max() <= 1e-9
+    t.close()
+
+
+def test_batch_errors(rt):
+    cases = _cases()[:2]
+    t = rt.Tracer(0)
+    with pytest.raises(rt.RtError) as e:
+        t.batch_prepare(cases)
+    assert e.value.status == rt.RT_ESTATE
+    t.setup_lines(cases[0].lines)
+    bad = rt.Tracer.default_tuning()
+    bad.chunk_points = 1000
+    with pytest.raises(rt.RtError) as e:
+        t.batch_workspace_size(cases, bad)
+    assert e.value.status == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        t.batch_launch()
+    assert e.value.status == rt.RT_ESTATE
+    t.close()
