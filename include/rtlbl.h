@@ -48,8 +48,10 @@ typedef enum {
 } rt_status;
 
 typedef enum {
-  RT_KAPPA_PLAIN = 0,       /* FP32 line sum                                */
-  RT_KAPPA_COMPENSATED = 1  /* FP32 line sum with compensated summation     */
+  RT_KAPPA_PLAIN = 0,        /* FP32 line sum                               */
+  RT_KAPPA_COMPENSATED = 1,  /* FP32 line sum with compensated summation    */
+  RT_KAPPA_SURROGATE = 2     /* learned form (rt_surrogate_train/load), with
+                                line-sum fallback and a sampled check       */
 } rt_kappa_mode;
 
 /* Form of the march (Eq. (3)); per-cell accumulators are FP64 in both.
@@ -246,6 +248,64 @@ rt_status rt_batch_autotune(rt_ctx ctx, int n_cases, const rt_case* cases,
                             int kappa_mode, void* workspace_dev,
                             int64_t workspace_bytes, const char* cache_path,
                             rt_batch_tuning* best);
+
+
+/* ------------------------------------------------------------------------
+ * Learned form: an MLP 4 -> 512 -> 512 -> 512 -> 256 (SiLU, BF16 weights,
+ * FP32 accumulation on MFMA) maps (T, x_H2O, p, spectral-chunk index) to
+ * the 256 values of ln(kappa/u) of a 256-point chunk, each output
+ * normalised over the training spectra.  It is trained on spectra of the
+ * exact line sum (Eqs. (1)-(2)) for the current line list and spectral
+ * grid.  rt_compute_kappa in RT_KAPPA_SURROGATE mode fills the kappa table
+ * from it, recomputes with the line sum every cell outside the training
+ * box, checks every chunk against the line sum on `check_cells` sampled
+ * cells and recomputes the whole chunk for all cells when the relative error
+ * of the chunk's absorptance along one cell edge h,
+ * |sum (a_mlp - a)| / sum a with a = 1 - exp(-kappa h), exceeds `tolerance`.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int n_samples;              /* training gas states (>= 64)               */
+  const double* T_K;          /* host arrays of n_samples states           */
+  const double* x_h2o;
+  const double* p_atm;
+  double T_min, T_max;        /* validity box of the surrogate             */
+  double x_min, x_max;
+  double p_min, p_max;
+  int epochs;                 /* passes over the (sample, chunk) rows      */
+  int batch;                  /* rows per Adam step, multiple of 64        */
+  float lr;                   /* initial Adam step (cosine decay)          */
+  uint64_t seed;              /* weight initialisation and shuffling       */
+  int check_cells;            /* cells sampled per inference check (>= 0)  */
+  double tolerance;           /* checked absorptance error for fallback    */
+} rt_surrogate_cfg;
+
+typedef struct {
+  double check_error;         /* largest checked chunk error, last inference */
+  int fallback_chunks;        /* chunks recomputed with the line sum         */
+  int fallback_cells;         /* out-of-range cells recomputed               */
+  int n_chunks;
+  double infer_ms, check_ms, fallback_ms;  /* device times, last inference   */
+  double train_loss;          /* mean squared normalised error, last epoch   */
+  double param_count;
+} rt_surrogate_stats;
+
+/* Trains a new surrogate for the current line list and spectral grid
+ * (replaces any previous one).  final_loss may be NULL. */
+rt_status rt_surrogate_train(rt_ctx ctx, const rt_surrogate_cfg* cfg, double* final_loss);
+
+/* Versioned binary blob with an FNV-1a checksum; load validates it. */
+rt_status rt_surrogate_save(rt_ctx ctx, const char* path);
+rt_status rt_surrogate_load(rt_ctx ctx, const char* path);
+
+/* Raw network outputs (normalised ln(kappa/u)) for n_rows host input rows of
+ * 4 normalised features each; outputs: host n_rows * 256 floats.  Synchronous. */
+rt_status rt_surrogate_forward(rt_ctx ctx, int n_rows, const float* inputs, float* outputs);
+
+/* FP32 master parameters W1 [4][512], b1, W2 [512][512], b2, W3, b3,
+ * W4 [512][256], b4 (row-major [in][out]) into a host array of n floats. */
+rt_status rt_surrogate_weights(rt_ctx ctx, float* out, int64_t n);
+
+rt_status rt_surrogate_get_stats(rt_ctx ctx, rt_surrogate_stats* out);
 
 #ifdef __cplusplus
 }

@@ -174,6 +174,7 @@ rt_status rt_destroy(rt_ctx c) {
   free_events(c->trace_events); free_events(c->march_events); free_events(c->kappa_events);
   free_events(c->batch_events);
   rt::destroy_batch(c);
+  rt::free_surrogate(c);
   delete c;
   return RT_OK;
 }
@@ -347,8 +348,11 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   if (!c) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL handle");
   if (!c->have_grid || !c->have_lines)
     return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_setup_grid and rt_setup_lines first");
-  if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED)
+  if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED && mode != RT_KAPPA_SURROGATE)
     return fail(c, RT_EINVAL, "rt_compute_kappa: unknown mode");
+  if (mode == RT_KAPPA_SURROGATE &&
+      (!c->surrogate || !rt::surrogate_ready(c)))
+    return fail(c, RT_ESTATE, "rt_compute_kappa: no trained surrogate for this spectral grid");
   if (!kappa_dev) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL kappa buffer");
   if (ld < rt_required_pitch(c) || ld % rt::kChunk != 0)
     return fail(c, RT_EINVAL, "rt_compute_kappa: ld must be a multiple of the march chunk (rt_required_pitch) and >= it");
@@ -369,10 +373,14 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     RT_HIP(c, rt::launch_cell_params(c));
     c->cells_valid = true;
   }
-  RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
+  if (mode == RT_KAPPA_SURROGATE) {
+    if (rt_status s = rt::surrogate_kappa(c)) return s;
+  } else {
+    RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
+  }
   if (rt_status s = record_end(c, c->kappa_events)) return s;
   RT_HIP(c, rt::launch_planck(c));  // wall row always; cell table if requested
-  c->stats.line_evals += c->line_evals_per_cell * (double)c->n_cells;
+  if (mode != RT_KAPPA_SURROGATE) c->stats.line_evals += c->line_evals_per_cell * (double)c->n_cells;
   c->have_kappa = true;
   return RT_OK;
 }

@@ -99,6 +99,8 @@ struct KappaTile {
   int64_t ld_out;
   int64_t col0;
   int64_t col_end;
+  const int32_t* cell_list = nullptr;  // logical cell i -> cell_list[i] when set
+  int compact_rows = 0;                // with a list: write row i instead of cell_list[i]
 };
 
 template <bool COMP>
@@ -137,6 +139,7 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
       const int i = base + li;
       int64_t cell = cell0 + cc;
       if (cell >= a.n_cells) cell = a.n_cells - 1;
+      if (a.cell_list) cell = a.cell_list[cell];
       float* rec = lds + li * REC;
       if (cc == 0) {
         rec[0] = (float)a.L.m[i];
@@ -198,8 +201,9 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
 
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const int64_t cell = cell0 + c;
+    int64_t cell = cell0 + c;
     if (cell >= a.n_cells) break;
+    if (a.cell_list && !a.compact_rows) cell = a.cell_list[cell];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int64_t j = wj0 + 64 * p + lane;

@@ -37,6 +37,7 @@ __global__ void cell_params_kernel(int64_t n, const double* __restrict__ T,
 struct KappaArgs {
   KappaTile t;
   int n_tiles;
+  int tile_begin;
 };
 
 template <bool COMP>
@@ -44,7 +45,8 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs 
   __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
   const int tile = blockIdx.x % a.n_tiles;
   const int64_t cg = blockIdx.x / a.n_tiles;
-  kappa_tile<COMP>(a.t, tile * kKappaTilePoints, cg * kKappaCells, reinterpret_cast<float*>(lds4));
+  kappa_tile<COMP>(a.t, (a.tile_begin + tile) * kKappaTilePoints, cg * kKappaCells,
+                   reinterpret_cast<float*>(lds4));
 }
 
 // Eq. (4): B = c1 nu^3 / (exp(c2 nu / T) - 1), evaluated in FP64 and stored
@@ -114,6 +116,7 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
   a.t.col0 = 0;
   a.t.col_end = c->ld;
   a.n_tiles = (int)((c->ld + kKappaTilePoints - 1) / kKappaTilePoints);
+  a.tile_begin = 0;
   const int64_t groups = (c->n_cells + kKappaCells - 1) / kKappaCells;
   const int64_t blocks = groups * a.n_tiles;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -123,6 +126,24 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
   else
     hipLaunchKernelGGL((kappa_linesum_kernel<false>), dim3((unsigned)blocks), dim3(kKappaThreads),
                        0, c->stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kappa_tiles(rt_ctx c, const KappaTile& t, int64_t n_cell_groups,
+                              int tile_begin, int n_tiles, bool comp, hipStream_t s) {
+  KappaArgs a;
+  a.t = t;
+  a.n_tiles = n_tiles;
+  a.tile_begin = tile_begin;
+  const int64_t blocks = n_cell_groups * n_tiles;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (blocks == 0) return hipSuccess;
+  if (comp)
+    hipLaunchKernelGGL((kappa_linesum_kernel<true>), dim3((unsigned)blocks), dim3(kKappaThreads),
+                       0, s, a);
+  else
+    hipLaunchKernelGGL((kappa_linesum_kernel<false>), dim3((unsigned)blocks), dim3(kKappaThreads),
+                       0, s, a);
   return hipGetLastError();
 }
 

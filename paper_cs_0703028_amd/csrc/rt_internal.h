@@ -65,6 +65,7 @@ struct Stats {
 };
 
 struct BatchPlan;
+struct Surrogate;
 }  // namespace rt
 
 struct rt_ctx_s {
@@ -118,6 +119,7 @@ struct rt_ctx_s {
   int64_t exit_cap = 0;
 
   rt::BatchPlan* batch = nullptr;  // prepared batched launch (owned)
+  rt::Surrogate* surrogate = nullptr;  // learned form (owned)
 
   rt::Stats stats;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> trace_events, march_events, kappa_events,
@@ -137,4 +139,7 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float
 hipError_t launch_tally(rt_ctx c);
 hipError_t launch_zero(rt_ctx c);
 void destroy_batch(rt_ctx c);
+void free_surrogate(rt_ctx c);
+rt_status surrogate_kappa(rt_ctx c);
+bool surrogate_ready(rt_ctx c);
 }  // namespace rt

@@ -1,0 +1,45 @@
+// surrogate.h -- state of the learned form: an MLP (T, x, p, chunk) -> 256
+// values of ln(kappa/u) per spectral chunk, BF16 weights on MFMA with FP32
+// accumulation, trained on line-sum spectra.
+#pragma once
+
+#include "rt_internal.h"
+
+namespace rt {
+
+typedef __bf16 bf16;
+
+constexpr int kMlpLayers = 4;
+constexpr int kMlpWidth = 256;                         // outputs per chunk
+constexpr int kMlpDims[kMlpLayers + 1] = {4, 512, 512, 512, 256};
+
+struct Surrogate {
+  bool trained = false;
+  int n_nu = 0, n_chunks = 0;
+  double T_min = 0, T_max = 0, x_min = 0, x_max = 0, p_min = 0, p_max = 0;
+  int check_cells = 8;
+  double tolerance = 1e-3;
+  uint64_t check_seed = 0;
+  // parameters: FP32 masters W_l [K][N] and b_l [N]; Adam moments; BF16
+  // copies for the forward GEMM ([N][K]) and for the input gradient ([K][N])
+  float* w[kMlpLayers] = {};
+  float* b[kMlpLayers] = {};
+  float* mw[kMlpLayers] = {};
+  float* vw[kMlpLayers] = {};
+  float* mb[kMlpLayers] = {};
+  float* vb[kMlpLayers] = {};
+  bf16* wt[kMlpLayers] = {};
+  bf16* wk[kMlpLayers] = {};
+  float* mean = nullptr;  // [n_chunks][256] normalisation of the targets
+  float* stdv = nullptr;
+  // last inference
+  double check_error = 0;       // largest checked relative L1 error of a chunk
+  int fallback_chunks = 0;      // chunks recomputed with the line sum
+  int fallback_cells = 0;       // out-of-range cells recomputed
+  double infer_ms = 0, check_ms = 0, fallback_ms = 0;
+  double train_loss = 0;
+  int64_t param_count = 0;
+};
+
+
+}  // namespace rt

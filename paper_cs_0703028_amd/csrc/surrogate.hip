@@ -1,0 +1,1039 @@
+// surrogate.hip -- learned form of the line sum (gfx950).
+//
+// An MLP 4 -> 512 -> 512 -> 512 -> 256 (SiLU) maps the gas state and a
+// spectral-chunk index, (T, x_H2O, p, k), encoded as (1/T, x, ln p, k), to
+// the 256 values of
+// ln(kappa / u) on chunk k, each output normalised by its mean and standard
+// deviation over the training spectra; kappa = u exp(mean + std * y).
+// Weights are BF16, products accumulate in FP32 on MFMA
+// (v_mfma_f32_32x32x16_bf16); the first layer (K = 4) runs on the VALU.
+// Training data are spectra of the exact line sum (the same kernel as
+// rt_compute_kappa) for caller-supplied gas states; training is plain Adam
+// on the mean squared error of the normalised outputs, one training step
+// captured in a HIP graph and replayed.
+//
+// Inference fills the kappa table; cells outside the training box are
+// recomputed with the line sum; every chunk is checked against the line
+// sum on a few sampled cells and recomputed for all cells when its relative
+// L1 error exceeds the tolerance.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+#include "surrogate.h"
+
+namespace rt {
+
+hipError_t launch_kappa_tiles(rt_ctx c, const dev::KappaTile& t, int64_t n_cell_groups,
+                              int tile_begin, int n_tiles, bool comp, hipStream_t s);
+hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const double* x,
+                                 const double* p, const CellSet& cells, hipStream_t s);
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ------------------------------------------------------------------ GEMM
+// C[m][n] = sum_r A[m][r] B[n][r] (both operands contiguous along r), FP32
+// out.  Block = 4 wavefronts = 64 x 64 outputs, each wavefront a 32 x 32
+// MFMA tile; operands are read straight from global memory (the layers are
+// small and stay in L2).  M, N multiples of 64, R of 16.
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const bf16* __restrict__ A, int lda,
+                                                      const bf16* __restrict__ B, int ldb,
+                                                      float* __restrict__ C, int ldc, int R) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const bf16* a = A + (size_t)(m0 + (lane & 31)) * lda + (lane >> 5) * 8;
+  const bf16* b = B + (size_t)(n0 + (lane & 31)) * ldb + (lane >> 5) * 8;
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int r = 0; r < R; r += 16) {
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + r);
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + r);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = m0 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    C[(size_t)row * ldc + n0 + (lane & 31)] = acc[i];
+  }
+}
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Z = X0 W1 + b1 (K = 4, FP32 with BF16-rounded weights); H = SiLU(Z).
+__global__ void layer1_kernel(const float* __restrict__ X0, const bf16* __restrict__ W1k,
+                              const float* __restrict__ b1, int M, float* Z, bf16* H, bf16* HT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = kMlpDims[1];
+  if (i >= (int64_t)M * N) return;
+  const int m = (int)(i / N), n = (int)(i % N);
+  float z = b1[n];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z = fmaf(X0[4 * m + k], (float)W1k[k * N + n], z);
+  const float h = z * sigmoid(z);
+  if (Z) Z[i] = z;
+  H[i] = (bf16)h;
+  if (HT) HT[(int64_t)n * M + m] = (bf16)h;
+}
+
+// Z = C + b; H = SiLU(Z) (BF16, optionally transposed too); Z kept in C.
+__global__ void bias_act_kernel(float* __restrict__ C, const float* __restrict__ b, int M, int N,
+                                bf16* H, bf16* HT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int m = (int)(i / N), n = (int)(i % N);
+  const float z = C[i] + b[n];
+  C[i] = z;
+  const float h = z * sigmoid(z);
+  H[i] = (bf16)h;
+  if (HT) HT[(int64_t)n * M + m] = (bf16)h;
+}
+
+__global__ void bias_kernel(float* __restrict__ C, const float* __restrict__ b, int M, int N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  C[i] += b[i % N];
+}
+
+// dP = 2 (P - Y) / (M 256) on valid outputs (0 beyond n_nu); squared error
+// accumulated in FP64.
+__global__ void loss_grad_kernel(const float* __restrict__ P, const float* __restrict__ Y,
+                                 const int32_t* __restrict__ row_chunk, int M, int n_nu,
+                                 bf16* dP, bf16* dPT, double* sse) {
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e2 = 0;
+  if (i < (int64_t)M * kMlpWidth) {
+    const int m = (int)(i / kMlpWidth), n = (int)(i % kMlpWidth);
+    const bool valid = (int64_t)row_chunk[m] * kMlpWidth + n < n_nu;
+    const float d = valid ? P[i] - Y[i] : 0.f;
+    e2 = (double)d * d;
+    const float g = 2.0f * d / ((float)M * kMlpWidth);
+    dP[i] = (bf16)g;
+    dPT[(int64_t)n * M + m] = (bf16)g;
+  }
+  red[threadIdx.x] = e2;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) unsafeAtomicAdd(sse, red[0]);
+}
+
+// dZ = dH * SiLU'(Z); BF16 (and transposed) or FP32 output.
+__global__ void act_bwd_kernel(const float* __restrict__ dH, const float* __restrict__ Z, int M,
+                               int N, bf16* dZ, bf16* dZT, float* dZf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int m = (int)(i / N), n = (int)(i % N);
+  const float z = Z[i];
+  const float s = sigmoid(z);
+  const float g = dH[i] * s * (1.0f + z * (1.0f - s));
+  if (dZf) dZf[i] = g;
+  if (dZ) dZ[i] = (bf16)g;
+  if (dZT) dZT[(int64_t)n * M + m] = (bf16)g;
+}
+
+// db[n] = sum_m G[m][n] (FP32 or BF16 source): block (64 columns, 256 rows),
+// 4 row groups per block reduced in LDS, one atomic per column and block;
+// db must be zero on entry.
+template <class T>
+__global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ G, int M, int N,
+                                                     float* db) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int m0 = blockIdx.y * 256;
+  float s = 0.f;
+  if (n < N)
+    for (int m = m0 + g; m < min(m0 + 256, M); m += 4) s += (float)G[(int64_t)m * N + n];
+  red[g][c] = s;
+  __syncthreads();
+  if (g == 0 && n < N) atomicAdd(db + n, red[0][c] + red[1][c] + red[2][c] + red[3][c]);
+}
+
+// dW1[k][n] = sum_m X0[m][k] dZ1[m][n] and db1[n] = sum_m dZ1[m][n], same
+// decomposition as colsum_kernel; outputs must be zero on entry.
+__global__ __launch_bounds__(256) void layer1_wgrad_kernel(const float* __restrict__ X0,
+                                                           const float* __restrict__ dZ1, int M,
+                                                           float* dW1, float* db1) {
+  __shared__ float red[5][4][64];
+  const int N = kMlpDims[1];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int m0 = blockIdx.y * 256;
+  float s[5] = {0, 0, 0, 0, 0};
+  for (int m = m0 + g; m < min(m0 + 256, M); m += 4) {
+    const float d = dZ1[(int64_t)m * N + n];
+    for (int k = 0; k < 4; ++k) s[k] = fmaf(X0[4 * m + k], d, s[k]);
+    s[4] += d;
+  }
+  for (int q = 0; q < 5; ++q) red[q][g][c] = s[q];
+  __syncthreads();
+  if (g == 0) {
+    for (int k = 0; k < 4; ++k)
+      atomicAdd(dW1 + k * N + n, red[k][0][c] + red[k][1][c] + red[k][2][c] + red[k][3][c]);
+    atomicAdd(db1 + n, red[4][0][c] + red[4][1][c] + red[4][2][c] + red[4][3][c]);
+  }
+}
+
+__global__ void zero_f32_kernel(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// Adam on W [K][N] (gradient given either as [K][N] or transposed [N][K])
+// and its bias; refreshes the BF16 copies [N][K] and [K][N].  Cosine decay
+// of the learning rate over total_steps.
+__global__ void adam_kernel(float* W, float* mW, float* vW, const float* __restrict__ g,
+                            int g_transposed, float* b, float* mb, float* vb,
+                            const float* __restrict__ gb, int K, int N, const int* step,
+                            int total_steps, float lr0, bf16* Wt, bf16* Wk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int t = *step + 1;
+  const float lr = lr0 * 0.5f * (1.0f + cospif(fminf((float)(t - 1) / (float)total_steps, 1.0f)));
+  const float c1 = 1.0f / (1.0f - powf(b1, (float)t)), c2 = 1.0f / (1.0f - powf(b2, (float)t));
+  if (i < (int64_t)K * N) {
+    const int k = (int)(i / N), n = (int)(i % N);
+    const float gi = g_transposed ? g[(int64_t)n * K + k] : g[i];
+    const float m = b1 * mW[i] + (1 - b1) * gi;
+    const float v = b2 * vW[i] + (1 - b2) * gi * gi;
+    mW[i] = m;
+    vW[i] = v;
+    const float w = W[i] - lr * (m * c1) / (sqrtf(v * c2) + eps);
+    W[i] = w;
+    Wt[(int64_t)n * K + k] = (bf16)w;
+    Wk[i] = (bf16)w;
+  }
+  if (i < N) {
+    const float m = b1 * mb[i] + (1 - b1) * gb[i];
+    const float v = b2 * vb[i] + (1 - b2) * gb[i] * gb[i];
+    mb[i] = m;
+    vb[i] = v;
+    b[i] -= lr * (m * c1) / (sqrtf(v * c2) + eps);
+  }
+}
+
+__global__ void step_kernel(int* step) { *step += 1; }
+
+__global__ void to_bf16_kernel(const float* __restrict__ W, int K, int N, bf16* Wt, bf16* Wk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)K * N) return;
+  const int k = (int)(i / N), n = (int)(i % N);
+  Wt[(int64_t)n * K + k] = (bf16)W[i];
+  Wk[i] = (bf16)W[i];
+}
+
+// Input encoding: 1/T, x and ln p, each mapped linearly onto [-1, 1] over
+// the training box, and the chunk index onto [-1, 1].  ln(kappa/u) is close
+// to linear in 1/T (Boltzmann factor of Eq. (1)) and in ln p (half widths).
+struct Box { float T0, Ts, x0, xs, p0, ps; int n_chunks; };
+
+__device__ __forceinline__ void features(const Box& bx, double T, double x, double p, int k,
+                                         float* f) {
+  f[0] = ((float)(1.0 / T) - bx.T0) * bx.Ts;
+  f[1] = ((float)x - bx.x0) * bx.xs;
+  f[2] = ((float)log(p) - bx.p0) * bx.ps;
+  f[3] = bx.n_chunks > 1 ? 2.0f * k / (float)(bx.n_chunks - 1) - 1.0f : 0.0f;
+}
+
+// Training batch: rows perm[step*M .. +M) of the (sample, chunk) table.
+__global__ void gather_kernel(const int32_t* __restrict__ perm, const int* step, int64_t n_rows,
+                              int M, const double* __restrict__ T, const double* __restrict__ x,
+                              const double* __restrict__ p, Box bx,
+                              const float* __restrict__ Yall, int64_t ld_s, float* X0,
+                              float* Y, int32_t* row_chunk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * kMlpWidth) return;
+  const int m = (int)(i / kMlpWidth), n = (int)(i % kMlpWidth);
+  const int64_t row = perm[((int64_t)*step * M + m) % n_rows];
+  const int64_t s = row / bx.n_chunks;
+  const int k = (int)(row % bx.n_chunks);
+  Y[i] = Yall[s * ld_s + (int64_t)k * kMlpWidth + n];
+  if (n == 0) {
+    float f[4];
+    features(bx, T[s], x[s], p[s], k, f);
+    for (int q = 0; q < 4; ++q) X0[4 * m + q] = f[q];
+    row_chunk[m] = k;
+  }
+}
+
+// Inference rows: row = cell * n_chunks + k.
+__global__ void infer_features_kernel(const double* __restrict__ T, const double* __restrict__ x,
+                                      const double* __restrict__ p, int64_t n_cells, Box bx,
+                                      int M, float* X0) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= M) return;
+  float f[4] = {0, 0, 0, 0};
+  if (row < n_cells * bx.n_chunks) {
+    const int64_t cell = row / bx.n_chunks;
+    features(bx, T[cell], x[cell], p[cell], (int)(row % bx.n_chunks), f);
+  }
+  for (int q = 0; q < 4; ++q) X0[4 * row + q] = f[q];
+}
+
+__device__ __forceinline__ double gas_density(double T, double x, double p) {
+  return x * p * kAtm / (kBoltzmann * T) * 1e-6;
+}
+
+// kappa[cell][k*256 + i] = u exp(mean + std * y), 0 beyond n_nu.
+__global__ void infer_kappa_kernel(const float* __restrict__ P, const float* __restrict__ mean,
+                                   const float* __restrict__ stdv, const double* __restrict__ T,
+                                   const double* __restrict__ x, const double* __restrict__ p,
+                                   int64_t n_cells, int n_chunks, int n_nu, int64_t ld,
+                                   float* kappa) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cells * ld) return;
+  const int64_t cell = i / ld, j = i % ld;
+  float v = 0.f;
+  if (j < n_nu) {
+    const int k = (int)(j / kMlpWidth), o = (int)(j % kMlpWidth);
+    const int64_t row = cell * n_chunks + k;
+    const float y = mean[k * kMlpWidth + o] + stdv[k * kMlpWidth + o] * P[row * kMlpWidth + o];
+    v = (float)(gas_density(T[cell], x[cell], p[cell]) * exp((double)y));
+  }
+  kappa[i] = v;
+}
+
+// Targets: y = ln(kappa / u) in place over the sample table; tiny floor.
+__global__ void log_target_kernel(float* K, int64_t n_samples, int64_t ld_s, int n_nu,
+                                  const double* __restrict__ T, const double* __restrict__ x,
+                                  const double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_samples * ld_s) return;
+  const int64_t s = i / ld_s, j = i % ld_s;
+  if (j >= n_nu) { K[i] = 0.f; return; }
+  const double u = gas_density(T[s], x[s], p[s]);
+  K[i] = (float)log(fmax((double)K[i] / u, 1e-45));
+}
+
+// mean and std per column over samples (FP64 sums), then normalise in place.
+__global__ void col_stats_kernel(const float* __restrict__ Y, int64_t n_samples, int64_t ld_s,
+                                 int n_cols, float* mean, float* stdv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_cols) return;
+  double s = 0, s2 = 0;
+  for (int64_t r = 0; r < n_samples; ++r) {
+    const double v = Y[r * ld_s + j];
+    s += v;
+    s2 += v * v;
+  }
+  const double m = s / n_samples;
+  const double var = fmax(s2 / n_samples - m * m, 0.0);
+  mean[j] = (float)m;
+  stdv[j] = (float)fmax(sqrt(var), 1e-3);
+}
+
+__global__ void normalize_kernel(float* Y, int64_t n_samples, int64_t ld_s, int n_cols,
+                                 const float* __restrict__ mean, const float* __restrict__ stdv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_samples * ld_s) return;
+  const int j = (int)(i % ld_s);
+  if (j < n_cols) Y[i] = (Y[i] - mean[j]) / stdv[j];
+}
+
+// out-of-range cells -> list
+__global__ void range_kernel(const double* __restrict__ T, const double* __restrict__ x,
+                             const double* __restrict__ p, int64_t n, double T0, double T1,
+                             double x0, double x1, double p0, double p1, int32_t* list,
+                             unsigned* count) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const bool in = T[c] >= T0 && T[c] <= T1 && x[c] >= x0 && x[c] <= x1 && p[c] >= p0 && p[c] <= p1;
+  if (!in) list[atomicAdd(count, 1u)] = (int32_t)c;
+}
+
+// per chunk: the relative error of the chunk's absorptance over the sampled
+// cells, |sum (a_mlp - a)| / sum a with a = 1 - exp(-kappa l) along one
+// cell edge l -- the quantity the absorbed and emitted power are linear in
+// for thin points and saturate in for thick ones.
+__global__ void check_kernel(const float* __restrict__ kappa, int64_t ld,
+                             const float* __restrict__ exact, int64_t ld_e,
+                             const int32_t* __restrict__ cells, int n_check, int n_nu,
+                             double l_cm, double* err) {
+  const int k = blockIdx.x;  // chunk
+  __shared__ double rd[256], rs[256];
+  double d = 0, s = 0;
+  for (int q = threadIdx.x; q < n_check * kMlpWidth; q += blockDim.x) {
+    const int ci = q / kMlpWidth, o = q % kMlpWidth;
+    const int64_t j = (int64_t)k * kMlpWidth + o;
+    if (j >= n_nu) continue;
+    const double e = -expm1(-(double)exact[(int64_t)ci * ld_e + j] * l_cm);
+    const double g = -expm1(-(double)kappa[(int64_t)cells[ci] * ld + j] * l_cm);
+    d += g - e;
+    s += e;
+  }
+  rd[threadIdx.x] = d;
+  rs[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) { rd[threadIdx.x] += rd[threadIdx.x + off]; rs[threadIdx.x] += rs[threadIdx.x + off]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) err[k] = rs[0] > 0 ? fabs(rd[0]) / rs[0] : (rd[0] != 0 ? 1e30 : 0.0);
+}
+
+int64_t grid1(int64_t n) { return (n + 255) / 256; }
+
+// deterministic 64-bit generator for weight init and shuffles (splitmix64)
+struct SplitMix {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+rt_status sfail(rt_ctx c, rt_status s, const std::string& m) {
+  c->err = m;
+  return s;
+}
+
+#define RT_SHIP(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return sfail(ctx, (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE,           \
+                   std::string(#call) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, int64_t n) {
+  *p = nullptr;
+  return hipMalloc(reinterpret_cast<void**>(p), (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+}
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+rt_status alloc_params(rt_ctx c, Surrogate& S) {
+  S.param_count = 0;
+  for (int l = 0; l < kMlpLayers; ++l) {
+    const int K = kMlpDims[l], N = kMlpDims[l + 1];
+    RT_SHIP(c, dalloc(&S.w[l], (int64_t)K * N));
+    RT_SHIP(c, dalloc(&S.b[l], N));
+    RT_SHIP(c, dalloc(&S.mw[l], (int64_t)K * N));
+    RT_SHIP(c, dalloc(&S.vw[l], (int64_t)K * N));
+    RT_SHIP(c, dalloc(&S.mb[l], N));
+    RT_SHIP(c, dalloc(&S.vb[l], N));
+    RT_SHIP(c, dalloc(&S.wt[l], (int64_t)K * N));
+    RT_SHIP(c, dalloc(&S.wk[l], (int64_t)K * N));
+    S.param_count += (int64_t)K * N + N;
+  }
+  RT_SHIP(c, dalloc(&S.mean, (int64_t)S.n_chunks * kMlpWidth));
+  RT_SHIP(c, dalloc(&S.stdv, (int64_t)S.n_chunks * kMlpWidth));
+  return RT_OK;
+}
+
+// Activation buffers for M rows.
+struct Acts {
+  int M = 0;
+  float *X0 = nullptr, *Z[3] = {}, *P = nullptr, *Y = nullptr, *dH = nullptr, *dZ1 = nullptr;
+  bf16 *H[3] = {}, *HT[3] = {}, *dP = nullptr, *dPT = nullptr, *dZ[3] = {}, *dZT[3] = {};
+  float *gW[kMlpLayers] = {}, *gb[kMlpLayers] = {};
+  int32_t* row_chunk = nullptr;
+  double* sse = nullptr;
+  int* step = nullptr;
+  void release() {
+    dfree(X0); dfree(P); dfree(Y); dfree(dH); dfree(dZ1); dfree(dP); dfree(dPT);
+    for (int l = 0; l < 3; ++l) { dfree(Z[l]); dfree(H[l]); dfree(HT[l]); dfree(dZ[l]); dfree(dZT[l]); }
+    for (int l = 0; l < kMlpLayers; ++l) { dfree(gW[l]); dfree(gb[l]); }
+    dfree(row_chunk); dfree(sse); dfree(step);
+  }
+};
+
+rt_status alloc_acts(rt_ctx c, Acts& a, int M, bool train) {
+  a.M = M;
+  const int W = 512;
+  RT_SHIP(c, dalloc(&a.X0, (int64_t)M * 4));
+  RT_SHIP(c, dalloc(&a.P, (int64_t)M * kMlpWidth));
+  for (int l = 0; l < 3; ++l) {
+    RT_SHIP(c, dalloc(&a.Z[l], (int64_t)M * W));
+    RT_SHIP(c, dalloc(&a.H[l], (int64_t)M * W));
+  }
+  if (!train) return RT_OK;
+  RT_SHIP(c, dalloc(&a.Y, (int64_t)M * kMlpWidth));
+  RT_SHIP(c, dalloc(&a.dH, (int64_t)M * W));
+  RT_SHIP(c, dalloc(&a.dZ1, (int64_t)M * W));
+  RT_SHIP(c, dalloc(&a.dP, (int64_t)M * kMlpWidth));
+  RT_SHIP(c, dalloc(&a.dPT, (int64_t)M * kMlpWidth));
+  for (int l = 0; l < 3; ++l) {
+    RT_SHIP(c, dalloc(&a.HT[l], (int64_t)M * W));
+    RT_SHIP(c, dalloc(&a.dZ[l], (int64_t)M * W));
+    RT_SHIP(c, dalloc(&a.dZT[l], (int64_t)M * W));
+  }
+  for (int l = 0; l < kMlpLayers; ++l) {
+    RT_SHIP(c, dalloc(&a.gW[l], (int64_t)kMlpDims[l] * kMlpDims[l + 1]));
+    RT_SHIP(c, dalloc(&a.gb[l], kMlpDims[l + 1]));
+  }
+  RT_SHIP(c, dalloc(&a.row_chunk, M));
+  RT_SHIP(c, dalloc(&a.sse, 1));
+  RT_SHIP(c, dalloc(&a.step, 1));
+  return RT_OK;
+}
+
+void gemm(const bf16* A, int lda, const bf16* B, int ldb, float* C, int ldc, int M, int N, int R,
+          hipStream_t s) {
+  hipLaunchKernelGGL(gemm_nt_kernel, dim3(N / 64, M / 64), dim3(256), 0, s, A, lda, B, ldb, C,
+                     ldc, R);
+}
+
+// forward pass over a.M rows (X0 filled); train: keep transposes
+void forward(const Surrogate& S, Acts& a, bool train, hipStream_t s) {
+  const int M = a.M, W = 512;
+  hipLaunchKernelGGL(layer1_kernel, dim3(grid1((int64_t)M * W)), dim3(256), 0, s, a.X0, S.wk[0],
+                     S.b[0], M, a.Z[0], a.H[0], train ? a.HT[0] : nullptr);
+  for (int l = 1; l <= 2; ++l) {
+    gemm(a.H[l - 1], W, S.wt[l], W, a.Z[l], W, M, W, W, s);
+    hipLaunchKernelGGL(bias_act_kernel, dim3(grid1((int64_t)M * W)), dim3(256), 0, s, a.Z[l],
+                       S.b[l], M, W, a.H[l], train ? a.HT[l] : nullptr);
+  }
+  gemm(a.H[2], W, S.wt[3], W, a.P, kMlpWidth, M, kMlpWidth, W, s);
+  hipLaunchKernelGGL(bias_kernel, dim3(grid1((int64_t)M * kMlpWidth)), dim3(256), 0, s, a.P,
+                     S.b[3], M, kMlpWidth);
+}
+
+void colsum_bf16(const bf16* G, int M, int N, float* db, hipStream_t s) {
+  hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(N)), dim3(256), 0, s, db, (int64_t)N);
+  hipLaunchKernelGGL(colsum_kernel<bf16>, dim3((N + 63) / 64, (M + 255) / 256), dim3(256), 0, s,
+                     G, M, N, db);
+}
+
+void backward(const Surrogate& S, Acts& a, hipStream_t s) {
+  const int M = a.M, W = 512, O = kMlpWidth;
+  // layer 4: dW4^T [256][512] = dP^T H3^T^T ; dH3 = dP W4
+  gemm(a.dPT, M, a.HT[2], M, a.gW[3], W, O, W, M, s);
+  colsum_bf16(a.dP, M, O, a.gb[3], s);
+  gemm(a.dP, O, S.wk[3], O, a.dH, W, M, W, O, s);
+  for (int l = 2; l >= 1; --l) {  // hidden layers 3 and 2
+    hipLaunchKernelGGL(act_bwd_kernel, dim3(grid1((int64_t)M * W)), dim3(256), 0, s, a.dH,
+                       a.Z[l], M, W, a.dZ[l], a.dZT[l], (float*)nullptr);
+    gemm(a.dZT[l], M, a.HT[l - 1], M, a.gW[l], W, W, W, M, s);
+    colsum_bf16(a.dZ[l], M, W, a.gb[l], s);
+    gemm(a.dZ[l], W, S.wk[l], W, a.dH, W, M, W, W, s);
+  }
+  hipLaunchKernelGGL(act_bwd_kernel, dim3(grid1((int64_t)M * W)), dim3(256), 0, s, a.dH, a.Z[0],
+                     M, W, (bf16*)nullptr, (bf16*)nullptr, a.dZ1);
+  hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(4 * W)), dim3(256), 0, s, a.gW[0], (int64_t)4 * W);
+  hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(W)), dim3(256), 0, s, a.gb[0], (int64_t)W);
+  hipLaunchKernelGGL(layer1_wgrad_kernel, dim3(W / 64, (M + 255) / 256), dim3(256), 0, s, a.X0,
+                     a.dZ1, M, a.gW[0], a.gb[0]);
+}
+
+void adam(Surrogate& S, Acts& a, int total_steps, float lr, hipStream_t s) {
+  for (int l = 0; l < kMlpLayers; ++l) {
+    const int K = kMlpDims[l], N = kMlpDims[l + 1];
+    hipLaunchKernelGGL(adam_kernel, dim3(grid1((int64_t)K * N)), dim3(256), 0, s, S.w[l],
+                       S.mw[l], S.vw[l], a.gW[l], l == 0 ? 0 : 1, S.b[l], S.mb[l], S.vb[l],
+                       a.gb[l], K, N, a.step, total_steps, lr, S.wt[l], S.wk[l]);
+  }
+  hipLaunchKernelGGL(step_kernel, dim3(1), dim3(1), 0, s, a.step);
+}
+
+Box make_box(const Surrogate& S) {
+  Box b;
+  const double u0 = 1.0 / S.T_max, u1 = 1.0 / S.T_min;
+  b.T0 = (float)(0.5 * (u0 + u1));
+  b.Ts = (float)(2.0 / (u1 - u0));
+  b.x0 = (float)(0.5 * (S.x_min + S.x_max));
+  b.xs = (float)(S.x_max > S.x_min ? 2.0 / (S.x_max - S.x_min) : 0.0);
+  const double l0 = std::log(S.p_min), l1 = std::log(S.p_max);
+  b.p0 = (float)(0.5 * (l0 + l1));
+  b.ps = (float)(2.0 / (l1 - l0));
+  b.n_chunks = S.n_chunks;
+  return b;
+}
+
+Surrogate& surrogate(rt_ctx c) {
+  if (!c->surrogate) c->surrogate = new Surrogate();
+  return *c->surrogate;
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ULL) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ULL; }
+  return h;
+}
+
+}  // namespace
+
+void free_surrogate(rt_ctx c) {
+  if (!c->surrogate) return;
+  Surrogate& S = *c->surrogate;
+  for (int l = 0; l < kMlpLayers; ++l) {
+    dfree(S.w[l]); dfree(S.b[l]); dfree(S.mw[l]); dfree(S.vw[l]); dfree(S.mb[l]); dfree(S.vb[l]);
+    dfree(S.wt[l]); dfree(S.wk[l]);
+  }
+  dfree(S.mean); dfree(S.stdv);
+  delete c->surrogate;
+  c->surrogate = nullptr;
+}
+
+bool surrogate_ready(rt_ctx c) {
+  return c->surrogate && c->surrogate->trained && c->surrogate->n_nu == c->n_nu;
+}
+
+// Learned kappa into c->kappa: inference, range fallback, sampled check,
+// chunk fallback.  Called by rt_compute_kappa in surrogate mode.
+rt_status surrogate_kappa(rt_ctx c) {
+  Surrogate& S = *c->surrogate;
+  const int64_t n_cells = c->n_cells;
+  const int64_t rows = n_cells * S.n_chunks;
+  const int M = (int)((rows + 63) / 64 * 64);
+  if (rows > (int64_t)1 << 28) return sfail(c, RT_EINVAL, "surrogate: too many (cell, chunk) rows");
+  Acts a;
+  rt_status st = alloc_acts(c, a, M, false);
+  int32_t* d_list = nullptr;
+  unsigned* d_count = nullptr;
+  double* d_err = nullptr;
+  float* d_exact = nullptr;
+  int32_t* d_check = nullptr;
+  hipEvent_t ev[4];
+  for (auto& e : ev) if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+  auto cleanup = [&]() {
+    a.release();
+    dfree(d_list); dfree(d_count); dfree(d_err); dfree(d_exact); dfree(d_check);
+    for (auto& e : ev) if (e) (void)hipEventDestroy(e);
+  };
+  if (st != RT_OK) { cleanup(); return st; }
+  hipStream_t s = c->stream;
+  const Box bx = make_box(S);
+  (void)hipEventRecord(ev[0], s);
+  hipLaunchKernelGGL(infer_features_kernel, dim3(grid1(M)), dim3(256), 0, s, c->d_T, c->d_x,
+                     c->d_p, n_cells, bx, M, a.X0);
+  forward(S, a, false, s);
+  hipLaunchKernelGGL(infer_kappa_kernel, dim3(grid1(n_cells * c->ld)), dim3(256), 0, s, a.P,
+                     S.mean, S.stdv, c->d_T, c->d_x, c->d_p, n_cells, S.n_chunks, c->n_nu, c->ld,
+                     c->kappa);
+  (void)hipEventRecord(ev[1], s);
+  auto chk = [&](hipError_t e) { return e == hipSuccess; };
+  // range check -> exact line sum for out-of-range cells over the whole row
+  bool ok = chk(dalloc(&d_list, n_cells)) && chk(dalloc(&d_count, 1)) &&
+            chk(hipMemsetAsync(d_count, 0, sizeof(unsigned), s));
+  if (ok) hipLaunchKernelGGL(range_kernel, dim3(grid1(n_cells)), dim3(256), 0, s, c->d_T, c->d_x,
+                             c->d_p, n_cells, S.T_min, S.T_max, S.x_min, S.x_max, S.p_min,
+                             S.p_max, d_list, d_count);
+  unsigned n_out = 0;
+  ok = ok && chk(hipMemcpyAsync(&n_out, d_count, sizeof(unsigned), hipMemcpyDeviceToHost, s)) &&
+       chk(hipStreamSynchronize(s));
+  dev::KappaTile t;
+  t.L = c->lines;
+  t.C = c->cells;
+  t.n_cells = n_cells;
+  t.n_nu = c->n_nu;
+  t.K = c->K;
+  t.have_E = c->have_E ? 1 : 0;
+  t.out = c->kappa;
+  t.ld_out = c->ld;
+  const int tiles_all = (int)((c->ld + dev::kKappaTilePoints - 1) / dev::kKappaTilePoints);
+  if (ok && n_out > 0) {
+    dev::KappaTile tl = t;
+    tl.cell_list = d_list;
+    tl.n_cells = n_out;
+    tl.col0 = 0;
+    tl.col_end = c->ld;
+    ok = chk(launch_kappa_tiles(c, tl, (n_out + dev::kKappaCells - 1) / dev::kKappaCells, 0,
+                                tiles_all, false, s));
+  }
+  (void)hipEventRecord(ev[2], s);
+  // sampled check: exact rows of a few cells, relative L1 error per chunk
+  const int n_check = (int)std::min<int64_t>(S.check_cells, n_cells);
+  std::vector<int32_t> pick;
+  {
+    SplitMix g{S.check_seed ^ 0xC0FFEEULL};
+    std::vector<int32_t> all(n_cells);
+    for (int64_t i = 0; i < n_cells; ++i) all[i] = (int32_t)i;
+    // the coldest and the hottest cell (where the network is least
+    // constrained), then uniformly drawn cells
+    std::vector<double> hT(n_cells);
+    if (hipMemcpy(hT.data(), c->d_T, n_cells * 8, hipMemcpyDeviceToHost) == hipSuccess) {
+      const int64_t lo = std::min_element(hT.begin(), hT.end()) - hT.begin();
+      const int64_t hi = std::max_element(hT.begin(), hT.end()) - hT.begin();
+      for (int64_t e : {lo, hi}) {
+        if ((int)pick.size() >= n_check) break;
+        if (std::find(pick.begin(), pick.end(), (int32_t)e) == pick.end()) pick.push_back((int32_t)e);
+      }
+    }
+    for (int i = 0; (int)pick.size() < n_check && i < n_cells; ++i) {
+      const int64_t r = i + (int64_t)(g.uniform() * (double)(n_cells - i));
+      std::swap(all[i], all[std::min<int64_t>(r, n_cells - 1)]);
+      if (std::find(pick.begin(), pick.end(), all[i]) == pick.end()) pick.push_back(all[i]);
+    }
+  }
+  std::vector<double> err(S.n_chunks, 0.0);
+  if (ok && n_check > 0) {
+    ok = chk(dalloc(&d_check, n_check)) && chk(dalloc(&d_exact, (int64_t)n_check * c->ld)) &&
+         chk(dalloc(&d_err, S.n_chunks)) &&
+         chk(hipMemcpyAsync(d_check, pick.data(), n_check * 4, hipMemcpyHostToDevice, s));
+    if (ok) {
+      dev::KappaTile te = t;
+      te.cell_list = d_check;
+      te.n_cells = n_check;
+      te.out = d_exact;
+      te.compact_rows = 1;
+      te.col0 = 0;
+      te.col_end = c->ld;
+      ok = chk(launch_kappa_tiles(c, te, (n_check + dev::kKappaCells - 1) / dev::kKappaCells, 0,
+                                  tiles_all, false, s));
+    }
+    if (ok) {
+      hipLaunchKernelGGL(check_kernel, dim3(S.n_chunks), dim3(256), 0, s, c->kappa, c->ld,
+                         d_exact, c->ld, d_check, n_check, c->n_nu, c->cell_m * 100.0, d_err);
+      ok = chk(hipMemcpyAsync(err.data(), d_err, S.n_chunks * 8, hipMemcpyDeviceToHost, s)) &&
+           chk(hipStreamSynchronize(s));
+    }
+  }
+  (void)hipEventRecord(ev[3], s);
+  S.check_error = 0;
+  S.fallback_chunks = 0;
+  S.fallback_cells = (int)n_out;
+  for (int k = 0; ok && k < S.n_chunks; ++k) {
+    S.check_error = std::max(S.check_error, err[k]);
+    if (err[k] > S.tolerance) {
+      ++S.fallback_chunks;
+      dev::KappaTile tc = t;
+      tc.col0 = (int64_t)k * kMlpWidth;
+      tc.col_end = tc.col0 + kMlpWidth;
+      tc.out = c->kappa + tc.col0;  // the tile writes column j - col0
+      const int tile = (int)(tc.col0 / dev::kKappaTilePoints);
+      ok = chk(launch_kappa_tiles(c, tc, (n_cells + dev::kKappaCells - 1) / dev::kKappaCells,
+                                  tile, 1, false, s));
+    }
+  }
+  ok = ok && chk(hipStreamSynchronize(s));
+  float f1 = 0, f2 = 0, f3 = 0;
+  if (ok && ev[3]) {
+    (void)hipEventElapsedTime(&f1, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&f2, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&f3, ev[2], ev[3]);
+  }
+  S.infer_ms = f1;
+  S.check_ms = f3;
+  S.fallback_ms = f2;
+  cleanup();
+  if (!ok) return sfail(c, RT_EDEVICE, "surrogate inference: a HIP call failed");
+  return RT_OK;
+}
+
+}  // namespace rt
+
+using namespace rt;
+
+extern "C" {
+
+rt_status rt_surrogate_train(rt_ctx c, const rt_surrogate_cfg* cfg, double* final_loss) {
+  if (!c || !cfg) return RT_EINVAL;
+  if (!c->have_lines) return sfail(c, RT_ESTATE, "rt_surrogate_train: call rt_setup_lines first");
+  const int n = cfg->n_samples;
+  if (n < 64 || !cfg->T_K || !cfg->x_h2o || !cfg->p_atm)
+    return sfail(c, RT_EINVAL, "rt_surrogate_train: need >= 64 samples with T, x, p");
+  if (cfg->epochs < 1 || cfg->batch < 64 || cfg->batch % 64 != 0 || !(cfg->lr > 0))
+    return sfail(c, RT_EINVAL, "rt_surrogate_train: epochs >= 1, batch a multiple of 64, lr > 0");
+  if (!(cfg->T_min > 0 && cfg->T_max > cfg->T_min && cfg->x_min >= 0 && cfg->x_max > cfg->x_min &&
+        cfg->x_max <= 1 && cfg->p_min > 0 && cfg->p_max > cfg->p_min))
+    return sfail(c, RT_EINVAL, "rt_surrogate_train: invalid training box");
+  if (cfg->check_cells < 0 || !(cfg->tolerance > 0))
+    return sfail(c, RT_EINVAL, "rt_surrogate_train: check_cells >= 0 and tolerance > 0");
+  for (int i = 0; i < n; ++i)
+    if (!(cfg->T_K[i] > 0) || !(cfg->x_h2o[i] >= 0 && cfg->x_h2o[i] <= 1) || !(cfg->p_atm[i] > 0))
+      return sfail(c, RT_EINVAL, "rt_surrogate_train: invalid sample state");
+  RT_SHIP(c, hipSetDevice(c->device));
+  free_surrogate(c);
+  Surrogate& S = surrogate(c);
+  S.n_nu = c->n_nu;
+  S.n_chunks = (c->n_nu + kMlpWidth - 1) / kMlpWidth;
+  S.T_min = cfg->T_min; S.T_max = cfg->T_max;
+  S.x_min = cfg->x_min; S.x_max = cfg->x_max;
+  S.p_min = cfg->p_min; S.p_max = cfg->p_max;
+  S.check_cells = cfg->check_cells;
+  S.tolerance = cfg->tolerance;
+  S.check_seed = cfg->seed;
+  if (rt_status s = alloc_params(c, S)) return s;
+  hipStream_t s = c->stream;
+  // initial weights: uniform +-sqrt(6 / (fan_in + fan_out)), zero biases
+  SplitMix g{cfg->seed};
+  for (int l = 0; l < kMlpLayers; ++l) {
+    const int K = kMlpDims[l], N = kMlpDims[l + 1];
+    std::vector<float> w((size_t)K * N), z((size_t)K * N, 0.f), zb(N, 0.f);
+    const double a = std::sqrt(6.0 / (K + N));
+    for (auto& v : w) v = (float)((2.0 * g.uniform() - 1.0) * a);
+    RT_SHIP(c, hipMemcpy(S.w[l], w.data(), w.size() * 4, hipMemcpyHostToDevice));
+    RT_SHIP(c, hipMemcpy(S.mw[l], z.data(), z.size() * 4, hipMemcpyHostToDevice));
+    RT_SHIP(c, hipMemcpy(S.vw[l], z.data(), z.size() * 4, hipMemcpyHostToDevice));
+    RT_SHIP(c, hipMemcpy(S.b[l], zb.data(), zb.size() * 4, hipMemcpyHostToDevice));
+    RT_SHIP(c, hipMemcpy(S.mb[l], zb.data(), zb.size() * 4, hipMemcpyHostToDevice));
+    RT_SHIP(c, hipMemcpy(S.vb[l], zb.data(), zb.size() * 4, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid1((int64_t)K * N)), dim3(256), 0, s, S.w[l], K,
+                       N, S.wt[l], S.wk[l]);
+  }
+  // training spectra from the line sum over a grid of sample cells
+  const int64_t ld_s = ((int64_t)S.n_chunks * kMlpWidth + dev::kKappaTilePoints - 1) /
+                       dev::kKappaTilePoints * dev::kKappaTilePoints;
+  double *dT = nullptr, *dx = nullptr, *dp = nullptr;
+  float* Yall = nullptr;
+  CellSet cs;
+  int32_t* perm_d = nullptr;
+  Acts a;
+  auto cleanup = [&]() {
+    dfree(dT); dfree(dx); dfree(dp); dfree(Yall); dfree(perm_d);
+    dfree(cs.G); dfree(cs.beta); dfree(cs.theta); dfree(cs.lam2); dfree(cs.P);
+    a.release();
+  };
+  auto fail = [&](rt_status st, const std::string& m) { cleanup(); return sfail(c, st, m); };
+#define RT_TRY(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(RT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  RT_TRY(dalloc(&dT, n)); RT_TRY(dalloc(&dx, n)); RT_TRY(dalloc(&dp, n));
+  RT_TRY(dalloc(&cs.G, n)); RT_TRY(dalloc(&cs.beta, n)); RT_TRY(dalloc(&cs.theta, n));
+  RT_TRY(dalloc(&cs.lam2, n)); RT_TRY(dalloc(&cs.P, n));
+  RT_TRY(dalloc(&Yall, (int64_t)n * ld_s));
+  RT_TRY(hipMemcpy(dT, cfg->T_K, n * 8, hipMemcpyHostToDevice));
+  RT_TRY(hipMemcpy(dx, cfg->x_h2o, n * 8, hipMemcpyHostToDevice));
+  RT_TRY(hipMemcpy(dp, cfg->p_atm, n * 8, hipMemcpyHostToDevice));
+  RT_TRY(launch_cell_params_on(c, n, dT, dx, dp, cs, s));
+  dev::KappaTile t;
+  t.L = c->lines;
+  t.C = cs;
+  t.n_cells = n;
+  t.n_nu = c->n_nu;
+  t.K = c->K;
+  t.have_E = c->have_E ? 1 : 0;
+  t.out = Yall;
+  t.ld_out = ld_s;
+  t.col0 = 0;
+  t.col_end = ld_s;
+  RT_TRY(launch_kappa_tiles(c, t, (n + dev::kKappaCells - 1) / dev::kKappaCells, 0,
+                            (int)(ld_s / dev::kKappaTilePoints), false, s));
+  const int n_cols = S.n_chunks * kMlpWidth;
+  hipLaunchKernelGGL(log_target_kernel, dim3(grid1((int64_t)n * ld_s)), dim3(256), 0, s, Yall,
+                     (int64_t)n, ld_s, c->n_nu, dT, dx, dp);
+  hipLaunchKernelGGL(col_stats_kernel, dim3(grid1(n_cols)), dim3(256), 0, s, Yall, (int64_t)n,
+                     ld_s, n_cols, S.mean, S.stdv);
+  hipLaunchKernelGGL(normalize_kernel, dim3(grid1((int64_t)n * ld_s)), dim3(256), 0, s, Yall,
+                     (int64_t)n, ld_s, n_cols, S.mean, S.stdv);
+  RT_TRY(hipGetLastError());
+  // training
+  const int M = cfg->batch;
+  const int64_t n_rows = (int64_t)n * S.n_chunks;
+  const int64_t steps_per_epoch = std::max<int64_t>(1, n_rows / M);
+  const int64_t total_steps = steps_per_epoch * cfg->epochs;
+  if (rt_status st = alloc_acts(c, a, M, true)) { cleanup(); return st; }
+  RT_TRY(dalloc(&perm_d, steps_per_epoch * M));
+  RT_TRY(hipMemsetAsync(a.step, 0, sizeof(int), s));
+  const Box bx = make_box(S);
+  std::vector<int32_t> perm(n_rows);
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  RT_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  RT_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+  {
+    // one step: batch gather, forward, loss, backward, Adam, step++
+    hipLaunchKernelGGL(gather_kernel, dim3(grid1((int64_t)M * kMlpWidth)), dim3(256), 0, cap,
+                       perm_d, a.step, steps_per_epoch * M, M, dT, dx, dp, bx, Yall, ld_s, a.X0,
+                       a.Y, a.row_chunk);
+    forward(S, a, true, cap);
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(grid1((int64_t)M * kMlpWidth)), dim3(256), 0, cap,
+                       a.P, a.Y, a.row_chunk, M, c->n_nu, a.dP, a.dPT, a.sse);
+    backward(S, a, cap);
+    adam(S, a, (int)total_steps, cfg->lr, cap);
+  }
+  hipError_t ce = hipStreamEndCapture(cap, &graph);
+  if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    return fail(RT_EDEVICE, std::string("rt_surrogate_train: graph: ") + hipGetErrorString(ce));
+  }
+  SplitMix sh{cfg->seed ^ 0x5EED5EEDULL};
+  double last_sse = 0;
+  hipError_t re = hipSuccess;
+  for (int ep = 0; ep < cfg->epochs && re == hipSuccess; ++ep) {
+    for (int64_t i = 0; i < n_rows; ++i) perm[i] = (int32_t)i;
+    for (int64_t i = n_rows - 1; i > 0; --i) {
+      const int64_t j = (int64_t)(sh.uniform() * (double)(i + 1));
+      std::swap(perm[i], perm[std::min(j, i)]);
+    }
+    // the permutation buffer is indexed by the global step modulo its size
+    const int64_t base = (int64_t)ep * steps_per_epoch * M;
+    std::vector<int32_t> rolled((size_t)steps_per_epoch * M);
+    const int64_t span = steps_per_epoch * M;
+    for (int64_t q = 0; q < span; ++q) rolled[(base + q) % span] = perm[q];
+    re = hipMemcpyAsync(perm_d, rolled.data(), rolled.size() * 4, hipMemcpyHostToDevice, s);
+    if (re == hipSuccess) re = hipMemsetAsync(a.sse, 0, sizeof(double), s);
+    if (re == hipSuccess) re = hipStreamSynchronize(s);
+    for (int64_t st = 0; st < steps_per_epoch && re == hipSuccess; ++st)
+      re = hipGraphLaunch(exec, s);
+    if (re == hipSuccess)
+      re = hipMemcpyAsync(&last_sse, a.sse, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (re == hipSuccess) re = hipStreamSynchronize(s);
+  }
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  if (re != hipSuccess) return fail(RT_EDEVICE, std::string("rt_surrogate_train: ") + hipGetErrorString(re));
+  S.train_loss = last_sse / ((double)steps_per_epoch * M * kMlpWidth);
+  if (final_loss) *final_loss = S.train_loss;
+  cleanup();
+  S.trained = true;
+#undef RT_TRY
+  return RT_OK;
+}
+
+rt_status rt_surrogate_forward(rt_ctx c, int n_rows, const float* inputs, float* outputs) {
+  if (!c || n_rows < 1 || !inputs || !outputs) return RT_EINVAL;
+  if (!c->surrogate || !c->surrogate->trained) return sfail(c, RT_ESTATE, "rt_surrogate_forward: no surrogate");
+  Surrogate& S = *c->surrogate;
+  const int M = (n_rows + 63) / 64 * 64;
+  Acts a;
+  if (rt_status st = alloc_acts(c, a, M, false)) { a.release(); return st; }
+  std::vector<float> x((size_t)M * 4, 0.f);
+  std::memcpy(x.data(), inputs, (size_t)n_rows * 16);
+  hipError_t e = hipMemcpy(a.X0, x.data(), x.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    forward(S, a, false, c->stream);
+    e = hipStreamSynchronize(c->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpy(outputs, a.P, (size_t)n_rows * kMlpWidth * 4, hipMemcpyDeviceToHost);
+  a.release();
+  if (e != hipSuccess) return sfail(c, RT_EDEVICE, std::string("rt_surrogate_forward: ") + hipGetErrorString(e));
+  return RT_OK;
+}
+
+rt_status rt_surrogate_weights(rt_ctx c, float* out, int64_t n) {
+  if (!c || !out) return RT_EINVAL;
+  if (!c->surrogate || !c->surrogate->trained) return sfail(c, RT_ESTATE, "rt_surrogate_weights: no surrogate");
+  Surrogate& S = *c->surrogate;
+  if (n < S.param_count) return sfail(c, RT_EINVAL, "rt_surrogate_weights: buffer too small");
+  int64_t off = 0;
+  for (int l = 0; l < kMlpLayers; ++l) {
+    const int64_t kn = (int64_t)kMlpDims[l] * kMlpDims[l + 1];
+    RT_SHIP(c, hipMemcpy(out + off, S.w[l], kn * 4, hipMemcpyDeviceToHost));
+    off += kn;
+    RT_SHIP(c, hipMemcpy(out + off, S.b[l], kMlpDims[l + 1] * 4, hipMemcpyDeviceToHost));
+    off += kMlpDims[l + 1];
+  }
+  return RT_OK;
+}
+
+rt_status rt_surrogate_get_stats(rt_ctx c, rt_surrogate_stats* out) {
+  if (!c || !out) return RT_EINVAL;
+  if (!c->surrogate || !c->surrogate->trained) return sfail(c, RT_ESTATE, "rt_surrogate_get_stats: no surrogate");
+  const Surrogate& S = *c->surrogate;
+  out->check_error = S.check_error;
+  out->fallback_chunks = S.fallback_chunks;
+  out->fallback_cells = S.fallback_cells;
+  out->n_chunks = S.n_chunks;
+  out->infer_ms = S.infer_ms;
+  out->check_ms = S.check_ms;
+  out->fallback_ms = S.fallback_ms;
+  out->train_loss = S.train_loss;
+  out->param_count = (double)S.param_count;
+  return RT_OK;
+}
+
+// Blob: "RTLBLMLP", version 1, header ints/doubles, FP32 masters and the
+// normalisation tables, FNV-1a 64 checksum of everything before it.
+rt_status rt_surrogate_save(rt_ctx c, const char* path) {
+  if (!c || !path) return RT_EINVAL;
+  if (!c->surrogate || !c->surrogate->trained) return sfail(c, RT_ESTATE, "rt_surrogate_save: no surrogate");
+  Surrogate& S = *c->surrogate;
+  std::vector<char> blob;
+  auto put = [&](const void* p, size_t n) {
+    const char* b = static_cast<const char*>(p);
+    blob.insert(blob.end(), b, b + n);
+  };
+  put("RTLBLMLP", 8);
+  const int32_t hdr[4] = {1, S.n_nu, S.n_chunks, S.check_cells};
+  put(hdr, sizeof(hdr));
+  const double box[7] = {S.T_min, S.T_max, S.x_min, S.x_max, S.p_min, S.p_max, S.tolerance};
+  put(box, sizeof(box));
+  put(&S.check_seed, 8);
+  for (int l = 0; l < kMlpLayers; ++l) {
+    const int64_t kn = (int64_t)kMlpDims[l] * kMlpDims[l + 1];
+    std::vector<float> w(kn), b(kMlpDims[l + 1]);
+    RT_SHIP(c, hipMemcpy(w.data(), S.w[l], kn * 4, hipMemcpyDeviceToHost));
+    RT_SHIP(c, hipMemcpy(b.data(), S.b[l], b.size() * 4, hipMemcpyDeviceToHost));
+    put(w.data(), w.size() * 4);
+    put(b.data(), b.size() * 4);
+  }
+  std::vector<float> mean((size_t)S.n_chunks * kMlpWidth), sd(mean.size());
+  RT_SHIP(c, hipMemcpy(mean.data(), S.mean, mean.size() * 4, hipMemcpyDeviceToHost));
+  RT_SHIP(c, hipMemcpy(sd.data(), S.stdv, sd.size() * 4, hipMemcpyDeviceToHost));
+  put(mean.data(), mean.size() * 4);
+  put(sd.data(), sd.size() * 4);
+  const uint64_t h = fnv1a(blob.data(), blob.size());
+  put(&h, 8);
+  std::ofstream f(path, std::ios::binary | std::ios::trunc);
+  f.write(blob.data(), (std::streamsize)blob.size());
+  if (!f) return sfail(c, RT_EINVAL, "rt_surrogate_save: cannot write file");
+  return RT_OK;
+}
+
+rt_status rt_surrogate_load(rt_ctx c, const char* path) {
+  if (!c || !path) return RT_EINVAL;
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return sfail(c, RT_EINVAL, "rt_surrogate_load: cannot read file");
+  std::vector<char> blob((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+  if (blob.size() < 8 + 16 + 56 + 8 + 8 || std::memcmp(blob.data(), "RTLBLMLP", 8) != 0)
+    return sfail(c, RT_EINVAL, "rt_surrogate_load: not a surrogate blob");
+  uint64_t h;
+  std::memcpy(&h, blob.data() + blob.size() - 8, 8);
+  if (h != fnv1a(blob.data(), blob.size() - 8)) return sfail(c, RT_EINVAL, "rt_surrogate_load: checksum mismatch");
+  size_t off = 8;
+  int32_t hdr[4];
+  std::memcpy(hdr, blob.data() + off, 16); off += 16;
+  if (hdr[0] != 1) return sfail(c, RT_EINVAL, "rt_surrogate_load: unknown version");
+  double box[7];
+  std::memcpy(box, blob.data() + off, 56); off += 56;
+  uint64_t seed;
+  std::memcpy(&seed, blob.data() + off, 8); off += 8;
+  int64_t need = 0;
+  for (int l = 0; l < kMlpLayers; ++l) need += ((int64_t)kMlpDims[l] * kMlpDims[l + 1] + kMlpDims[l + 1]) * 4;
+  need += 2LL * hdr[2] * kMlpWidth * 4;
+  if ((int64_t)blob.size() != (int64_t)off + need + 8) return sfail(c, RT_EINVAL, "rt_surrogate_load: size mismatch");
+  RT_SHIP(c, hipSetDevice(c->device));
+  free_surrogate(c);
+  Surrogate& S = surrogate(c);
+  S.n_nu = hdr[1]; S.n_chunks = hdr[2]; S.check_cells = hdr[3];
+  S.T_min = box[0]; S.T_max = box[1]; S.x_min = box[2]; S.x_max = box[3];
+  S.p_min = box[4]; S.p_max = box[5]; S.tolerance = box[6];
+  S.check_seed = seed;
+  if (rt_status st = alloc_params(c, S)) return st;
+  for (int l = 0; l < kMlpLayers; ++l) {
+    const int K = kMlpDims[l], N = kMlpDims[l + 1];
+    RT_SHIP(c, hipMemcpy(S.w[l], blob.data() + off, (size_t)K * N * 4, hipMemcpyHostToDevice));
+    off += (size_t)K * N * 4;
+    RT_SHIP(c, hipMemcpy(S.b[l], blob.data() + off, (size_t)N * 4, hipMemcpyHostToDevice));
+    off += (size_t)N * 4;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid1((int64_t)K * N)), dim3(256), 0, c->stream,
+                       S.w[l], K, N, S.wt[l], S.wk[l]);
+  }
+  RT_SHIP(c, hipMemcpy(S.mean, blob.data() + off, (size_t)S.n_chunks * kMlpWidth * 4, hipMemcpyHostToDevice));
+  off += (size_t)S.n_chunks * kMlpWidth * 4;
+  RT_SHIP(c, hipMemcpy(S.stdv, blob.data() + off, (size_t)S.n_chunks * kMlpWidth * 4, hipMemcpyHostToDevice));
+  RT_SHIP(c, hipStreamSynchronize(c->stream));
+  S.trained = true;
+  return RT_OK;
+}
+
+}  // extern "C"

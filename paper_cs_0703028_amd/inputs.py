@@ -175,5 +175,18 @@ def batched_cases(n_cases: int = 64, seed: int = 0, sizes=(16, 24, 32, 48),
     return cases
 
 
+SURROGATE_BOX = (300.0, 2000.0, 0.01, 0.3, 0.5, 2.0)  # T, x_H2O, p ranges
+
+
+def surrogate_samples(n: int = 1 << 16, seed: int = 0, box=SURROGATE_BOX):
+    """Training gas states for the learned form: T, x_H2O, p uniform in the
+    box (Philox stream 8)."""
+    r = rng(seed, STREAM_TRAIN)
+    T = r.uniform(box[0], box[1], n)
+    x = r.uniform(box[2], box[3], n)
+    p = r.uniform(box[4], box[5], n)
+    return T, x, p
+
+
 def with_lines(w: Workload, **kw) -> Workload:
     return replace(w, lines=replace(w.lines, **kw))

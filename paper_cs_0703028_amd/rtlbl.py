@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtlbl.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-KAPPA_PLAIN, KAPPA_COMPENSATED = 0, 1
+KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE = 0, 1, 2
 TALLY_F32, TALLY_F64 = 0, 1
 
 if not os.path.exists(LIB_PATH):
@@ -60,6 +60,25 @@ class BatchTuning(C.Structure):
         return cls(**{n: int(d[n]) for n, _ in cls._fields_})
 
 
+class SurrogateCfg(C.Structure):
+    _fields_ = [("n_samples", C.c_int), ("T_K", C.c_void_p), ("x_h2o", C.c_void_p),
+                ("p_atm", C.c_void_p), ("T_min", C.c_double), ("T_max", C.c_double),
+                ("x_min", C.c_double), ("x_max", C.c_double), ("p_min", C.c_double),
+                ("p_max", C.c_double), ("epochs", C.c_int), ("batch", C.c_int),
+                ("lr", C.c_float), ("seed", C.c_uint64), ("check_cells", C.c_int),
+                ("tolerance", C.c_double)]
+
+
+class SurrogateStats(C.Structure):
+    _fields_ = [("check_error", C.c_double), ("fallback_chunks", C.c_int),
+                ("fallback_cells", C.c_int), ("n_chunks", C.c_int), ("infer_ms", C.c_double),
+                ("check_ms", C.c_double), ("fallback_ms", C.c_double),
+                ("train_loss", C.c_double), ("param_count", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 def _load():
     L = C.CDLL(LIB_PATH)
     vp = C.c_void_p
@@ -90,6 +109,15 @@ def _load():
     L.rt_batch_results.argtypes = [vp, vp, vp, vp]
     L.rt_batch_autotune.argtypes = [vp, C.c_int, C.POINTER(RtCase), C.c_int, vp, C.c_int64,
                                     C.c_char_p, C.POINTER(BatchTuning)]
+    L.rt_surrogate_train.argtypes = [vp, C.POINTER(SurrogateCfg), C.POINTER(C.c_double)]
+    L.rt_surrogate_save.argtypes = [vp, C.c_char_p]
+    L.rt_surrogate_load.argtypes = [vp, C.c_char_p]
+    L.rt_surrogate_forward.argtypes = [vp, C.c_int, _f32p, _f32p]
+    L.rt_surrogate_weights.argtypes = [vp, _f32p, C.c_int64]
+    L.rt_surrogate_get_stats.argtypes = [vp, C.POINTER(SurrogateStats)]
+    for f in ("rt_surrogate_train", "rt_surrogate_save", "rt_surrogate_load",
+              "rt_surrogate_forward", "rt_surrogate_weights", "rt_surrogate_get_stats"):
+        getattr(L, f).restype = C.c_int
     for f in ("rt_create", "rt_destroy", "rt_setup_grid", "rt_setup_lines", "rt_compute_kappa",
               "rt_trace_rays", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
               "rt_debug_segments", "rt_get_stats", "rt_batch_default_tuning",
@@ -186,13 +214,20 @@ class Tracer:
                 torch.empty((n, ld), dtype=torch.float32, device=dev))
 
     def compute_kappa(self, mode=KAPPA_PLAIN, kappa=None, planck=None):
-        if kappa is None or planck is None:
+        """Fills `kappa` (and `planck` when given) on the device.  With no
+        kappa buffer, both tables are allocated here.  planck=None with a
+        given kappa buffer means no Planck table (the plain march forms its
+        Planck values in registers; the precision form needs the table)."""
+        if kappa is None:
             kappa, planck = self.alloc_tables()
         for t in (kappa, planck):
+            if t is None:
+                continue
             if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
                 raise ValueError("tables must be contiguous 2-D float32 device tensors")
-        self._check(lib.rt_compute_kappa(self._h, mode, C.c_void_p(kappa.data_ptr()),
-                                         C.c_void_p(planck.data_ptr()), kappa.shape[1]))
+        pp = C.c_void_p(planck.data_ptr()) if planck is not None else None
+        self._check(lib.rt_compute_kappa(self._h, mode, C.c_void_p(kappa.data_ptr()), pp,
+                                         kappa.shape[1]))
         self._tables = (kappa, planck)  # keep the caller's buffers alive
         return kappa, planck
 
@@ -303,6 +338,53 @@ class Tracer:
                                           cache_path.encode() if cache_path else None,
                                           C.byref(best)))
         return best
+
+    # -------------------------------------------------------- learned form
+    MLP_DIMS = (4, 512, 512, 512, 256)
+
+    def surrogate_train(self, T, x, p, box, epochs=10, batch=4096, lr=1e-3, seed=0,
+                        check_cells=8, tolerance=1e-3):
+        """Train the MLP on line-sum spectra of the gas states (T, x, p);
+        box = (T_min, T_max, x_min, x_max, p_min, p_max).  Returns the final
+        mean squared normalised error."""
+        T, x, p = _f64(T), _f64(x), _f64(p)
+        cfg = SurrogateCfg(len(T), T.ctypes.data, x.ctypes.data, p.ctypes.data, *box,
+                           epochs, batch, lr, seed, check_cells, tolerance)
+        loss = C.c_double()
+        self._check(lib.rt_surrogate_train(self._h, C.byref(cfg), C.byref(loss)))
+        return loss.value
+
+    def surrogate_save(self, path):
+        self._check(lib.rt_surrogate_save(self._h, path.encode()))
+
+    def surrogate_load(self, path):
+        self._check(lib.rt_surrogate_load(self._h, path.encode()))
+
+    def surrogate_forward(self, inputs):
+        inputs = np.ascontiguousarray(inputs, np.float32).reshape(-1, 4)
+        out = np.zeros((inputs.shape[0], 256), np.float32)
+        self._check(lib.rt_surrogate_forward(self._h, inputs.shape[0], inputs.ravel(),
+                                             out.ravel()))
+        return out
+
+    def surrogate_weights(self):
+        d = self.MLP_DIMS
+        n = sum(d[i] * d[i + 1] + d[i + 1] for i in range(4))
+        buf = np.zeros(n, np.float32)
+        self._check(lib.rt_surrogate_weights(self._h, buf, n))
+        out, off = [], 0
+        for i in range(4):
+            W = buf[off:off + d[i] * d[i + 1]].reshape(d[i], d[i + 1])
+            off += d[i] * d[i + 1]
+            b = buf[off:off + d[i + 1]]
+            off += d[i + 1]
+            out.append((W.copy(), b.copy()))
+        return out
+
+    def surrogate_stats(self):
+        st = SurrogateStats()
+        self._check(lib.rt_surrogate_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
 
     # ------------------------------------------------------------- helpers
     def raw_status(self, name, *args):

@@ -1,0 +1,139 @@
+"""GPU tests of the learned form (MLP surrogate of the line sum).
+
+* the network's forward pass (BF16 MFMA GEMMs) equals a PyTorch CPU FP32
+  evaluation of the same network with the same BF16 roundings;
+* with the range check, the sampled check and the line-sum fallback, the
+  per-cell absorbed and emitted power of the march driven by the surrogate
+  match the plain line-sum path within 1e-3 relative (the surrogate bar),
+  and out-of-range cells receive the exact line-sum kappa;
+* save / load reproduces the network exactly.
+"""
+import numpy as np
+import pytest
+
+from paper_cs_0703028_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_cs_0703028_amd import rtlbl
+    return rtlbl
+
+
+@pytest.fixture(scope="module")
+def trained(rt):
+    w = I.plain_8cube()
+    t = rt.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(w.lines)
+    T, x, p = I.surrogate_samples(4096, seed=1)
+    print("training small surrogate", flush=True)
+    loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=12, batch=1024, lr=2e-3, seed=3,
+                             check_cells=32, tolerance=2e-4)
+    print(f"  loss {loss:.4e}", flush=True)
+    assert np.isfinite(loss)
+    yield t, w
+    t.close()
+
+
+def _bf16(a):
+    import torch
+    return torch.as_tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float32)
+
+
+def test_forward_matches_torch(rt, trained):
+    import torch
+    t, _ = trained
+    params = t.surrogate_weights()
+    rng = np.random.default_rng(0)
+    X = rng.uniform(-1, 1, (200, 4)).astype(np.float32)
+    got = t.surrogate_forward(X)
+    h = torch.as_tensor(X)
+    for i, (W, b) in enumerate(params):
+        z = h @ _bf16(W) + torch.as_tensor(b)
+        if i < 3:
+            h = _bf16(z * torch.sigmoid(z))
+        else:
+            h = z
+    ref = h.numpy()
+    err = np.abs(got - ref).max()
+    scale = 1.0 + np.abs(ref).max()
+    print(f"forward max abs err {err:.3e} (scale {scale:.3e})", flush=True)
+    assert err <= 2e-2 * scale
+
+
+def test_surrogate_tallies_within_1e3_of_plain(rt, trained):
+    t, w = trained
+    # plain line-sum reference on a separate handle
+    r = rt.Tracer(0)
+    r.setup_grid(w.grid)
+    r.setup_lines(w.lines)
+    r.compute_kappa(rt.KAPPA_PLAIN, *r.alloc_tables())
+    r.trace_rays(w.seed, w.n_rays)
+    a0, e0, b0 = r.tally()
+    k0 = r._tables[0].cpu().numpy()
+    r.close()
+    kap, B = t.alloc_tables()
+    t.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
+    st = t.surrogate_stats()
+    print("surrogate stats", st, flush=True)
+    t.reset_tally()
+    t.trace_rays(w.seed, w.n_rays)
+    a1, e1, b1 = t.tally()
+    ra = np.abs(a1 - a0)[a0 > 0] / a0[a0 > 0]
+    re_ = np.abs(e1 - e0)[e0 > 0] / e0[e0 > 0]
+    print(f"per-cell absorbed rel err max {ra.max():.3e}, emitted {re_.max():.3e}", flush=True)
+    assert ra.max() <= 1e-3 and re_.max() <= 1e-3
+    assert 0 <= st["fallback_chunks"] <= st["n_chunks"]
+    # chunks recomputed by the fallback are bit-identical to the line sum
+    k1 = kap.cpu().numpy()
+    nz = w.lines.n_nu
+    exact = sum(np.array_equal(k1[:, 256 * k:min(256 * (k + 1), nz)],
+                               k0[:, 256 * k:min(256 * (k + 1), nz)])
+                for k in range(st["n_chunks"]))
+    assert exact >= st["fallback_chunks"]
+
+
+def test_out_of_range_cells_get_exact_kappa(rt, trained):
+    t, w = trained
+    g = I.plain_8cube().grid
+    g.T = g.T.copy()
+    g.T[5] = 2600.0  # outside the 300-2000 K training box
+    g.p = g.p.copy()
+    g.p[9] = 3.0     # outside 0.5-2 atm
+    t.setup_grid(g)
+    kap, _ = t.alloc_tables()
+    t.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
+    st = t.surrogate_stats()
+    assert st["fallback_cells"] == 2
+    r = rt.Tracer(0)
+    r.setup_grid(g)
+    r.setup_lines(w.lines)
+    k_ref, _ = r.compute_kappa(rt.KAPPA_PLAIN, *r.alloc_tables())
+    for c in (5, 9):
+        np.testing.assert_array_equal(kap[c].cpu().numpy(), k_ref[c].cpu().numpy())
+    r.close()
+    t.setup_grid(w.grid)
+
+
+def test_save_load_roundtrip(rt, trained, tmp_path):
+    t, w = trained
+    path = str(tmp_path / "mlp.bin")
+    t.surrogate_save(path)
+    X = np.random.default_rng(1).uniform(-1, 1, (64, 4)).astype(np.float32)
+    y0 = t.surrogate_forward(X)
+    u = rt.Tracer(0)
+    u.setup_lines(w.lines)
+    u.surrogate_load(path)
+    np.testing.assert_array_equal(u.surrogate_forward(X), y0)
+    raw = open(path, "rb").read()
+    bad = raw[:100] + bytes([raw[100] ^ 1]) + raw[101:]
+    open(path, "wb").write(bad)
+    with pytest.raises(rt.RtError):
+        u.surrogate_load(path)
+    u.close()
