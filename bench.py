@@ -2,13 +2,15 @@
 50,000-point, 2^20-ray workload (Gaussian hot spot 400-1800 K, x_H2O
 U[0.05, 0.2], 1 m cube), inputs resident on the GPU:
 
-    compute_kappa (Eq. (1)-(2) line sum + Eq. (4) Planck table)
-    -> trace_rays (Philox rays, integer traversal, Eq. (3) march, tallies)
+    compute_kappa (Eq. (1)-(2) line sum)
+    -> trace_rays (Philox rays, integer traversal, Eq. (3) march with the
+       Eq. (4) Planck values formed in registers, per-cell tallies)
     -> tally (energy balance, per-cell powers to the host)
 
 Prints one JSON line.  `value` is ray-cell-nu updates per second of the whole
 step; the line-sum rate, the march roofline and the FP64 CPU oracle timed on a
-bounded sample are reported beside it.  One GPU only.
+bounded sample are reported beside it, and `forms` carries the precision,
+batched and learned forms, each on its own workload.  One GPU only.
 """
 from __future__ import annotations
 
@@ -25,21 +27,53 @@ METRIC = ("ray·cell·nu updates/s + line evals/s; "
           "surrogate vs plain at ≤1e-3 rel power")
 
 # Algorithmic work per ray-cell-nu update of Eq. (3) with the Planck value
-# read once per (cell, nu) from a table: x = kappa * (-l log2 e), t = 2^x,
-# a = 1 - t, d = I - B, I -= d a, absorbed += I a, emitted += B a:
-# 9 FP32 flops (an FMA counts 2) in 6 full-rate VALU issue slots, plus one
-# base-2 exponential.
+# read once per (cell, nu): x = kappa * (-l log2 e), t = 2^x, a = 1 - t,
+# d = I - B, I -= d a, absorbed += I a, emitted += B a: 9 FP32 flops (an FMA
+# counts 2) in 6 full-rate VALU issue slots, plus one base-2 exponential.
 MARCH_FLOPS_PER_UPDATE = 9.0
 MARCH_SLOTS_PER_UPDATE = 6.0
 # MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz = 39.32e12 lane-slots/s (packed
-# FP32 is not used).  The hardware exponential issues at half rate on gfx950
-# (2 slots), as measured by paper_cs_0703028_amd/probe/alu_rates.hip.
+# FP32 is not used).  The hardware exponential and reciprocal issue at half
+# rate on gfx950 (2 slots), as measured by paper_cs_0703028_amd/probe/alu_rates.hip.
 LANE_SLOTS_PER_S = 256 * 64 * 2.4e9
 TRANS_SLOTS = 2.0
+# Eq. (2) per in-window (cell, line, nu) triple, with the squared offset
+# shared by the cells of a tile: g2 + d^2 (1 add), reciprocal, acc += A * rcp
+# (1 FMA): 4 FP32 flops in 2 full-rate slots plus one half-rate reciprocal.
+LINE_FLOPS_PER_EVAL = 4.0
+LINE_SLOTS_PER_EVAL = 2.0 + TRANS_SLOTS
+BF16_DENSE_PEAK = 2.5e15
+MLP_WEIGHTS = 4 * 512 + 512 * 512 + 512 * 512 + 512 * 256
+TUNING_CACHE = os.path.join(ROOT, "paper_cs_0703028_amd", "tuning", "batch_tune.json")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "march_kernel_plain_32cube_hbm_counters.md")
+MARCH_SOURCES = ("paper_cs_0703028_amd/csrc/march.hip", "paper_cs_0703028_amd/csrc/device_common.h",
+                 "paper_cs_0703028_amd/csrc/rt_internal.h")
+
+
+def measured_traffic():
+    """HBM bytes per march launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None once the march sources differ from the profiled ones."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        h = hashlib.sha256()
+        for s in MARCH_SOURCES:
+            h.update(open(os.path.join(ROOT, s), "rb").read())
+        fields = dict(line.split(": ", 1) for line in text.splitlines()
+                      if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
+        if fields.get("source_sha256", "").strip() != h.hexdigest():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def march_peak_updates_per_s():
     return LANE_SLOTS_PER_S / (MARCH_SLOTS_PER_UPDATE + TRANS_SLOTS)
+
+
+def line_peak_evals_per_s():
+    return LANE_SLOTS_PER_S / LINE_SLOTS_PER_EVAL
 
 
 def cpu_baseline(w, n_cells_sample=32, n_rays_sample=96):
@@ -80,13 +114,191 @@ def cpu_baseline(w, n_cells_sample=32, n_rays_sample=96):
     }
 
 
+def _rel(g, o):
+    import numpy as np
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    nz = o != 0
+    return float(np.max(np.abs(g[nz] - o[nz]) / np.abs(o[nz]))) if nz.any() else 0.0
+
+
+def form_precision(rtlbl, I):
+    """Precision form on the 8^3 workload: compensated line sums, Planck
+    table, FP64 partial sums; the error of each result against the FP64
+    oracle, plus the 1 m isothermal slab against its closed form."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    w = I.plain_8cube()
+    t = rtlbl.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(w.lines)
+    kap, B = t.alloc_tables()
+
+    def step():
+        t.reset_tally()
+        t.compute_kappa(rtlbl.KAPPA_COMPENSATED, kap, B)
+        t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, rtlbl.TALLY_F64)
+        return t.tally()
+
+    step()
+    torch.cuda.synchronize()
+    t.stats()
+    t0 = time.perf_counter()
+    a, e, b = step()
+    dt = time.perf_counter() - t0
+    st = t.stats()
+    ref = O.run(w.grid, w.lines, w.n_rays, seed=w.seed)
+    n = w.lines.n_nu
+    out = {
+        "workload": w.name,
+        "ms_per_step": dt * 1e3,
+        "updates_per_s": st["updates"] / dt,
+        "line_evals_per_s_kappa": st["line_evals"] / (st["kappa_ms"] * 1e-3),
+        "err_vs_fp64_oracle_max_rel": {
+            "kappa": _rel(kap.cpu().numpy()[:, :n], ref["kappa"]),
+            "planck": _rel(B.cpu().numpy()[:, :n], ref["planck"]),
+            "absorbed": _rel(a, ref["absorbed"]),
+            "emitted": _rel(e, ref["emitted"]),
+            "balance": _rel(b, ref["balance"]),
+        },
+        "energy_balance_residual": float(abs(b[0] + b[1] - b[2] - b[3]) / (b[0] + b[1])),
+    }
+    t.close()
+    s = I.slab_1cell()
+    t = rtlbl.Tracer(0)
+    t.setup_grid(s.grid)
+    t.setup_lines(s.lines)
+    t.compute_kappa(rtlbl.KAPPA_COMPENSATED)
+    U = 1 << 21
+    ex = t.trace_explicit(np.array([[0, U // 2 + 1, U // 2 + 1]]), np.array([[1 << 20, 0, 0]]),
+                          1.0, prec=rtlbl.TALLY_F64, want_exit=True)[0]
+    t.close()
+    k = O.kappa(s.grid, s.lines)[0]
+    Bc = O.planck_rows(s.grid, s.lines)[0]
+    nu = s.lines.nu0 + np.arange(s.lines.n_nu) * s.lines.dnu
+    Bw = np.array([O.planck(v, s.grid.T_wall) for v in nu])
+    tr = np.exp(-k * s.grid.cell_m * 100.0)
+    closed = Bw * tr + Bc * (1 - tr)
+    out["slab_1m_exit_radiance_max_rel_vs_closed_form"] = _rel(ex, closed)
+    return out
+
+
+def form_batched(rtlbl, I):
+    """Batched form: 64 receiver cases (16^3-48^3 cells, 2^14-2^18 rays, 5,000
+    lines, 20,000 points) in one persistent, graph-captured launch, with the
+    tuning looked up in (or written to) the autotuner's cache."""
+    import numpy as np
+    import torch
+    cases = I.batched_cases(64)
+    t = rtlbl.Tracer(0)
+    t.setup_lines(cases[0].lines)
+    big = rtlbl.Tracer.default_tuning()
+    big.chunk_points = 4096
+    big.blocks_per_cu = 4
+    ws = torch.empty(t.batch_workspace_size(cases, big), dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    best = t.batch_autotune(cases, rtlbl.KAPPA_PLAIN, ws, TUNING_CACHE)
+    tune_s = time.perf_counter() - t0
+    t.batch_prepare(cases, rtlbl.KAPPA_PLAIN, best, ws)
+    t.batch_launch()
+    t.batch_results()
+    t.stats()
+    t0 = time.perf_counter()
+    t.batch_launch()
+    res = t.batch_results()
+    dt = time.perf_counter() - t0
+    st = t.stats()
+    t.close()
+    bal = np.array([r[2] for r in res])
+    return {
+        "workload": "64 cases, 16^3-48^3 cells, 2^14-2^18 rays, 5,000 lines, 20,000 nu",
+        "cells": int(sum(c.grid.n_cells for c in cases)),
+        "rays": int(sum(c.n_rays for c in cases)),
+        "ms_per_launch": dt * 1e3,
+        "device_ms": st["batch_ms"],
+        "updates": st["batch_updates"],
+        "line_evals": st["batch_line_evals"],
+        "updates_per_s": st["batch_updates"] / dt,
+        "line_evals_per_s": st["batch_line_evals"] / dt,
+        "tuning": best.as_dict(),
+        "tuning_s": tune_s,
+        "energy_balance_residual_max": float(np.max(
+            np.abs(bal[:, 0] + bal[:, 1] - bal[:, 2] - bal[:, 3]) / (bal[:, 0] + bal[:, 1]))),
+    }
+
+
+def form_learned(rtlbl, I, epochs=40):
+    """Learned form on the 8^3 workload: train the MLP on 2^16 line-sum
+    spectra, then take kappa from it (range check, sampled check, line-sum
+    fallback) for the plain march; error and speed-up against the line sum."""
+    import numpy as np
+    import torch
+    w = I.plain_8cube()
+    t = rtlbl.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(w.lines)
+    T, x, p = I.surrogate_samples(1 << 16, seed=0)
+    t0 = time.perf_counter()
+    loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=epochs, batch=4096, lr=1e-3,
+                             seed=0, check_cells=32, tolerance=2e-4)
+    train_s = time.perf_counter() - t0
+    kap = torch.empty((w.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
+
+    def run(mode, reps=5):
+        best = 1e30
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            t.compute_kappa(mode, kap, None)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - a)
+        t.reset_tally()
+        t.trace_rays(w.seed, w.n_rays)
+        return best, t.tally()
+
+    t_plain, (a0, e0, _) = run(rtlbl.KAPPA_PLAIN)
+    t_sur, (a1, e1, _) = run(rtlbl.KAPPA_SURROGATE)
+    st = t.surrogate_stats()
+    t.close()
+    ra = np.abs(a1 - a0)[a0 > 0] / a0[a0 > 0]
+    re_ = np.abs(e1 - e0)[e0 > 0] / e0[e0 > 0]
+    flops = 2.0 * MLP_WEIGHTS * w.grid.n_cells * st["n_chunks"]
+    return {
+        "workload": w.name,
+        "train_s": train_s,
+        "train_samples": 1 << 16,
+        "epochs": epochs,
+        "train_mse_normalised": loss,
+        "kappa_ms_surrogate": t_sur * 1e3,
+        "kappa_ms_plain_line_sum": t_plain * 1e3,
+        "speedup_vs_plain": t_plain / t_sur,
+        "mlp_infer_ms": st["infer_ms"],
+        "mlp_check_ms": st["check_ms"],
+        "mlp_fallback_ms": st["fallback_ms"],
+        "mlp_tflops": flops / (st["infer_ms"] * 1e-3) / 1e12 if st["infer_ms"] > 0 else None,
+        "mlp_frac_of_bf16_peak": (flops / (st["infer_ms"] * 1e-3) / BF16_DENSE_PEAK
+                                  if st["infer_ms"] > 0 else None),
+        "fallback_chunks": st["fallback_chunks"],
+        "fallback_cells": st["fallback_cells"],
+        "n_chunks": st["n_chunks"],
+        "check_error_max": st["check_error"],
+        "rel_err_vs_plain_max": {"absorbed": float(ra.max()), "emitted": float(re_.max())},
+        "within_1e-3": bool(max(ra.max(), re_.max()) <= 1e-3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--workload", default="plain_32cube")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device once (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -95,6 +307,15 @@ def main():
 
     import torch
 
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 1 << 30, "copy_probe_bytes_written": 1 << 30}))
+        return
+
     from paper_cs_0703028_amd import inputs as I
     from paper_cs_0703028_amd import rtlbl
 
@@ -102,19 +323,18 @@ def main():
     t = rtlbl.Tracer(0)
     t.setup_grid(w.grid)
     t.setup_lines(w.lines)
-    kap, B = t.alloc_tables()
+    kap = torch.empty((w.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
 
     def step():
         t.reset_tally()
-        t.compute_kappa(rtlbl.KAPPA_PLAIN, kap, B)
+        t.compute_kappa(rtlbl.KAPPA_PLAIN, kap, None)
         t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, rtlbl.TALLY_F32)
         return t.tally()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    st = t.stats()  # drains the warmup timers
-    t.reset_tally()
+    t.stats()
     kappa_ms = march_ms = 0.0
     launches = updates = evals = 0.0
     torch.cuda.synchronize()
@@ -129,19 +349,21 @@ def main():
         evals += st["line_evals"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
-    value = updates / dt
-    kappa_ms_timed = kappa_ms
+    print(f"# headline done: {dt / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    t.close()
+    del kap
+    torch.cuda.empty_cache()
     peak = march_peak_updates_per_s()
     march_rate = updates / (march_ms * 1e-3)
+    line_rate = evals / (kappa_ms * 1e-3)
     rec = {
         "metric": METRIC,
-        "value": value,
+        "value": updates / dt,
         "unit": "ray·cell·nu updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -150,7 +372,12 @@ def main():
         "config": {"workload": w.name, "cells": w.grid.n_cells, "lines": int(len(w.lines.nu)),
                    "n_nu": w.lines.n_nu, "rays": w.n_rays, "kappa_mode": "plain",
                    "tally": "f32 partials, f64 accumulators"},
-        "line_evals_per_s": evals / (kappa_ms_timed * 1e-3) if kappa_ms_timed > 0 else None,
+        "kappa_ms_per_step": kappa_ms / args.steps,
+        "march_ms_per_step": march_ms / args.steps,
+        "line_evals_per_s": line_rate,
+        "line_sum_alu": {"achieved": line_rate * LINE_FLOPS_PER_EVAL / 1e12,
+                         "peak": line_peak_evals_per_s() * LINE_FLOPS_PER_EVAL / 1e12,
+                         "unit": "TFLOP/s", "frac": line_rate / line_peak_evals_per_s()},
         "trace_updates_per_s": march_rate,
         "energy_balance_rel": float(abs(bal[0] + bal[1] - bal[2] - bal[3]) / (bal[0] + bal[1])),
         "roofline": {
@@ -160,12 +387,21 @@ def main():
             "peak": peak * MARCH_FLOPS_PER_UPDATE / 1e12,
             "unit": "TFLOP/s",
             "frac": march_rate / peak,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
             "launches": launches,
             "avg_launch_ms": march_ms / launches if launches else None,
         },
     }
-    t.close()
+    if not args.no_forms:
+        rec["forms"] = {}
+        for name, fn in (("precision", form_precision), ("batched", form_batched),
+                         ("learned", form_learned)):
+            try:
+                rec["forms"][name] = fn(rtlbl, I)
+            except Exception as exc:  # a failing form must not hide the headline
+                rec["forms"][name] = {"error": repr(exc)}
+            print(f"# form {name} done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
