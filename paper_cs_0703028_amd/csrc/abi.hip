@@ -103,18 +103,26 @@ rt_status set_device(rt_ctx c) {
 }
 
 // Ray scratch: per-ray segment lists for one batch of rays.
-rt_status ensure_batch(rt_ctx c) {
+// Batch scratch for `need` rays, up to the cap: at most ~1 GiB of segments
+// per batch (large batches make the coherent ray order denser), at least
+// 4096 and at most 2^21 rays.  Grows, never shrinks, for one grid shape.
+rt_status ensure_batch(rt_ctx c, int64_t need) {
   const int max_segs = c->nx + c->ny + c->nz;
-  // at most ~96 MB of segments per batch, at least 4096 rays
-  int64_t want = std::max<int64_t>(4096, (int64_t)(96ll << 20) / (8ll * max_segs));
-  want = std::min<int64_t>(want, 1 << 18);
-  if (c->d_segs && c->max_segs == max_segs && c->batch_rays == want) return RT_OK;
+  int64_t cap = std::max<int64_t>(4096, (int64_t)(1ll << 30) / (8ll * max_segs));
+  cap = std::min<int64_t>(cap, 1 << 21) / 4096 * 4096;
+  const int64_t want = std::min<int64_t>(cap, (std::max<int64_t>(need, 1) + 4095) / 4096 * 4096);
+  if (c->d_segs && c->max_segs == max_segs && c->batch_rays >= want) return RT_OK;
   dev_free(c->d_segs);
   dev_free(c->d_counts);
+  dev_free(c->d_keys);
+  dev_free(c->d_perm);
   c->max_segs = max_segs;
   c->batch_rays = want;
   RT_HIP(c, dev_alloc(&c->d_segs, (size_t)want * max_segs));
   RT_HIP(c, dev_alloc(&c->d_counts, (size_t)want));
+  RT_HIP(c, dev_alloc(&c->d_keys, (size_t)want));
+  RT_HIP(c, dev_alloc(&c->d_perm, (size_t)want));
+  if (!c->d_hist) RT_HIP(c, dev_alloc(&c->d_hist, (size_t)rt::kOrderBuckets));
   return RT_OK;
 }
 
@@ -171,6 +179,7 @@ rt_status rt_destroy(rt_ctx c) {
   dev_free(c->d_abs); dev_free(c->d_emi); dev_free(c->d_slots); dev_free(c->d_balance);
   dev_free(c->d_segcount);
   dev_free(c->d_segs); dev_free(c->d_counts); dev_free(c->d_rays_explicit); dev_free(c->d_exit);
+  dev_free(c->d_keys); dev_free(c->d_perm); dev_free(c->d_hist);
   free_events(c->trace_events); free_events(c->march_events); free_events(c->kappa_events);
   free_events(c->batch_events);
   rt::destroy_batch(c);
@@ -387,12 +396,15 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
 
 static rt_status trace_batches(rt_ctx c, uint64_t seed, uint64_t begin, uint64_t count,
                                double weight, bool f64, bool explicit_rays, float* exit_dev) {
-  if (rt_status s = ensure_batch(c)) return s;
+  if (rt_status s = ensure_batch(c, (int64_t)count)) return s;
   if (rt_status s = record_begin(c, c->trace_events)) return s;
   for (uint64_t off = 0; off < count; off += (uint64_t)c->batch_rays) {
     const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)c->batch_rays, count - off);
     if (explicit_rays && off > 0) return fail(c, RT_EINVAL, "explicit rays exceed one batch");
-    RT_HIP(c, rt::launch_raygen(c, seed, begin + off, n, explicit_rays, nullptr, true));
+    const bool order = !explicit_rays && n >= rt::kOrderMinRays;
+    if (order) RT_HIP(c, rt::launch_order(c, seed, begin + off, n));
+    RT_HIP(c, rt::launch_raygen(c, seed, begin + off, n, explicit_rays, nullptr, true,
+                                order ? c->d_perm : nullptr));
     if (rt_status s = record_begin(c, c->march_events)) return s;
     RT_HIP(c, rt::launch_march(c, n, weight, f64, exit_dev));
     if (rt_status s = record_end(c, c->march_events)) return s;
@@ -431,7 +443,7 @@ rt_status rt_trace_explicit(rt_ctx c, int n_rays, const int64_t* O, const int64_
     return fail(c, RT_EINVAL, "rt_trace_explicit: unknown tally precision");
   if (tally_prec == RT_TALLY_F64 && !c->planck)
     return fail(c, RT_ESTATE, "rt_trace_explicit: the precision form needs the Planck table");
-  if (rt_status s = ensure_batch(c)) return s;
+  if (rt_status s = ensure_batch(c, n_rays)) return s;
   if (n_rays > c->batch_rays) return fail(c, RT_EINVAL, "rt_trace_explicit: too many rays");
   const int64_t lim[3] = {c->nx * rt::kCellUnits, c->ny * rt::kCellUnits, c->nz * rt::kCellUnits};
   std::vector<int64_t> buf((size_t)n_rays * 6);
@@ -531,7 +543,7 @@ rt_status rt_debug_segments(rt_ctx c, uint64_t seed, uint64_t ray_begin, uint64_
   if (!counts || !cells || !len_cm) return fail(c, RT_EINVAL, "rt_debug_segments: NULL output");
   if (max_segs < c->nx + c->ny + c->nz) return fail(c, RT_EINVAL, "rt_debug_segments: max_segs < nx+ny+nz");
   if (rt_status s = set_device(c)) return s;
-  if (rt_status s = ensure_batch(c)) return s;
+  if (rt_status s = ensure_batch(c, (int64_t)count)) return s;
   if (c->explicit_cap < c->batch_rays) {
     dev_free(c->d_rays_explicit);
     RT_HIP(c, dev_alloc(&c->d_rays_explicit, (size_t)c->batch_rays * 6));
@@ -542,7 +554,8 @@ rt_status rt_debug_segments(rt_ctx c, uint64_t seed, uint64_t ray_begin, uint64_
   std::vector<int64_t> rays;
   for (uint64_t off = 0; off < count; off += (uint64_t)c->batch_rays) {
     const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)c->batch_rays, count - off);
-    RT_HIP(c, rt::launch_raygen(c, seed, ray_begin + off, n, false, c->d_rays_explicit, false));
+    RT_HIP(c, rt::launch_raygen(c, seed, ray_begin + off, n, false, c->d_rays_explicit, false,
+                                nullptr));
     seg.resize((size_t)n * c->max_segs);
     cnt.resize((size_t)n);
     rays.resize((size_t)n * 6);

@@ -1,5 +1,7 @@
 // march.hip -- Monte-Carlo rays through the cell grid on gfx950.
 //
+//   order      : a coherent processing order for the rays of a batch
+//                (counting sort on a direction/position key)
 //   raygen_dda : Philox4x64-10 ray sampling (uniform boundary point,
 //                cosine-weighted inward direction) and exact integer
 //                traversal -> per-ray list of (cell, length) segments
@@ -16,10 +18,96 @@ namespace {
 
 using namespace dev;
 
+// ------------------------------------------------------------ ray order
+// Rays that run nearly parallel through nearby cells read the same kappa
+// rows.  Marching them together (and on one XCD, see march_kernel) lets those
+// rows be served from L2 instead of beyond it.  The key is the dominant axis
+// and sign of D, a 3 x 3 bin of the two transverse direction ratios, and the
+// Morton index (6 bits per axis) of the point where the ray's line crosses
+// the grid's mid-plane normal to the dominant axis, over [-N, 2N] cells.
+// The order changes only the order of the FP64 tally additions.
+__device__ __forceinline__ uint32_t spread6(uint32_t v) {  // bits 0..5 -> even bits
+  v = (v | (v << 4)) & 0x30fu;
+  v = (v | (v << 2)) & 0x333u;
+  v = (v | (v << 1)) & 0x555u;
+  return v;
+}
+
+__device__ uint32_t order_key(const int64_t O[3], const int64_t D[3], int nx, int ny, int nz) {
+  const int64_t n[3] = {nx, ny, nz};
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (llabs(D[k]) > llabs(D[ax])) ax = k;
+  const int a1 = ax == 2 ? 0 : ax + 1, a2 = ax == 0 ? 2 : ax - 1;
+  const double dax = (double)D[ax];
+  const double inv = 1.0 / fabs(dax);
+  const int b1 = min(2, (int)(((double)D[a1] * inv + 1.0) * 1.5));
+  const int b2 = min(2, (int)(((double)D[a2] * inv + 1.0) * 1.5));
+  const double t = (0.5 * (double)(n[ax] * kCellUnits) - (double)O[ax]) / dax;
+  const double N = (double)max(nx, max(ny, nz));
+  const double scale = 64.0 / (3.0 * N * (double)kCellUnits);
+  const double p1 = ((double)O[a1] + t * (double)D[a1] + N * kCellUnits) * scale;
+  const double p2 = ((double)O[a2] + t * (double)D[a2] + N * kCellUnits) * scale;
+  const uint32_t q1 = (uint32_t)fmin(63.0, fmax(0.0, p1));
+  const uint32_t q2 = (uint32_t)fmin(63.0, fmax(0.0, p2));
+  const uint32_t dir = (uint32_t)((ax * 2 + (D[ax] > 0)) * 9 + b1 * 3 + b2);
+  return dir * 4096u + (spread6(q1) | (spread6(q2) << 1));
+}
+
+__global__ void order_key_kernel(uint64_t seed, uint64_t begin, int64_t count, int nx, int ny,
+                                 int nz, uint32_t* keys, uint32_t* hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int64_t O[3], D[3];
+  sample_ray(seed, begin + (uint64_t)i, nx, ny, nz, O, D);
+  const uint32_t k = order_key(O, D, nx, ny, nz);
+  keys[i] = k;
+  atomicAdd(hist + k, 1u);
+}
+
+// Exclusive prefix sum of hist[0..n) in place; one block of 1024 threads,
+// each owning a contiguous run.
+__global__ __launch_bounds__(1024) void order_scan_kernel(uint32_t* hist, int n) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int run = (n + 1023) / 1024;
+  const int lo = min(n, t * run), hi = min(n, lo + run);
+  uint32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += hist[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t acc = part[t] - s;  // exclusive
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t v = hist[i];
+    hist[i] = acc;
+    acc += v;
+  }
+}
+
+__global__ void order_scatter_kernel(const uint32_t* __restrict__ keys, int64_t count,
+                                     uint32_t* offsets, uint32_t* perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  perm[atomicAdd(offsets + keys[i], 1u)] = (uint32_t)i;
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Slot i of the batch holds ray begin + perm[i] (begin + i without perm).
 __global__ void raygen_dda_kernel(uint64_t seed, uint64_t begin, int64_t count, int nx, int ny,
                                   int nz, double unit_cm, int max_segs,
                                   const int64_t* __restrict__ explicit_rays, int64_t* rays_out,
-                                  int2* segs, int32_t* counts, unsigned long long* seg_total) {
+                                  int2* segs, int32_t* counts, unsigned long long* seg_total,
+                                  const uint32_t* __restrict__ perm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int ns = 0;
   if (i < count) {
@@ -30,7 +118,7 @@ __global__ void raygen_dda_kernel(uint64_t seed, uint64_t begin, int64_t count, 
         D[k] = explicit_rays[6 * i + 3 + k];
       }
     } else {
-      sample_ray(seed, begin + (uint64_t)i, nx, ny, nz, O, D);
+      sample_ray(seed, begin + (perm ? (uint64_t)perm[i] : (uint64_t)i), nx, ny, nz, O, D);
     }
     if (rays_out)
       for (int k = 0; k < 3; ++k) {
@@ -49,7 +137,7 @@ __global__ void raygen_dda_kernel(uint64_t seed, uint64_t begin, int64_t count, 
 struct MarchArgs {
   MarchWave w;
   int n_chunks;
-  int64_t ray_blocks;
+  int64_t ray_blocks_x;  // ray blocks per XCD
   const int2* segs;
   const int32_t* counts;
   int max_segs;
@@ -58,14 +146,18 @@ struct MarchArgs {
   float* exit_I;
 };
 
-// Block = 4 wavefronts = 4 consecutive rays on one spectral chunk; blocks run
-// chunk-major so that the waves in flight share kappa[:, chunk].
+// Block = 4 wavefronts = 4 consecutive rays (batch slots) on one spectral
+// chunk.  Workgroups are dispatched to the 8 XCDs round-robin, so block b
+// runs on XCD b % 8; that XCD is given a contiguous range of ray blocks,
+// chunk-major, so the waves in flight on it march neighbouring rays of the
+// coherent order through one chunk and share kappa rows in its L2.
 template <bool PREC, bool EXIT>
 __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
   using PT = typename Partial<PREC>::T;
   const int64_t b = blockIdx.x;
-  const int chunk = (int)(b / a.ray_blocks);
-  const int64_t rb = b % a.ray_blocks;
+  const int64_t xcd = b & 7, local = b >> 3;
+  const int chunk = (int)(local / a.ray_blocks_x);
+  const int64_t rb = xcd * a.ray_blocks_x + local % a.ray_blocks_x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t ray = rb * 4 + wave;
@@ -114,15 +206,30 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
 
 static_assert(kSlots == 1024, "tally kernel assumes 1024 slots");
 
+hipError_t launch_order(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count) {
+  const int threads = 256;
+  const unsigned blocks = (unsigned)((count + threads - 1) / threads);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((kOrderBuckets + threads - 1) / threads), dim3(threads),
+                     0, c->stream, c->d_hist, (int64_t)kOrderBuckets);
+  hipLaunchKernelGGL(order_key_kernel, dim3(blocks), dim3(threads), 0, c->stream, seed, begin,
+                     count, c->nx, c->ny, c->nz, c->d_keys, c->d_hist);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(1024), 0, c->stream, c->d_hist,
+                     kOrderBuckets);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(threads), 0, c->stream, c->d_keys,
+                     count, c->d_hist, c->d_perm);
+  return hipGetLastError();
+}
+
 hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count,
-                         bool explicit_rays, int64_t* rays_out, bool count_work) {
+                         bool explicit_rays, int64_t* rays_out, bool count_work,
+                         const uint32_t* perm) {
   const int threads = 256;
   const int64_t blocks = (count + threads - 1) / threads;
   const double unit_cm = c->cell_m * 100.0 / (double)kCellUnits;
   hipLaunchKernelGGL(raygen_dda_kernel, dim3((unsigned)blocks), dim3(threads), 0, c->stream,
                      seed, begin, count, c->nx, c->ny, c->nz, unit_cm, c->max_segs,
                      explicit_rays ? c->d_rays_explicit : nullptr, rays_out, c->d_segs,
-                     c->d_counts, count_work ? c->d_segcount : nullptr);
+                     c->d_counts, count_work ? c->d_segcount : nullptr, perm);
   return hipGetLastError();
 }
 
@@ -141,14 +248,14 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float
   a.w.acc_abs = c->d_abs;
   a.w.acc_emi = c->d_emi;
   a.n_chunks = (int)(c->ld / kChunk);
-  a.ray_blocks = (count + 3) / 4;
+  a.ray_blocks_x = ((count + 3) / 4 + 7) / 8;
   a.segs = c->d_segs;
   a.counts = c->d_counts;
   a.max_segs = c->max_segs;
   a.n_rays = count;
   a.slots = c->d_slots;
   a.exit_I = exit_dev;
-  const int64_t blocks = a.ray_blocks * a.n_chunks;
+  const int64_t blocks = 8 * a.ray_blocks_x * a.n_chunks;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)blocks), t(256);
   if (prec) {

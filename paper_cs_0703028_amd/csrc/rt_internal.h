@@ -114,6 +114,9 @@ struct rt_ctx_s {
   int2* d_segs = nullptr;
   int32_t* d_counts = nullptr;
   int64_t* d_rays_explicit = nullptr;  // [n][6]: O(3), D(3)
+  uint32_t* d_keys = nullptr;   // coherent-order key per batch ray
+  uint32_t* d_perm = nullptr;   // batch slot -> ray offset in the batch
+  uint32_t* d_hist = nullptr;   // [kOrderBuckets] counts, then offsets
   int64_t explicit_cap = 0;
   float* d_exit = nullptr;
   int64_t exit_cap = 0;
@@ -128,13 +131,19 @@ struct rt_ctx_s {
 
 namespace rt {
 constexpr int kSlots = 1024;
+// Coherent ray order: 6 dominant directions x 3 x 3 transverse direction
+// bins x 64 x 64 positions on the mid-plane; used for batches of at least
+// kOrderMinRays rays.
+constexpr int kOrderBuckets = 6 * 9 * 4096;
+constexpr int64_t kOrderMinRays = int64_t(1) << 15;
 
 // kernel launchers (defined in the .hip files)
 hipError_t launch_cell_params(rt_ctx c);
 hipError_t launch_kappa(rt_ctx c, bool compensated);
 hipError_t launch_planck(rt_ctx c);
 hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,
-                         int64_t* rays_out, bool count_work);
+                         int64_t* rays_out, bool count_work, const uint32_t* perm);
+hipError_t launch_order(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count);
 hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev);
 hipError_t launch_tally(rt_ctx c);
 hipError_t launch_zero(rt_ctx c);
