@@ -93,9 +93,13 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   pl.cases.assign(n_cases, BatchCase());
   int64_t cell_off = 0, seg_off = 0, ray_off = 0, max_cells = 0;
   double evals = 0;
+  double T_min = INFINITY, T_max = 0;
   for (int k = 0; k < n_cases; ++k) {
     const rt_case& q = cases[k];
     BatchCase& b = pl.cases[k];
+    const int64_t nc = (int64_t)q.nx * q.ny * q.nz;
+    T_min = std::min(T_min, *std::min_element(q.T_K, q.T_K + nc));
+    T_max = std::max(T_max, *std::max_element(q.T_K, q.T_K + nc));
     b.nx = q.nx; b.ny = q.ny; b.nz = q.nz;
     b.max_segs = q.nx + q.ny + q.nz;
     b.n_cells = (int64_t)q.nx * q.ny * q.nz;
@@ -116,6 +120,7 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   }
   pl.total_cells = cell_off;
   pl.total_rays = ray_off;
+  pl.planck_quad = planck_needs_quadratic(T_min, T_max, c->nu0, c->dnu, c->n_nu);
   pl.max_cells = max_cells;
   pl.line_evals = limit_points > 0 ? 0.0 : evals;
   pl.slab_stride = max_cells * t.chunk_points;

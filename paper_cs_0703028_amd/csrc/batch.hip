@@ -79,6 +79,7 @@ __device__ __forceinline__ bool wait_count(const unsigned* p, unsigned target, u
   return true;
 }
 
+template <bool QUAD>
 __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
   __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
   __shared__ long long s_item;
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
       for (int sub = 0; sub < a.chunk_points / kChunk; ++sub) {
         const int64_t j = w.col0 + (int64_t)sub * kChunk + lane * kQ;
         float te, tx;
-        march_wave<false, false>(w, sg, ns, j, lane, nullptr, te, tx);
+        march_wave<false, false, QUAD>(w, sg, ns, j, lane, nullptr, te, tx);
         if (lane == 0) {
           const int s = (int)(r % kCaseSlots);
           unsafeAtomicAdd(cslots + s, w.weight * (double)te);
@@ -320,7 +321,10 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
   a.k_done = a.rg_done + pl.n_cases;
   a.m_done = a.k_done + pl.n_pairs;
   a.spin_limit = 1u << 24;
-  hipLaunchKernelGGL(batch_kernel, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
+  if (pl.planck_quad)
+    hipLaunchKernelGGL(batch_kernel<true>, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(batch_kernel<false>, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
   hipLaunchKernelGGL(case_tally_kernel, dim3((unsigned)pl.n_cases), dim3(256), 0, s, pl.d_cases,
                      pl.d_abs, pl.d_emi, pl.d_case_slots, pl.d_balance);
   return hipGetLastError();

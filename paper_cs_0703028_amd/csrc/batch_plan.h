@@ -32,6 +32,7 @@ struct BatchCase {
 struct BatchPlan {
   rt_batch_tuning tuning;
   bool comp = false;
+  bool planck_quad = true;  // second-order Planck expansion in the march
   int n_cases = 0, n_chunks = 0, n_pairs = 0, n_stages = 0;
   int64_t total_items = 0, total_cells = 0, total_rays = 0, max_cells = 0;
   int64_t grid_blocks = 0;

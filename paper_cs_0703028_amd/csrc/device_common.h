@@ -437,7 +437,10 @@ struct MarchWave {
   double* acc_emi;
 };
 
-template <bool PREC, bool EXIT>
+// QUAD: keep the second-order term of the per-lane Planck expansion (plain
+// form); the host drops it when its relative size over a lane's span is
+// below FP32 unit roundoff for every cell temperature and wavenumber.
+template <bool PREC, bool EXIT, bool QUAD = true>
 __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, int ns, int64_t j,
                                            int lane, float* exit_row,
                                            typename Partial<PREC>::T& enter_sum,
@@ -504,9 +507,14 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
       const float g1 = fmaf(-thf, t1, three_nu);
       const float g2 = fmaf(thf * thf, r * t1, -three_nu2);
       const float K1 = B0 * g1 * dnu_f;
-      const float K2 = 0.5f * B0 * fmaf(g1, g1, g2) * (dnu_f * dnu_f);
+      if (QUAD) {
+        const float K2 = 0.5f * B0 * fmaf(g1, g1, g2) * (dnu_f * dnu_f);
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) bv[q] = fmaf(fmaf(K2, (float)q, K1), (float)q, B0);
+        for (int q = 0; q < kQ; ++q) bv[q] = fmaf(fmaf(K2, (float)q, K1), (float)q, B0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) bv[q] = fmaf(K1, (float)q, B0);
+      }
     }
     float av[kQ];
     if (PREC) {
@@ -524,10 +532,15 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
         kmin = fminf(kmin, kv[q]);
       }
       if (__ballot(kmin * l < 0.0625f)) {
+        // tau < 1/16: a = tau - tau^2/2 + tau^3/6 written in x = -tau log2(e)
+        constexpr float L1 = -0.69314718055994531f, L2 = -0.24022650695910071f,
+                        L3 = -0.055504108664821580f;
+        constexpr float xlim = -0.0625f * 1.4426950408889634f;
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-          const float tau = kv[q] * l;
-          av[q] = tau < 0.0625f ? poly3(tau) : av[q];
+          const float x = kv[q] * xs;
+          const float ser = x * fmaf(x, fmaf(x, L3, L2), L1);
+          av[q] = x > xlim ? ser : av[q];
         }
       }
     }

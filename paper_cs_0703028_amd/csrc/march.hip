@@ -151,7 +151,7 @@ struct MarchArgs {
 // runs on XCD b % 8; that XCD is given a contiguous range of ray blocks,
 // chunk-major, so the waves in flight on it march neighbouring rays of the
 // coherent order through one chunk and share kappa rows in its L2.
-template <bool PREC, bool EXIT>
+template <bool PREC, bool EXIT, bool QUAD>
 __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
   using PT = typename Partial<PREC>::T;
   const int64_t b = blockIdx.x;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
   if (ray >= a.n_rays) return;
   const int64_t j = (int64_t)chunk * kChunk + lane * kQ;
   PT te, tx;
-  march_wave<PREC, EXIT>(a.w, a.segs + ray * a.max_segs, a.counts[ray], j, lane,
+  march_wave<PREC, EXIT, QUAD>(a.w, a.segs + ray * a.max_segs, a.counts[ray], j, lane,
                          EXIT ? a.exit_I + ray * a.w.ld : nullptr, te, tx);
   if (lane == 0) {
     const int slot = (int)(b % kSlots);
@@ -233,6 +233,30 @@ hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count,
   return hipGetLastError();
 }
 
+// The plain march expands B(nu_a + s) = B0 (1 + g1 s + (g1^2 + g2) s^2 / 2
+// + ...) about a lane's first point nu_a, s <= (kQ - 1) dnu, with
+// g1 = d ln B / d nu = 3/nu - theta (1 + r), g2 = d g1 / d nu
+// = -3/nu^2 + theta^2 r (1 + r), theta = c2/T, r = 1/(exp(theta nu) - 1).
+// The second-order term is needed unless its relative size stays below FP32
+// unit roundoff (2^-24) over the grid's temperatures and wavenumbers
+// (checked at the extremes and midpoints of both ranges).
+bool planck_needs_quadratic(double T_min, double T_max, double nu0, double dnu, int n_nu) {
+  const double c2 = second_radiation_cm_K();
+  const double span = (kQ - 1) * dnu;
+  const double nu_lo = nu0, nu_hi = nu0 + (n_nu - 1) * dnu;
+  const double Ts[3] = {T_min, T_max, std::sqrt(T_min * T_max)};
+  const double nus[3] = {nu_lo, nu_hi, 0.5 * (nu_lo + nu_hi)};
+  double worst = 0;
+  for (double T : Ts)
+    for (double nu : nus) {
+      const double th = c2 / T, r = 1.0 / std::expm1(th * nu);
+      const double g1 = 3.0 / nu - th * (1.0 + r);
+      const double g2 = -3.0 / (nu * nu) + th * th * r * (1.0 + r);
+      worst = std::max(worst, 0.5 * std::fabs(g1 * g1 + g2) * span * span);
+    }
+  return !(worst < std::ldexp(1.0, -24));
+}
+
 hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev) {
   MarchArgs a;
   a.w.kappa = c->kappa;
@@ -259,11 +283,14 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)blocks), t(256);
   if (prec) {
-    if (exit_dev) hipLaunchKernelGGL((march_kernel<true, true>), g, t, 0, c->stream, a);
-    else hipLaunchKernelGGL((march_kernel<true, false>), g, t, 0, c->stream, a);
+    if (exit_dev) hipLaunchKernelGGL((march_kernel<true, true, true>), g, t, 0, c->stream, a);
+    else hipLaunchKernelGGL((march_kernel<true, false, true>), g, t, 0, c->stream, a);
+  } else if (planck_needs_quadratic(c->T_min, c->T_max, c->nu0, c->dnu, c->n_nu)) {
+    if (exit_dev) hipLaunchKernelGGL((march_kernel<false, true, true>), g, t, 0, c->stream, a);
+    else hipLaunchKernelGGL((march_kernel<false, false, true>), g, t, 0, c->stream, a);
   } else {
-    if (exit_dev) hipLaunchKernelGGL((march_kernel<false, true>), g, t, 0, c->stream, a);
-    else hipLaunchKernelGGL((march_kernel<false, false>), g, t, 0, c->stream, a);
+    if (exit_dev) hipLaunchKernelGGL((march_kernel<false, true, false>), g, t, 0, c->stream, a);
+    else hipLaunchKernelGGL((march_kernel<false, false, false>), g, t, 0, c->stream, a);
   }
   return hipGetLastError();
 }

@@ -75,6 +75,7 @@ struct rt_ctx_s {
 
   // grid
   bool have_grid = false;
+  double T_min = 0, T_max = 0;  // cell temperature range of the grid
   int nx = 0, ny = 0, nz = 0;
   int64_t n_cells = 0;
   double cell_m = 0, T_wall = 0;
@@ -144,6 +145,8 @@ hipError_t launch_planck(rt_ctx c);
 hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,
                          int64_t* rays_out, bool count_work, const uint32_t* perm);
 hipError_t launch_order(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count);
+// whether the plain march needs the second-order term of its Planck expansion
+bool planck_needs_quadratic(double T_min, double T_max, double nu0, double dnu, int n_nu);
 hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev);
 hipError_t launch_tally(rt_ctx c);
 hipError_t launch_zero(rt_ctx c);
