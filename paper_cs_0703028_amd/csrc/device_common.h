@@ -355,16 +355,19 @@ __device__ __forceinline__ double dpp_f64(double v) {
 }
 
 // Sum over the 64 lanes: butterflies inside each row of 16 (quad
-// permutations, half-row and row mirrors), then the row totals are combined
-// with the row broadcasts; lane 63 ends with the total, which is returned
-// to every lane.  Disabled rows receive 0, so the adds are no-ops there.
+// permutations, half-row and row mirrors) leave every lane of row k with the
+// row total r_k.  Row broadcasts then combine the rows, with all rows
+// enabled so that each step is a single DPP add: after row_bcast:15 row 1
+// holds r0 + r1 and row 3 holds r2 + r3 (row 0 takes no source lane and
+// receives 0); after row_bcast:31 row 3 holds r0 + r1 + r2 + r3.  Only
+// lane 63 is read, so what rows 0-2 end with does not matter.
 __device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_f32<0xB1>(v);        // quad_perm [1,0,3,2]
-  v += dpp_f32<0x4E>(v);        // quad_perm [2,3,0,1]
-  v += dpp_f32<0x141>(v);       // row_half_mirror
-  v += dpp_f32<0x140>(v);       // row_mirror
-  v += dpp_f32<0x142, 0xA>(v);  // row_bcast:15 -> rows 1, 3
-  v += dpp_f32<0x143, 0xC>(v);  // row_bcast:31 -> rows 2, 3
+  v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f32<0x141>(v);  // row_half_mirror
+  v += dpp_f32<0x140>(v);  // row_mirror
+  v += dpp_f32<0x142>(v);  // row_bcast:15
+  v += dpp_f32<0x143>(v);  // row_bcast:31
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 __device__ __forceinline__ double wave_sum(double v) {
@@ -372,8 +375,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_f64<0x4E>(v);
   v += dpp_f64<0x141>(v);
   v += dpp_f64<0x140>(v);
-  v += dpp_f64<0x142, 0xA>(v);
-  v += dpp_f64<0x143, 0xC>(v);
+  v += dpp_f64<0x142>(v);
+  v += dpp_f64<0x143>(v);
   int2 h = *reinterpret_cast<int2*>(&v);
   int2 r;
   r.x = __builtin_amdgcn_readlane(h.x, 63);
@@ -384,22 +387,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 // a = 1 - e^{-tau} for tau >= 0, two accuracy levels.
 //   precision form: degree-5 Taylor polynomial of (1 - e^{-tau})/tau below
 //     tau = 1/4 (truncation < 5e-8), 1 - 2^{-tau log2 e} above (<= 5e-7);
-//   plain form: degree-3 polynomial below tau = 1/16 (truncation < 1.3e-7),
+//   plain form (in march_wave): the same series to tau^4 below tau = 1/16
+//     (truncation < 1.3e-7), written in the exponent argument, and
 //     1 - 2^{-tau log2 e} above (<= 2e-6 just above the switch, falling as
-//     1/tau), and the polynomial is skipped by the whole wavefront when no
-//     lane needs it.
+//     1/tau); the series is skipped by the whole wavefront when no lane
+//     needs it.
 // The exponent is folded into base 2 per segment, as the paper's listing
 // folds 1/ln 2 into the per-volume scalar.
 __device__ __forceinline__ float poly5(float tau) {
   float p = fmaf(tau, -1.0f / 720.0f, 1.0f / 120.0f);
   p = fmaf(tau, p, -1.0f / 24.0f);
   p = fmaf(tau, p, 1.0f / 6.0f);
-  p = fmaf(tau, p, -0.5f);
-  p = fmaf(tau, p, 1.0f);
-  return tau * p;
-}
-__device__ __forceinline__ float poly3(float tau) {
-  float p = fmaf(tau, -1.0f / 24.0f, 1.0f / 6.0f);
   p = fmaf(tau, p, -0.5f);
   p = fmaf(tau, p, 1.0f);
   return tau * p;
@@ -532,14 +530,16 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
         kmin = fminf(kmin, kv[q]);
       }
       if (__ballot(kmin * l < 0.0625f)) {
-        // tau < 1/16: a = tau - tau^2/2 + tau^3/6 written in x = -tau log2(e)
+        // tau < 1/16: a = tau - tau^2/2 + tau^3/6 - tau^4/24 written in
+        // x = -tau log2(e), i.e. a = -sum_k (x ln 2)^k / k!, k = 1..4
+        // (truncation below 1.3e-7 relative)
         constexpr float L1 = -0.69314718055994531f, L2 = -0.24022650695910071f,
-                        L3 = -0.055504108664821580f;
+                        L3 = -0.055504108664821576f, L4 = -0.0096181291076284772f;
         constexpr float xlim = -0.0625f * 1.4426950408889634f;
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
           const float x = kv[q] * xs;
-          const float ser = x * fmaf(x, fmaf(x, L3, L2), L1);
+          const float ser = x * fmaf(x, fmaf(x, fmaf(x, L4, L3), L2), L1);
           av[q] = x > xlim ? ser : av[q];
         }
       }

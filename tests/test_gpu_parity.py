@@ -234,3 +234,54 @@ def test_full_size_32cube_sampled(rt, O):
     _say(f"  absorbed max rel {ra.max():.3e}, emitted {re.max():.3e}")
     assert ra.max() <= REL and re.max() <= REL
     t.close()
+
+
+def test_coherent_order_matches_natural_order(rt):
+    """A batch of >= 2^15 rays is marched in the coherent (sorted) order; the
+    same rays traced in pieces below that size run in index order.  Only the
+    order of the FP64 tally additions may differ."""
+    w = I.plain_8cube()
+    n = 1 << 16
+    t = _tracer(rt, w)
+    t.compute_kappa(0)
+    _say(f"coherent order: {n} rays in one call")
+    t.trace_rays(w.seed, n, 0, n)
+    a1, e1, b1 = t.tally()
+    t.reset_tally()
+    _say("natural order: 4 calls of 2^14 rays")
+    for b in range(0, n, 1 << 14):
+        t.trace_rays(w.seed, n, b, 1 << 14)
+    a2, e2, b2 = t.tally()
+    assert (a1 > 0).sum() == (a2 > 0).sum()
+    np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(e1, e2, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(b1, b2, rtol=1e-12, atol=0)
+    t.close()
+
+
+def test_quadratic_planck_expansion_path(rt, O):
+    """With a coarse spectral step the plain march keeps the second-order
+    term of its per-lane Planck expansion; tallies still match the oracle."""
+    w = I.small_ragged()
+    w = I.with_lines(w, dnu=0.05, n_nu=700)
+    # relative size of the second-order term over a lane's 15 steps
+    c2, span = 1.438776877, 15 * w.lines.dnu
+    worst = 0.0
+    for T in (w.grid.T.min(), w.grid.T.max()):
+        for nu in (w.lines.nu0, w.lines.nu0 + (w.lines.n_nu - 1) * w.lines.dnu):
+            th = c2 / T
+            r = 1.0 / math.expm1(th * nu)
+            g1 = 3.0 / nu - th * (1 + r)
+            g2 = -3.0 / nu ** 2 + th * th * r * (1 + r)
+            worst = max(worst, 0.5 * abs(g1 * g1 + g2) * span * span)
+    assert worst > 2.0 ** -24, "workload must need the quadratic term"
+    t = _tracer(rt, w)
+    t.compute_kappa(0)
+    t.trace_rays(w.seed, w.n_rays)
+    ag, eg, _ = t.tally()
+    res = O.run(w.grid, w.lines, w.n_rays, seed=w.seed)
+    ra = _rel(ag, res["absorbed"])
+    re = _rel(eg, res["emitted"])
+    _say(f"  quadratic Planck: absorbed max {ra.max():.3e}, emitted {re.max():.3e}")
+    assert ra.max() <= REL and re.max() <= REL
+    t.close()
