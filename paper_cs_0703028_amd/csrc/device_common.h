@@ -4,6 +4,8 @@
 // one wavefront over one spectral chunk of one ray.
 #pragma once
 
+#include <type_traits>
+
 #include "rt_internal.h"
 
 namespace rt {
@@ -11,7 +13,7 @@ namespace dev {
 
 constexpr int kKappaThreads = 256;
 constexpr int kLineTile = 256;
-constexpr int kKappaCells = 4;   // cells per lane in the line sum
+constexpr int kKappaCells = 8;   // cells per lane in the line sum
 constexpr int kKappaPoints = 2;  // nu points per lane in the line sum
 constexpr int kKappaTilePoints = kKappaThreads * kKappaPoints;
 constexpr int kQ = kChunk / 64;  // contiguous nu points per lane in the march
@@ -124,12 +126,66 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
   for (int p = 0; p < P; ++p) jf[p] = (float)(wj0 + 64 * p + lane);
   const float Kf = (float)a.K;
 
+  // windows are non-decreasing along the sorted list, so the lines whose
+  // window covers [wj0, wj0 + span) are the contiguous range [f_first, f_end)
+  const int f_first = first_ge(a.L.whi, nl, wj0 + span - 1);
+  const int f_end = first_gt(a.L.wlo, nl, wj0);
+
   float acc[P][C];
   float cmp[P][C];
 #pragma unroll
   for (int p = 0; p < P; ++p)
 #pragma unroll
     for (int c = 0; c < C; ++c) { acc[p][c] = 0.f; cmp[p][c] = 0.f; }
+
+  // Adds lines [l0, l1) of the staged tile starting at line `base`.  FULL:
+  // every point is inside the window.  Otherwise a point outside it gets an
+  // infinite offset, whose reciprocal term is 0.  COMP: blocks of 16 lines
+  // are summed plainly and folded into (acc, cmp) with TwoSum.
+  auto sum_lines = [&](auto full_tag, int base, int l0, int l1) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    for (int s0 = l0; s0 < l1;) {
+      const int s1 = COMP ? min(s0 + 16, l1) : l1;
+      float part[P][C];
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int c = 0; c < C; ++c) part[p][c] = COMP ? 0.f : acc[p][c];
+      for (int l = s0; l < s1; ++l) {
+        const float* rec = lds + (l - base) * REC;
+        const float4 h = *reinterpret_cast<const float4*>(rec);
+        float dv[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const float t = jf[p] - h.x;
+          const float d = t - h.y;
+          if (FULL) {
+            dv[p] = d;
+          } else {
+            const bool in = (t >= h.z) & (t <= Kf);
+            dv[p] = in ? d : __builtin_inff();
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < C; c += 2) {
+          const float4 ag = *reinterpret_cast<const float4*>(rec + 4 + 2 * c);
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            part[p][c] = fmaf(ag.x, fast_rcp(fmaf(dv[p], dv[p], ag.y)), part[p][c]);
+            part[p][c + 1] = fmaf(ag.z, fast_rcp(fmaf(dv[p], dv[p], ag.w)), part[p][c + 1]);
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          if (COMP) two_sum_acc(acc[p][c], cmp[p][c], part[p][c]);
+          else acc[p][c] = part[p][c];
+        }
+      s0 = s1;
+    }
+  };
 
   for (int base = blk_first; base < blk_end; base += kLineTile) {
     const int nt = min(kLineTile, blk_end - base);
@@ -159,44 +215,11 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
     __syncthreads();
 
     const int lb = max(base, w_first), le = min(base + nt, w_end);
-    const int step = COMP ? 16 : 0x7fffffff;
-    // COMP: blocks of 16 lines summed plainly, then folded in with TwoSum
-    for (int l0 = lb; l0 < le; l0 += step) {
-      const int l1 = COMP ? min(l0 + 16, le) : le;
-      float part[P][C];
-#pragma unroll
-      for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int c = 0; c < C; ++c) part[p][c] = COMP ? 0.f : acc[p][c];
-      for (int l = l0; l < l1; ++l) {
-        const float* rec = lds + (l - base) * REC;
-        const float4 h = *reinterpret_cast<const float4*>(rec);
-        float dd[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          const float t = jf[p] - h.x;
-          const float d = t - h.y;
-          const bool in = (t >= h.z) & (t <= Kf);
-          dd[p] = in ? d * d : __builtin_inff();
-        }
-#pragma unroll
-        for (int c = 0; c < C; c += 2) {
-          const float4 ag = *reinterpret_cast<const float4*>(rec + 4 + 2 * c);
-#pragma unroll
-          for (int p = 0; p < P; ++p) {
-            part[p][c] = fmaf(ag.x, fast_rcp(dd[p] + ag.y), part[p][c]);
-            part[p][c + 1] = fmaf(ag.z, fast_rcp(dd[p] + ag.w), part[p][c + 1]);
-          }
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          if (COMP) two_sum_acc(acc[p][c], cmp[p][c], part[p][c]);
-          else acc[p][c] = part[p][c];
-        }
-    }
+    // lines [f_first, f_end) cover all of the wave's points: no membership test
+    const int fb = min(le, max(lb, f_first)), fe = max(fb, min(le, f_end));
+    sum_lines(std::false_type(), base, lb, fb);
+    sum_lines(std::true_type(), base, fb, fe);
+    sum_lines(std::false_type(), base, fe, le);
   }
 
 #pragma unroll

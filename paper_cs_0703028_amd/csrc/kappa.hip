@@ -2,7 +2,7 @@
 //
 //   cell_params   : per-cell gas state -> FP32/FP64 factors (FP64 arithmetic)
 //   kappa_linesum : Eq. (2) with the Eq. (1) strength ratio (line tiles staged
-//                   in LDS, each lane owns 2 nu points of 4 cells, kappa
+//                   in LDS, each lane owns 2 nu points of 8 cells, kappa
 //                   written coalesced along nu; see dev::kappa_tile)
 //   planck_table  : Eq. (4), wavenumber form, per (cell, nu) and for the walls
 #include "batch_plan.h"
