@@ -197,6 +197,7 @@ def form_batched(rtlbl, I):
     big = rtlbl.Tracer.default_tuning()
     big.chunk_points = 4096
     big.blocks_per_cu = 4
+    big.slots = 8
     ws = torch.empty(t.batch_workspace_size(cases, big), dtype=torch.uint8, device="cuda")
     t0 = time.perf_counter()
     best = t.batch_autotune(cases, rtlbl.KAPPA_PLAIN, ws, TUNING_CACHE)

@@ -202,7 +202,7 @@ typedef struct {
 
 typedef struct {
   int chunk_points;   /* nu points per (case, chunk) pair, multiple of 1024 */
-  int kappa_groups;   /* groups of 4 cells per line-sum work item, >= 1     */
+  int kappa_groups;   /* groups of 8 cells per line-sum work item, >= 1     */
   int march_rays;     /* rays per march work item, multiple of 4            */
   int blocks_per_cu;  /* persistent blocks per compute unit, 1..8           */
   int slots;          /* kappa slabs in flight, 2..8                        */
@@ -238,7 +238,7 @@ rt_status rt_batch_launch(rt_ctx ctx);
 rt_status rt_batch_results(rt_ctx ctx, double* absorbed_W, double* emitted_W,
                            double* balance);
 
-/* Picks chunk_points, kappa_groups, march_rays and blocks_per_cu by timing
+/* Picks chunk_points, kappa_groups, march_rays, blocks_per_cu and slots by timing
  * launches restricted to the first spectral chunks of every case (a sweep
  * one parameter at a time from the default), and remembers the winner in a
  * JSON file keyed by device architecture and a bucket of the batch shape

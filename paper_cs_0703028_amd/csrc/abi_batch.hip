@@ -152,9 +152,13 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
     const BatchCase& b = pl.cases[pair_case(p)];
     m_stage[p] = add(kStageMarch, pair_case(p), pair_chunk(p), p, (b.n_rays + t.march_rays - 1) / t.march_rays);
   };
-  add_k(0);
+  // software pipeline over the slab ring: the line sums run slots - 1 pairs
+  // ahead of the march, K(0) .. K(L-1), then K(p + L) M(p) for every p, with
+  // L = slots - 1; K(p + L) reuses the slab of M(p - 1), which precedes it
+  const int L = std::max(1, t.slots - 1);
+  for (int p = 0; p < std::min(L, pl.n_pairs); ++p) add_k(p);
   for (int p = 0; p < pl.n_pairs; ++p) {
-    if (p + 1 < pl.n_pairs) add_k(p + 1);
+    if (p + L < pl.n_pairs) add_k(p + L);
     add_m(p);
   }
   for (int p = 0; p < pl.n_pairs; ++p) {
@@ -184,6 +188,8 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   int64_t o_cs = take((int64_t)n_cases * 2 * kCaseSlots * 8), o_bal = take((int64_t)n_cases * 4 * 8);
   int64_t o_bw = take((int64_t)n_cases * pl.bwall_ld * 4);
   int64_t o_segs = take(seg_off * 8), o_cnt = take(ray_off * 4);
+  int64_t o_keys = take(ray_off * 4), o_perm = take(ray_off * 4);
+  int64_t o_hist = take((int64_t)n_cases * kOrderBuckets * 4);
   int64_t o_slab = take((int64_t)t.slots * pl.slab_stride * 4);
   int64_t o_ctr = take(pl.n_counters * 4);
   int64_t o_st = take((int64_t)pl.n_stages * sizeof(BatchStage));
@@ -206,6 +212,9 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   pl.d_bwall = reinterpret_cast<float*>(o_bw);
   pl.d_segs = reinterpret_cast<int2*>(o_segs);
   pl.d_counts = reinterpret_cast<int32_t*>(o_cnt);
+  pl.d_keys = reinterpret_cast<uint32_t*>(o_keys);
+  pl.d_perm = reinterpret_cast<uint32_t*>(o_perm);
+  pl.d_hist = reinterpret_cast<uint32_t*>(o_hist);
   pl.d_slabs = reinterpret_cast<float*>(o_slab);
   pl.d_counters = reinterpret_cast<unsigned*>(o_ctr);
   pl.d_stages = reinterpret_cast<BatchStage*>(o_st);
@@ -223,6 +232,7 @@ void carve(BatchPlan& pl, void* ws) {
   rebase(pl.cells.lam2, b); rebase(pl.cells.P, b);
   rebase(pl.d_abs, b); rebase(pl.d_emi, b); rebase(pl.d_case_slots, b); rebase(pl.d_balance, b);
   rebase(pl.d_bwall, b); rebase(pl.d_segs, b); rebase(pl.d_counts, b); rebase(pl.d_slabs, b);
+  rebase(pl.d_keys, b); rebase(pl.d_perm, b); rebase(pl.d_hist, b);
   rebase(pl.d_counters, b); rebase(pl.d_stages, b); rebase(pl.d_cases, b);
 }
 
@@ -302,7 +312,7 @@ std::string shape_key(rt_ctx c, int n_cases, const rt_case* cases) {
     rays += (double)cases[k].n_rays;
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
+  std::snprintf(buf, sizeof(buf), "v2|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
                 arch_name(c).c_str(), n_cases, (int)std::lround(std::log2(cells)),
                 (int)std::lround(std::log2(rays)), c->n_nu,
                 (int)std::lround(std::log2((double)std::max(1, c->lines.n))));
@@ -471,13 +481,15 @@ rt_status rt_batch_autotune(rt_ctx c, int n_cases, const rt_case* cases, int kap
   const int groups[] = {4, 16, 64};
   const int rays[] = {16, 64, 256};
   const int bpc[] = {1, 2, 4};
-  for (int param = 0; param < 4; ++param) {
+  const int slots[] = {2, 4, 8};
+  for (int param = 0; param < 5; ++param) {
     for (int v = 0; v < 3; ++v) {
       rt_batch_tuning t = cur;
       if (param == 0) t.chunk_points = chunks[v];
       if (param == 1) t.kappa_groups = groups[v];
       if (param == 2) t.march_rays = rays[v];
       if (param == 3) t.blocks_per_cu = bpc[v];
+      if (param == 4) t.slots = slots[v];
       if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
       double ms = -1;
       if (rt_status s = trial(t, &ms)) return s;

@@ -46,6 +46,7 @@ struct BatchArgs {
   int slots;
   int2* segs;
   int32_t* counts;
+  const uint32_t* perm;  // per case: slot -> ray index (coherent order)
   const float* bwall;  // [case][bwall_ld]
   int64_t bwall_ld;
   double* acc_abs;
@@ -105,10 +106,11 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
     if (!s_ok) continue;  // a wait timed out somewhere: drain the queue
 
     if (st.kind == kStageRaygen) {
+      // slot r of the case holds ray perm[r] of the coherent order
       const int64_t r = local * 256 + tid;
       if (r < cs.n_rays) {
         int64_t O[3], D[3];
-        sample_ray(cs.seed, (uint64_t)r, cs.nx, cs.ny, cs.nz, O, D);
+        sample_ray(cs.seed, (uint64_t)a.perm[cs.ray_off + r], cs.nx, cs.ny, cs.nz, O, D);
         const int ns = traverse(cs.nx, cs.ny, cs.nz, cs.unit_cm, O, D, cs.max_segs,
                                 a.segs + cs.seg_off + r * cs.max_segs);
         a.counts[cs.ray_off + r] = ns;
@@ -241,6 +243,66 @@ __global__ __launch_bounds__(256) void case_tally_kernel(const BatchCase* cases,
   if (t < 4) balance[4 * blockIdx.x + t] = red[t][0];
 }
 
+// Coherent ray order per case (see order_key): counting sort of every
+// case's rays by key, run before the persistent kernel in the same graph.
+__device__ __forceinline__ int case_of_ray(const BatchCase* cases, int n_cases, int64_t r) {
+  int lo = 0, hi = n_cases - 1;  // last case with ray_off <= r
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cases[mid].ray_off <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void batch_order_key_kernel(const BatchCase* __restrict__ cases, int n_cases,
+                                       int64_t total_rays, uint32_t* keys, uint32_t* hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total_rays) return;
+  const int k = case_of_ray(cases, n_cases, i);
+  const BatchCase cs = cases[k];
+  int64_t O[3], D[3];
+  sample_ray(cs.seed, (uint64_t)(i - cs.ray_off), cs.nx, cs.ny, cs.nz, O, D);
+  const uint32_t key = order_key(O, D, cs.nx, cs.ny, cs.nz);
+  keys[i] = key;
+  atomicAdd(hist + (int64_t)k * kOrderBuckets + key, 1u);
+}
+
+// one block of 1024 threads per case: exclusive prefix sum of its histogram
+__global__ __launch_bounds__(1024) void batch_order_scan_kernel(uint32_t* hist) {
+  __shared__ uint32_t part[1024];
+  uint32_t* h = hist + (int64_t)blockIdx.x * kOrderBuckets;
+  const int t = threadIdx.x;
+  constexpr int run = (kOrderBuckets + 1023) / 1024;
+  const int lo = min(kOrderBuckets, t * run), hi = min(kOrderBuckets, lo + run);
+  uint32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += h[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t acc = part[t] - s;
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t v = h[i];
+    h[i] = acc;
+    acc += v;
+  }
+}
+
+__global__ void batch_order_scatter_kernel(const BatchCase* __restrict__ cases, int n_cases,
+                                           int64_t total_rays, const uint32_t* __restrict__ keys,
+                                           uint32_t* hist, uint32_t* perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total_rays) return;
+  const int k = case_of_ray(cases, n_cases, i);
+  const int64_t off = cases[k].ray_off;
+  const uint32_t pos = atomicAdd(hist + (int64_t)k * kOrderBuckets + keys[i], 1u);
+  perm[off + pos] = (uint32_t)(i - off);
+}
+
 __global__ void fill_u32_kernel(unsigned* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -284,6 +346,14 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
     hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
   };
   fill_u(pl.d_counters, pl.n_counters);
+  fill_u(pl.d_hist, (int64_t)pl.n_cases * kOrderBuckets);
+  const unsigned ray_blocks = (unsigned)((pl.total_rays + 255) / 256);
+  hipLaunchKernelGGL(batch_order_key_kernel, dim3(ray_blocks), dim3(256), 0, s, pl.d_cases,
+                     pl.n_cases, pl.total_rays, pl.d_keys, pl.d_hist);
+  hipLaunchKernelGGL(batch_order_scan_kernel, dim3((unsigned)pl.n_cases), dim3(1024), 0, s,
+                     pl.d_hist);
+  hipLaunchKernelGGL(batch_order_scatter_kernel, dim3(ray_blocks), dim3(256), 0, s, pl.d_cases,
+                     pl.n_cases, pl.total_rays, pl.d_keys, pl.d_hist, pl.d_perm);
   fill_d(pl.d_abs, pl.total_cells);
   fill_d(pl.d_emi, pl.total_cells);
   fill_d(pl.d_case_slots, (int64_t)pl.n_cases * 2 * kCaseSlots);
@@ -307,6 +377,7 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
   a.slots = pl.tuning.slots;
   a.segs = pl.d_segs;
   a.counts = pl.d_counts;
+  a.perm = pl.d_perm;
   a.bwall = pl.d_bwall;
   a.bwall_ld = pl.bwall_ld;
   a.acc_abs = pl.d_abs;

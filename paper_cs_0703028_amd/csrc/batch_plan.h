@@ -48,6 +48,9 @@ struct BatchPlan {
   float* d_bwall = nullptr;
   int2* d_segs = nullptr;
   int32_t* d_counts = nullptr;
+  uint32_t* d_keys = nullptr;  // coherent-order key per ray (all cases)
+  uint32_t* d_perm = nullptr;  // case-local slot -> case-local ray index
+  uint32_t* d_hist = nullptr;  // [n_cases][kOrderBuckets] counts, then offsets
   float* d_slabs = nullptr;
   unsigned* d_counters = nullptr;  // [queue lo, queue hi, error, pad, rg_done..., k_done..., m_done...]
   BatchStage* d_stages = nullptr;

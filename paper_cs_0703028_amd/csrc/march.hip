@@ -18,42 +18,6 @@ namespace {
 
 using namespace dev;
 
-// ------------------------------------------------------------ ray order
-// Rays that run nearly parallel through nearby cells read the same kappa
-// rows.  Marching them together (and on one XCD, see march_kernel) lets those
-// rows be served from L2 instead of beyond it.  The key is the dominant axis
-// and sign of D, a 3 x 3 bin of the two transverse direction ratios, and the
-// Morton index (6 bits per axis) of the point where the ray's line crosses
-// the grid's mid-plane normal to the dominant axis, over [-N, 2N] cells.
-// The order changes only the order of the FP64 tally additions.
-__device__ __forceinline__ uint32_t spread6(uint32_t v) {  // bits 0..5 -> even bits
-  v = (v | (v << 4)) & 0x30fu;
-  v = (v | (v << 2)) & 0x333u;
-  v = (v | (v << 1)) & 0x555u;
-  return v;
-}
-
-__device__ uint32_t order_key(const int64_t O[3], const int64_t D[3], int nx, int ny, int nz) {
-  const int64_t n[3] = {nx, ny, nz};
-  int ax = 0;
-  for (int k = 1; k < 3; ++k)
-    if (llabs(D[k]) > llabs(D[ax])) ax = k;
-  const int a1 = ax == 2 ? 0 : ax + 1, a2 = ax == 0 ? 2 : ax - 1;
-  const double dax = (double)D[ax];
-  const double inv = 1.0 / fabs(dax);
-  const int b1 = min(2, (int)(((double)D[a1] * inv + 1.0) * 1.5));
-  const int b2 = min(2, (int)(((double)D[a2] * inv + 1.0) * 1.5));
-  const double t = (0.5 * (double)(n[ax] * kCellUnits) - (double)O[ax]) / dax;
-  const double N = (double)max(nx, max(ny, nz));
-  const double scale = 64.0 / (3.0 * N * (double)kCellUnits);
-  const double p1 = ((double)O[a1] + t * (double)D[a1] + N * kCellUnits) * scale;
-  const double p2 = ((double)O[a2] + t * (double)D[a2] + N * kCellUnits) * scale;
-  const uint32_t q1 = (uint32_t)fmin(63.0, fmax(0.0, p1));
-  const uint32_t q2 = (uint32_t)fmin(63.0, fmax(0.0, p2));
-  const uint32_t dir = (uint32_t)((ax * 2 + (D[ax] > 0)) * 9 + b1 * 3 + b2);
-  return dir * 4096u + (spread6(q1) | (spread6(q2) << 1));
-}
-
 __global__ void order_key_kernel(uint64_t seed, uint64_t begin, int64_t count, int nx, int ny,
                                  int nz, uint32_t* keys, uint32_t* hist) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
