@@ -275,7 +275,7 @@ typedef struct {
   int batch;                  /* rows per Adam step, multiple of 64        */
   float lr;                   /* initial Adam step (cosine decay)          */
   uint64_t seed;              /* weight initialisation and shuffling       */
-  int check_cells;            /* cells sampled per inference check (>= 0)  */
+  int check_cells;            /* cells sampled per inference check, 0..256 */
   double tolerance;           /* checked absorptance error for fallback    */
 } rt_surrogate_cfg;
 

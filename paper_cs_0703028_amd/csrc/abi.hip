@@ -235,8 +235,11 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   c->n_cells = n;
   c->cell_m = cell_m;
   c->T_wall = T_wall;
-  c->T_min = *std::min_element(T, T + n);
-  c->T_max = *std::max_element(T, T + n);
+  c->T_argmin = std::min_element(T, T + n) - T;
+  c->T_argmax = std::max_element(T, T + n) - T;
+  c->T_min = T[c->T_argmin];
+  c->T_max = T[c->T_argmax];
+  c->grid_epoch += 1;
   c->have_grid = true;
   c->stats = rt::Stats();
   RT_HIP(c, rt::launch_zero(c));

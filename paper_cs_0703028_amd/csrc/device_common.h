@@ -105,6 +105,19 @@ struct KappaTile {
   int compact_rows = 0;                // with a list: write row i instead of cell_list[i]
 };
 
+// Optional device-side gating of a launch of line-sum tiles, decided per
+// block before any barrier: a block runs if its group of cells is marked
+// with the current epoch in group_flag, or if one of the width-chunk_w
+// spectral chunks its tile touches has chunk_err above tol.
+struct TileGate {
+  const unsigned* group_flag = nullptr;
+  unsigned epoch = 0;
+  const float* chunk_err = nullptr;
+  float tol = 0;
+  int chunk_w = 0;
+  int n_chunks = 0;
+};
+
 template <bool COMP>
 __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds) {
   constexpr int C = kKappaCells, P = kKappaPoints;

@@ -38,6 +38,7 @@ struct KappaArgs {
   KappaTile t;
   int n_tiles;
   int tile_begin;
+  TileGate gate;
 };
 
 template <bool COMP>
@@ -45,8 +46,17 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs 
   __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
   const int tile = blockIdx.x % a.n_tiles;
   const int64_t cg = blockIdx.x / a.n_tiles;
-  kappa_tile<COMP>(a.t, (a.tile_begin + tile) * kKappaTilePoints, cg * kKappaCells,
-                   reinterpret_cast<float*>(lds4));
+  const int j0 = (a.tile_begin + tile) * kKappaTilePoints;
+  if (a.gate.group_flag || a.gate.chunk_err) {
+    bool need = a.gate.group_flag && a.gate.group_flag[cg] == a.gate.epoch;
+    if (a.gate.chunk_err) {
+      const int c0 = j0 / a.gate.chunk_w;
+      const int c1 = min(a.gate.n_chunks - 1, (j0 + kKappaTilePoints - 1) / a.gate.chunk_w);
+      for (int k = c0; k <= c1; ++k) need = need || a.gate.chunk_err[k] > a.gate.tol;
+    }
+    if (!need) return;
+  }
+  kappa_tile<COMP>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
 }
 
 // Eq. (4): B = c1 nu^3 / (exp(c2 nu / T) - 1), evaluated in FP64 and stored
@@ -130,9 +140,11 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
 }
 
 hipError_t launch_kappa_tiles(rt_ctx c, const KappaTile& t, int64_t n_cell_groups,
-                              int tile_begin, int n_tiles, bool comp, hipStream_t s) {
+                              int tile_begin, int n_tiles, bool comp, hipStream_t s,
+                              const TileGate& gate) {
   KappaArgs a;
   a.t = t;
+  a.gate = gate;
   a.n_tiles = n_tiles;
   a.tile_begin = tile_begin;
   const int64_t blocks = n_cell_groups * n_tiles;

@@ -76,6 +76,8 @@ struct rt_ctx_s {
   // grid
   bool have_grid = false;
   double T_min = 0, T_max = 0;  // cell temperature range of the grid
+  int64_t T_argmin = 0, T_argmax = 0;
+  uint64_t grid_epoch = 0;      // bumped by every rt_setup_grid
   int nx = 0, ny = 0, nz = 0;
   int64_t n_cells = 0;
   double cell_m = 0, T_wall = 0;

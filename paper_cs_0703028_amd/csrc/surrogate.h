@@ -11,6 +11,7 @@ typedef __bf16 bf16;
 
 constexpr int kMlpLayers = 4;
 constexpr int kMlpWidth = 256;                         // outputs per chunk
+constexpr int kMaxCheckCells = 256;                    // sampled cells per check, at most
 constexpr int kMlpDims[kMlpLayers + 1] = {4, 512, 512, 512, 256};
 
 struct Surrogate {
@@ -30,6 +31,11 @@ struct Surrogate {
   float* vb[kMlpLayers] = {};
   bf16* wt[kMlpLayers] = {};
   bf16* wk[kMlpLayers] = {};
+  // inference copies of layers 2-4 in MFMA fragment order: for column tile
+  // ct, k-step s (16) and lane l, the 8 values of W^T[32 ct + l % 32]
+  // [16 s + 8 (l / 32) ..] are contiguous, so a wavefront's operand load is
+  // one contiguous 1 KB read
+  bf16* wf[kMlpLayers] = {};
   float* mean = nullptr;  // [n_chunks][256] normalisation of the targets
   float* stdv = nullptr;
   // last inference
@@ -39,6 +45,18 @@ struct Surrogate {
   double infer_ms = 0, check_ms = 0, fallback_ms = 0;
   double train_loss = 0;
   int64_t param_count = 0;
+  // inference scratch, kept between calls (sized for the current grid)
+  int64_t inf_cells = 0, inf_ld = 0;
+  int inf_check = 0, inf_chunks = 0;
+  unsigned* d_cell_flag = nullptr;   // = epoch: cell outside the training box
+  unsigned* d_group_flag = nullptr;  // = epoch: its line-sum group of cells
+  unsigned epoch = 0;                // inference calls so far
+  float* d_err = nullptr;            // checked error per chunk
+  int32_t* d_check = nullptr;   // sampled cells
+  float* d_exact = nullptr;     // their exact rows
+  uint64_t pick_epoch = ~0ull;  // grid the sampled cells were drawn for
+  hipEvent_t ev[4] = {};
+  bool stats_pending = false;   // counts of the last inference not read yet
 };
 
 

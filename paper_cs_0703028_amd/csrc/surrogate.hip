@@ -17,6 +17,7 @@
 // sum on a few sampled cells and recomputed for all cells when its relative
 // L1 error exceeds the tolerance.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,7 +31,8 @@
 namespace rt {
 
 hipError_t launch_kappa_tiles(rt_ctx c, const dev::KappaTile& t, int64_t n_cell_groups,
-                              int tile_begin, int n_tiles, bool comp, hipStream_t s);
+                              int tile_begin, int n_tiles, bool comp, hipStream_t s,
+                              const dev::TileGate& gate = dev::TileGate());
 hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const double* x,
                                  const double* p, const CellSet& cells, hipStream_t s);
 
@@ -67,7 +69,11 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const bf16* __restrict__ A
   }
 }
 
-__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function from the hardware base-2 exponential and reciprocal
+// (about 1 ulp each); training and inference use the same one
+__device__ __forceinline__ float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
 
 // Z = X0 W1 + b1 (K = 4, FP32 with BF16-rounded weights); H = SiLU(Z).
 __global__ void layer1_kernel(const float* __restrict__ X0, const bf16* __restrict__ W1k,
@@ -235,6 +241,16 @@ __global__ void to_bf16_kernel(const float* __restrict__ W, int K, int N, bf16* 
   Wk[i] = (bf16)W[i];
 }
 
+// W^T [N][512] (BF16) -> fragment order, see Surrogate::wf
+__global__ void pack_fragments_kernel(const bf16* __restrict__ wt, int N, bf16* wf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)N * 512) return;
+  const int e = (int)(i & 7), l = (int)((i >> 3) & 63);
+  const int64_t st = i >> 9;  // ct * 32 + s
+  const int s = (int)(st & 31), ct = (int)(st >> 5);
+  wf[i] = wt[(int64_t)(ct * 32 + (l & 31)) * 512 + s * 16 + (l >> 5) * 8 + e];
+}
+
 // Input encoding: 1/T, x and ln p, each mapped linearly onto [-1, 1] over
 // the training box, and the chunk index onto [-1, 1].  ln(kappa/u) is close
 // to linear in 1/T (Boltzmann factor of Eq. (1)) and in ln p (half widths).
@@ -306,6 +322,237 @@ __global__ void infer_kappa_kernel(const float* __restrict__ P, const float* __r
   kappa[i] = v;
 }
 
+// ------------------------------------------------------------ fused inference
+// One block of 8 wavefronts takes 64 rows through all four layers.  The
+// hidden activations stay in LDS as BF16 (64 x 512, each row padded by 8
+// elements so that the fragment reads of 32 consecutive rows spread over the
+// banks).  Each wavefront computes a 64-column slice of a hidden layer (32 of
+// the output layer) as 2 x 2 (2 x 1) tiles of 32 x 32 MFMA with FP32
+// accumulators; its weight fragments are read from L2, where the 1.3 MB of
+// BF16 weights stay.
+// The arithmetic is that of the layer-by-layer kernels (the same MFMA
+// sequence over k, the same bias and SiLU), so both give identical values.
+// Inputs are either given features (FROM_STATE false) or gas states and the
+// chunk index of each row (row = cell * n_chunks + k); the output is either
+// the raw last layer or kappa = u exp(mean + std * y), written straight into
+// the table with zeros beyond n_nu.
+constexpr int kFuseThreads = 512;  // 8 wavefronts
+constexpr int kHidden = 512;
+constexpr int kLdsRow = kHidden + 8;
+
+struct FusedArgs {
+  const bf16* W1k;  // [4][512]
+  const float* b1;
+  const bf16* wt2;  // fragment order (Surrogate::wf)
+  const float* b2;
+  const bf16* wt3;
+  const float* b3;
+  const bf16* wt4;
+  const float* b4;
+  int64_t rows;
+  const float* X0;  // [rows][4] features
+  const double* T;
+  const double* x;
+  const double* p;
+  Box bx;
+  float* P;         // [rows][256]
+  const float* mean;
+  const float* stdv;
+  float* kappa;
+  int64_t ld;
+  int n_nu;
+  double T_lo, T_hi, x_lo, x_hi, p_lo, p_hi;  // training box
+  unsigned epoch;
+  unsigned* cell_flag;   // marked with epoch when outside the box
+  unsigned* group_flag;  // and the cell's line-sum group
+};
+
+// C += A W over K = 512 for RT row tiles x NT column tiles: A from LDS, W in
+// fragment order from L2.  The weight fragments are loaded kPrefetch k-steps
+// ahead through a ring of registers (the k loop is unrolled so that every
+// ring index is static), which covers the L2 latency behind the MFMAs; the
+// activation fragments come from LDS one step ahead.  Two row tiles keep the
+// ring at 6 steps so that two blocks fit a CU's registers.
+template <int RT>
+constexpr int prefetch_steps() { return RT == 2 ? 6 : 8; }
+
+template <int RT, int NT>
+__device__ __forceinline__ void mfma_layer(const bf16* __restrict__ H, const bf16* __restrict__ wf,
+                                           int n_base, int lane, f32x16 (&acc)[RT][NT]) {
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[rt][ct][i] = 0.f;
+  const int r = lane & 31, kh = (lane >> 5) * 8;
+  const bf16* hrow[RT];
+  const bf16* wrow[NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) hrow[rt] = H + (rt * 32 + r) * kLdsRow + kh;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct) wrow[ct] = wf + ((size_t)(n_base / 32 + ct) * 32 * 64 + lane) * 8;
+  constexpr int kSteps = kHidden / 16;
+  constexpr int kPrefetch = prefetch_steps<RT>();
+  bf16x8 bq[kPrefetch][NT];
+  bf16x8 aq[2][RT];
+#pragma unroll
+  for (int d = 0; d < kPrefetch; ++d)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) bq[d][ct] = *reinterpret_cast<const bf16x8*>(wrow[ct] + d * 512);
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) aq[0][rt] = *reinterpret_cast<const bf16x8*>(hrow[rt]);
+#pragma unroll
+  for (int st = 0; st < kSteps; ++st) {
+    if (st + 1 < kSteps)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        aq[(st + 1) & 1][rt] = *reinterpret_cast<const bf16x8*>(hrow[rt] + (st + 1) * 16);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct)
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[st & 1][rt], bq[st % kPrefetch][ct],
+                                                               acc[rt][ct], 0, 0, 0);
+    if (st + kPrefetch < kSteps)
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct)
+        bq[st % kPrefetch][ct] = *reinterpret_cast<const bf16x8*>(wrow[ct] + (st + kPrefetch) * 512);
+  }
+}
+
+template <int RT, bool FROM_STATE, bool TO_KAPPA>
+__global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
+  constexpr int kFuseRows = 32 * RT;
+  __shared__ bf16 H[kFuseRows * kLdsRow];  // also holds the FP32 outputs
+  static_assert(kFuseRows * kLdsRow * sizeof(bf16) >= kFuseRows * kMlpWidth * sizeof(float),
+                "LDS buffer too small for the output layer");
+  __shared__ float F[kFuseRows][4];
+  __shared__ float U[kFuseRows];
+  __shared__ int64_t RowBase[kFuseRows];  // kappa offset of the row's chunk (-1: no row)
+  __shared__ int RowJ[kFuseRows];         // first wavenumber index of the row's chunk
+  __shared__ int RowK[kFuseRows];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t row0 = (int64_t)blockIdx.x * kFuseRows;
+  const int n_chunks = a.bx.n_chunks;
+  if (tid < kFuseRows) {
+    const int64_t row = row0 + tid;
+    float f[4] = {0.f, 0.f, 0.f, 0.f};
+    float u = 0.f;
+    int64_t base = -1;
+    int k = 0;
+    if (row < a.rows) {
+      if (FROM_STATE) {
+        const int64_t cell = row / n_chunks;
+        k = (int)(row - cell * n_chunks);
+        const double T = a.T[cell], x = a.x[cell], p = a.p[cell];
+        features(a.bx, T, x, p, k, f);
+        u = (float)gas_density(T, x, p);
+        base = cell * a.ld + (int64_t)k * kMlpWidth;
+        if (k == 0 && !(T >= a.T_lo && T <= a.T_hi && x >= a.x_lo && x <= a.x_hi &&
+                        p >= a.p_lo && p <= a.p_hi)) {
+          a.cell_flag[cell] = a.epoch;
+          a.group_flag[cell / dev::kKappaCells] = a.epoch;
+        }
+      } else {
+        for (int q = 0; q < 4; ++q) f[q] = a.X0[4 * row + q];
+        base = row * kMlpWidth;
+      }
+    }
+    for (int q = 0; q < 4; ++q) F[tid][q] = f[q];
+    U[tid] = u;
+    RowBase[tid] = base;
+    RowK[tid] = k;
+    RowJ[tid] = k * kMlpWidth;
+  }
+  __syncthreads();
+  // layer 1 (K = 4) on the VALU: thread t owns column t
+  {
+    const int n = tid;
+    float w1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w1[k] = (float)a.W1k[k * kHidden + n];
+    const float b1 = a.b1[n];
+    for (int r = 0; r < kFuseRows; ++r) {
+      float z = b1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) z = fmaf(F[r][k], w1[k], z);
+      H[r * kLdsRow + n] = (bf16)(z * sigmoid(z));
+    }
+  }
+  __syncthreads();
+  // layers 2 and 3: wavefront w computes columns [64 w, 64 w + 64)
+  for (int l = 0; l < 2; ++l) {
+    const bf16* wt = l == 0 ? a.wt2 : a.wt3;
+    const float* b = l == 0 ? a.b2 : a.b3;
+    const int n_base = wave * 64;
+    f32x16 acc[RT][2];
+    mfma_layer<RT, 2>(H, wt, n_base, lane, acc);
+    __syncthreads();  // every wavefront has read the layer input
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int row = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+          const int col = n_base + ct * 32 + (lane & 31);
+          const float z = acc[rt][ct][i] + b[col];
+          H[row * kLdsRow + col] = (bf16)(z * sigmoid(z));
+        }
+    __syncthreads();
+  }
+  // output layer (wavefront w: columns [32 w, 32 w + 32)); accumulators to
+  // LDS as FP32 over the activation buffer, then a row-major pass with
+  // coalesced stores
+  {
+    const int n_base = wave * 32;
+    f32x16 acc[RT][1];
+    mfma_layer<RT, 1>(H, a.wt4, n_base, lane, acc);
+    __syncthreads();  // every wavefront has read the last hidden layer
+    float* Z = reinterpret_cast<float*>(H);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int row = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const int col = n_base + (lane & 31);
+        Z[row * kMlpWidth + col] = acc[rt][0][i] + a.b4[col];
+      }
+    __syncthreads();
+  }
+  const float* Z = reinterpret_cast<const float*>(H);
+  static_assert(kMlpWidth == 256, "row = i >> 8 below");
+  for (int i = tid; i < kFuseRows * kMlpWidth; i += kFuseThreads) {
+    const int row = i >> 8, col = i & (kMlpWidth - 1);
+    const int64_t base = RowBase[row];
+    if (base < 0) break;
+    const float z = Z[i];
+    if (!TO_KAPPA) {
+      a.P[base + col] = z;
+    } else {
+      const int j = RowJ[row] + col;
+      const int k = RowK[row];
+      float v = 0.f;
+      if (j < a.n_nu) {  // exp to ~1e-6 relative, far inside the network's own error
+        const float y = a.mean[k * kMlpWidth + col] + a.stdv[k * kMlpWidth + col] * z;
+        v = U[row] * __builtin_amdgcn_exp2f(1.4426950408889634f * y);
+      }
+      if (j < a.ld) a.kappa[base + col] = v;
+    }
+  }
+  if (TO_KAPPA) {  // pitch columns past the last chunk
+    const int pad0 = n_chunks * kMlpWidth;
+    for (int r = 0; r < kFuseRows; ++r) {
+      if (RowBase[r] < 0) break;
+      if (RowK[r] != n_chunks - 1) continue;
+      const int64_t rowbase = RowBase[r] - (int64_t)RowJ[r];
+      for (int64_t j = pad0 + tid; j < a.ld; j += kFuseThreads) a.kappa[rowbase + j] = 0.f;
+    }
+  }
+}
+
 // Targets: y = ln(kappa / u) in place over the sample table; tiny floor.
 __global__ void log_target_kernel(float* K, int64_t n_samples, int64_t ld_s, int n_nu,
                                   const double* __restrict__ T, const double* __restrict__ x,
@@ -344,47 +591,52 @@ __global__ void normalize_kernel(float* Y, int64_t n_samples, int64_t ld_s, int 
 }
 
 // out-of-range cells -> list
-__global__ void range_kernel(const double* __restrict__ T, const double* __restrict__ x,
-                             const double* __restrict__ p, int64_t n, double T0, double T1,
-                             double x0, double x1, double p0, double p1, int32_t* list,
-                             unsigned* count) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const bool in = T[c] >= T0 && T[c] <= T1 && x[c] >= x0 && x[c] <= x1 && p[c] >= p0 && p[c] <= p1;
-  if (!in) list[atomicAdd(count, 1u)] = (int32_t)c;
-}
 
 // per chunk: the relative error of the chunk's absorptance over the sampled
 // cells, |sum (a_mlp - a)| / sum a with a = 1 - exp(-kappa l) along one
 // cell edge l -- the quantity the absorbed and emitted power are linear in
-// for thin points and saturate in for thick ones.
-__global__ void check_kernel(const float* __restrict__ kappa, int64_t ld,
-                             const float* __restrict__ exact, int64_t ld_e,
-                             const int32_t* __restrict__ cells, int n_check, int n_nu,
-                             double l_cm, double* err) {
+// for thin points and saturate in for thick ones.  Cells outside the
+// training box (recomputed exactly anyway) are left out.
+__global__ __launch_bounds__(256) void check_kernel(const float* __restrict__ kappa, int64_t ld,
+                                                    const float* __restrict__ exact, int64_t ld_e,
+                                                    const int32_t* __restrict__ cells, int n_check,
+                                                    int n_nu, float l_cm,
+                                                    const unsigned* __restrict__ cell_flag,
+                                                    unsigned epoch, float* err) {
   const int k = blockIdx.x;  // chunk
-  __shared__ double rd[256], rs[256];
-  double d = 0, s = 0;
-  for (int q = threadIdx.x; q < n_check * kMlpWidth; q += blockDim.x) {
-    const int ci = q / kMlpWidth, o = q % kMlpWidth;
-    const int64_t j = (int64_t)k * kMlpWidth + o;
-    if (j >= n_nu) continue;
-    const double e = -expm1(-(double)exact[(int64_t)ci * ld_e + j] * l_cm);
-    const double g = -expm1(-(double)kappa[(int64_t)cells[ci] * ld + j] * l_cm);
-    d += g - e;
-    s += e;
+  const int t = threadIdx.x;
+  __shared__ int64_t row[kMaxCheckCells];  // kappa row offset, -1: left out
+  __shared__ float rd[256], rs[256];
+  for (int ci = t; ci < n_check; ci += 256) {
+    const int cell = cells[ci];
+    row[ci] = cell_flag[cell] == epoch ? -1 : (int64_t)cell * ld;
   }
-  rd[threadIdx.x] = d;
-  rs[threadIdx.x] = s;
+  __syncthreads();
+  // thread t owns point k * 256 + t of every sampled cell
+  const int j = k * kMlpWidth + t;
+  float d = 0, s = 0;
+  if (j < n_nu) {
+#pragma unroll 4
+    for (int ci = 0; ci < n_check; ++ci) {
+      if (row[ci] < 0) continue;
+      const float e = -expm1f(-exact[(int64_t)ci * ld_e + j] * l_cm);
+      const float g = -expm1f(-kappa[row[ci] + j] * l_cm);
+      d += g - e;
+      s += e;
+    }
+  }
+  rd[t] = d;
+  rs[t] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) { rd[threadIdx.x] += rd[threadIdx.x + off]; rs[threadIdx.x] += rs[threadIdx.x + off]; }
+    if (t < off) { rd[t] += rd[t + off]; rs[t] += rs[t + off]; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) err[k] = rs[0] > 0 ? fabs(rd[0]) / rs[0] : (rd[0] != 0 ? 1e30 : 0.0);
+  if (t == 0) err[k] = rs[0] > 0 ? fabsf(rd[0]) / rs[0] : (rd[0] != 0 ? 1e30f : 0.0f);
 }
 
 int64_t grid1(int64_t n) { return (n + 255) / 256; }
+
 
 // deterministic 64-bit generator for weight init and shuffles (splitmix64)
 struct SplitMix {
@@ -434,6 +686,7 @@ rt_status alloc_params(rt_ctx c, Surrogate& S) {
     RT_SHIP(c, dalloc(&S.vb[l], N));
     RT_SHIP(c, dalloc(&S.wt[l], (int64_t)K * N));
     RT_SHIP(c, dalloc(&S.wk[l], (int64_t)K * N));
+    if (l > 0) RT_SHIP(c, dalloc(&S.wf[l], (int64_t)K * N));
     S.param_count += (int64_t)K * N + N;
   }
   RT_SHIP(c, dalloc(&S.mean, (int64_t)S.n_chunks * kMlpWidth));
@@ -571,6 +824,59 @@ uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ULL) {
   return h;
 }
 
+void pack_weights(const Surrogate& S, hipStream_t s) {
+  for (int l = 1; l < kMlpLayers; ++l) {
+    const int N = kMlpDims[l + 1];
+    hipLaunchKernelGGL(pack_fragments_kernel, dim3(grid1((int64_t)N * 512)), dim3(256), 0, s,
+                       S.wt[l], N, S.wf[l]);
+  }
+}
+
+// The fused kernel over `rows` rows: features X0 or gas states in, raw
+// outputs P or the kappa table out.
+void launch_fused(rt_ctx c, const Surrogate& S, int64_t rows, const float* X0, float* P,
+                  bool to_kappa, hipStream_t s) {
+  FusedArgs a;
+  a.W1k = S.wk[0]; a.b1 = S.b[0];
+  a.wt2 = S.wf[1]; a.b2 = S.b[1];
+  a.wt3 = S.wf[2]; a.b3 = S.b[2];
+  a.wt4 = S.wf[3]; a.b4 = S.b[3];
+  a.rows = rows;
+  a.X0 = X0;
+  a.T = c->d_T; a.x = c->d_x; a.p = c->d_p;
+  a.bx = make_box(S);
+  a.P = P;
+  a.mean = S.mean; a.stdv = S.stdv;
+  a.kappa = c->kappa; a.ld = c->ld; a.n_nu = c->n_nu;
+  a.T_lo = S.T_min; a.T_hi = S.T_max; a.x_lo = S.x_min; a.x_hi = S.x_max;
+  a.p_lo = S.p_min; a.p_hi = S.p_max;
+  a.epoch = S.epoch;
+  a.cell_flag = S.d_cell_flag;
+  a.group_flag = S.d_group_flag;
+  // rows per block 32 RT: 64 rows fit two blocks per CU, 96 one; pick the
+  // size with the least work on the busiest CU (on a tie, the fewest weight
+  // reads)
+  const int64_t cus = 256;
+  int best = 2;
+  double best_cost = 1e300;
+  for (int rt : {2, 3}) {
+    const int64_t blocks = (rows + 32 * rt - 1) / (32 * rt);
+    const int64_t per_cu = rt == 2 ? 2 : 1;
+    const double cost = (double)((blocks + cus * per_cu - 1) / (cus * per_cu)) * rt * per_cu -
+                        1e-3 * rt;
+    if (cost < best_cost) { best_cost = cost; best = rt; }
+  }
+  const dim3 t(kFuseThreads);
+  auto go = [&](auto rt_tag) {
+    constexpr int RT = decltype(rt_tag)::value;
+    const dim3 g((unsigned)((rows + 32 * RT - 1) / (32 * RT)));
+    if (to_kappa) hipLaunchKernelGGL((mlp_fused_kernel<RT, true, true>), g, t, 0, s, a);
+    else hipLaunchKernelGGL((mlp_fused_kernel<RT, false, false>), g, t, 0, s, a);
+  };
+  if (best == 2) go(std::integral_constant<int, 2>());
+  else go(std::integral_constant<int, 3>());
+}
+
 }  // namespace
 
 void free_surrogate(rt_ctx c) {
@@ -578,9 +884,13 @@ void free_surrogate(rt_ctx c) {
   Surrogate& S = *c->surrogate;
   for (int l = 0; l < kMlpLayers; ++l) {
     dfree(S.w[l]); dfree(S.b[l]); dfree(S.mw[l]); dfree(S.vw[l]); dfree(S.mb[l]); dfree(S.vb[l]);
-    dfree(S.wt[l]); dfree(S.wk[l]);
+    dfree(S.wt[l]); dfree(S.wk[l]); dfree(S.wf[l]);
   }
   dfree(S.mean); dfree(S.stdv);
+  dfree(S.d_cell_flag); dfree(S.d_group_flag); dfree(S.d_err); dfree(S.d_check);
+  dfree(S.d_exact);
+  for (auto& e : S.ev)
+    if (e) (void)hipEventDestroy(e);
   delete c->surrogate;
   c->surrogate = nullptr;
 }
@@ -589,49 +899,67 @@ bool surrogate_ready(rt_ctx c) {
   return c->surrogate && c->surrogate->trained && c->surrogate->n_nu == c->n_nu;
 }
 
-// Learned kappa into c->kappa: inference, range fallback, sampled check,
-// chunk fallback.  Called by rt_compute_kappa in surrogate mode.
+// Learned kappa into c->kappa, four stream-ordered launches with every
+// decision taken on the device (no host round trip):
+//   1. the fused network writes kappa and marks cells outside the training
+//      box (and their line-sum groups) with this call's epoch;
+//   2. exact rows of the sampled cells;
+//   3. the checked error per chunk (marked cells left out);
+//   4. the line sum over every tile that touches a chunk over tolerance or a
+//      marked group of cells.
+// The counts and timings are read back lazily by rt_surrogate_get_stats.
+// Called by rt_compute_kappa in surrogate mode.
 rt_status surrogate_kappa(rt_ctx c) {
   Surrogate& S = *c->surrogate;
   const int64_t n_cells = c->n_cells;
   const int64_t rows = n_cells * S.n_chunks;
-  const int M = (int)((rows + 63) / 64 * 64);
   if (rows > (int64_t)1 << 28) return sfail(c, RT_EINVAL, "surrogate: too many (cell, chunk) rows");
-  Acts a;
-  rt_status st = alloc_acts(c, a, M, false);
-  int32_t* d_list = nullptr;
-  unsigned* d_count = nullptr;
-  double* d_err = nullptr;
-  float* d_exact = nullptr;
-  int32_t* d_check = nullptr;
-  hipEvent_t ev[4];
-  for (auto& e : ev) if (hipEventCreate(&e) != hipSuccess) e = nullptr;
-  auto cleanup = [&]() {
-    a.release();
-    dfree(d_list); dfree(d_count); dfree(d_err); dfree(d_exact); dfree(d_check);
-    for (auto& e : ev) if (e) (void)hipEventDestroy(e);
-  };
-  if (st != RT_OK) { cleanup(); return st; }
-  hipStream_t s = c->stream;
-  const Box bx = make_box(S);
-  (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(infer_features_kernel, dim3(grid1(M)), dim3(256), 0, s, c->d_T, c->d_x,
-                     c->d_p, n_cells, bx, M, a.X0);
-  forward(S, a, false, s);
-  hipLaunchKernelGGL(infer_kappa_kernel, dim3(grid1(n_cells * c->ld)), dim3(256), 0, s, a.P,
-                     S.mean, S.stdv, c->d_T, c->d_x, c->d_p, n_cells, S.n_chunks, c->n_nu, c->ld,
-                     c->kappa);
-  (void)hipEventRecord(ev[1], s);
+  const int n_check = (int)std::min<int64_t>(S.check_cells, n_cells);
+  const int64_t groups_all = (n_cells + dev::kKappaCells - 1) / dev::kKappaCells;
   auto chk = [&](hipError_t e) { return e == hipSuccess; };
-  // range check -> exact line sum for out-of-range cells over the whole row
-  bool ok = chk(dalloc(&d_list, n_cells)) && chk(dalloc(&d_count, 1)) &&
-            chk(hipMemsetAsync(d_count, 0, sizeof(unsigned), s));
-  if (ok) hipLaunchKernelGGL(range_kernel, dim3(grid1(n_cells)), dim3(256), 0, s, c->d_T, c->d_x,
-                             c->d_p, n_cells, S.T_min, S.T_max, S.x_min, S.x_max, S.p_min,
-                             S.p_max, d_list, d_count);
-  unsigned n_out = 0;
-  ok = ok && chk(hipMemcpyAsync(&n_out, d_count, sizeof(unsigned), hipMemcpyDeviceToHost, s)) &&
-       chk(hipStreamSynchronize(s));
+  hipStream_t s = c->stream;
+  bool ok = true;
+  if (S.inf_cells != n_cells || S.inf_ld != c->ld || S.inf_check != n_check ||
+      S.inf_chunks != S.n_chunks || !S.d_cell_flag) {
+    dfree(S.d_cell_flag); dfree(S.d_group_flag); dfree(S.d_err); dfree(S.d_check);
+    dfree(S.d_exact);
+    ok = chk(dalloc(&S.d_cell_flag, n_cells)) && chk(dalloc(&S.d_group_flag, groups_all)) &&
+         chk(dalloc(&S.d_err, S.n_chunks)) && chk(dalloc(&S.d_check, std::max(1, n_check))) &&
+         chk(dalloc(&S.d_exact, std::max<int64_t>(1, (int64_t)n_check * c->ld)));
+    // marks start at 0, which no call uses as its epoch
+    ok = ok && chk(hipMemsetAsync(S.d_cell_flag, 0, n_cells * 4, s)) &&
+         chk(hipMemsetAsync(S.d_group_flag, 0, groups_all * 4, s));
+    if (!ok) return sfail(c, RT_ENOMEM, "surrogate inference: device allocation failed");
+    S.inf_cells = n_cells;
+    S.inf_ld = c->ld;
+    S.inf_check = n_check;
+    S.inf_chunks = S.n_chunks;
+    S.pick_epoch = ~0ull;
+  }
+  for (auto& e : S.ev)
+    if (!e && hipEventCreate(&e) != hipSuccess) return sfail(c, RT_EDEVICE, "surrogate: event");
+
+  if (S.pick_epoch != c->grid_epoch && n_check > 0) {
+    // sampled cells: the coldest and the hottest (where the network is least
+    // constrained), then uniformly drawn cells
+    std::vector<int32_t> pick;
+    for (int64_t e : {c->T_argmin, c->T_argmax})
+      if ((int)pick.size() < n_check && std::find(pick.begin(), pick.end(), (int32_t)e) == pick.end())
+        pick.push_back((int32_t)e);
+    SplitMix g{S.check_seed ^ 0xC0FFEEULL};
+    std::vector<int32_t> all(n_cells);
+    for (int64_t i = 0; i < n_cells; ++i) all[i] = (int32_t)i;
+    for (int i = 0; (int)pick.size() < n_check && i < n_cells; ++i) {
+      const int64_t r = i + (int64_t)(g.uniform() * (double)(n_cells - i));
+      std::swap(all[i], all[std::min<int64_t>(r, n_cells - 1)]);
+      if (std::find(pick.begin(), pick.end(), all[i]) == pick.end()) pick.push_back(all[i]);
+    }
+    ok = chk(hipMemcpyAsync(S.d_check, pick.data(), pick.size() * 4, hipMemcpyHostToDevice, s)) &&
+         chk(hipStreamSynchronize(s));  // the host vector goes out of scope
+    if (!ok) return sfail(c, RT_EDEVICE, "surrogate inference: copy of the sampled cells failed");
+    S.pick_epoch = c->grid_epoch;
+  }
+  S.epoch = S.epoch + 1 == 0 ? 1 : S.epoch + 1;
   dev::KappaTile t;
   t.L = c->lines;
   t.C = c->cells;
@@ -641,93 +969,75 @@ rt_status surrogate_kappa(rt_ctx c) {
   t.have_E = c->have_E ? 1 : 0;
   t.out = c->kappa;
   t.ld_out = c->ld;
+  t.col0 = 0;
+  t.col_end = c->ld;
   const int tiles_all = (int)((c->ld + dev::kKappaTilePoints - 1) / dev::kKappaTilePoints);
-  if (ok && n_out > 0) {
-    dev::KappaTile tl = t;
-    tl.cell_list = d_list;
-    tl.n_cells = n_out;
-    tl.col0 = 0;
-    tl.col_end = c->ld;
-    ok = chk(launch_kappa_tiles(c, tl, (n_out + dev::kKappaCells - 1) / dev::kKappaCells, 0,
-                                tiles_all, false, s));
-  }
-  (void)hipEventRecord(ev[2], s);
-  // sampled check: exact rows of a few cells, relative L1 error per chunk
-  const int n_check = (int)std::min<int64_t>(S.check_cells, n_cells);
-  std::vector<int32_t> pick;
-  {
-    SplitMix g{S.check_seed ^ 0xC0FFEEULL};
-    std::vector<int32_t> all(n_cells);
-    for (int64_t i = 0; i < n_cells; ++i) all[i] = (int32_t)i;
-    // the coldest and the hottest cell (where the network is least
-    // constrained), then uniformly drawn cells
-    std::vector<double> hT(n_cells);
-    if (hipMemcpy(hT.data(), c->d_T, n_cells * 8, hipMemcpyDeviceToHost) == hipSuccess) {
-      const int64_t lo = std::min_element(hT.begin(), hT.end()) - hT.begin();
-      const int64_t hi = std::max_element(hT.begin(), hT.end()) - hT.begin();
-      for (int64_t e : {lo, hi}) {
-        if ((int)pick.size() >= n_check) break;
-        if (std::find(pick.begin(), pick.end(), (int32_t)e) == pick.end()) pick.push_back((int32_t)e);
-      }
-    }
-    for (int i = 0; (int)pick.size() < n_check && i < n_cells; ++i) {
-      const int64_t r = i + (int64_t)(g.uniform() * (double)(n_cells - i));
-      std::swap(all[i], all[std::min<int64_t>(r, n_cells - 1)]);
-      if (std::find(pick.begin(), pick.end(), all[i]) == pick.end()) pick.push_back(all[i]);
-    }
-  }
-  std::vector<double> err(S.n_chunks, 0.0);
+
+  (void)hipEventRecord(S.ev[0], s);
+  launch_fused(c, S, rows, nullptr, nullptr, true, s);
+  ok = ok && chk(hipGetLastError());
+  (void)hipEventRecord(S.ev[1], s);
   if (ok && n_check > 0) {
-    ok = chk(dalloc(&d_check, n_check)) && chk(dalloc(&d_exact, (int64_t)n_check * c->ld)) &&
-         chk(dalloc(&d_err, S.n_chunks)) &&
-         chk(hipMemcpyAsync(d_check, pick.data(), n_check * 4, hipMemcpyHostToDevice, s));
-    if (ok) {
-      dev::KappaTile te = t;
-      te.cell_list = d_check;
-      te.n_cells = n_check;
-      te.out = d_exact;
-      te.compact_rows = 1;
-      te.col0 = 0;
-      te.col_end = c->ld;
-      ok = chk(launch_kappa_tiles(c, te, (n_check + dev::kKappaCells - 1) / dev::kKappaCells, 0,
-                                  tiles_all, false, s));
-    }
-    if (ok) {
+    dev::KappaTile te = t;
+    te.cell_list = S.d_check;
+    te.n_cells = n_check;
+    te.out = S.d_exact;
+    te.compact_rows = 1;
+    ok = chk(launch_kappa_tiles(c, te, (n_check + dev::kKappaCells - 1) / dev::kKappaCells, 0,
+                                tiles_all, false, s));
+    if (ok)
       hipLaunchKernelGGL(check_kernel, dim3(S.n_chunks), dim3(256), 0, s, c->kappa, c->ld,
-                         d_exact, c->ld, d_check, n_check, c->n_nu, c->cell_m * 100.0, d_err);
-      ok = chk(hipMemcpyAsync(err.data(), d_err, S.n_chunks * 8, hipMemcpyDeviceToHost, s)) &&
-           chk(hipStreamSynchronize(s));
-    }
+                         S.d_exact, c->ld, S.d_check, n_check, c->n_nu,
+                         (float)(c->cell_m * 100.0), S.d_cell_flag, S.epoch, S.d_err);
+  } else if (ok) {
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(S.n_chunks)), dim3(256), 0, s, S.d_err,
+                       (int64_t)S.n_chunks);
   }
-  (void)hipEventRecord(ev[3], s);
+  (void)hipEventRecord(S.ev[2], s);
+  if (ok) {
+    dev::TileGate gate;
+    gate.group_flag = S.d_group_flag;
+    gate.epoch = S.epoch;
+    gate.chunk_err = S.d_err;
+    gate.tol = (float)S.tolerance;
+    gate.chunk_w = kMlpWidth;
+    gate.n_chunks = S.n_chunks;
+    ok = chk(launch_kappa_tiles(c, t, groups_all, 0, tiles_all, false, s, gate));
+  }
+  (void)hipEventRecord(S.ev[3], s);
+  ok = ok && chk(hipGetLastError());
+  S.stats_pending = true;
+  if (!ok) return sfail(c, RT_EDEVICE, "surrogate inference: a HIP call failed");
+  return RT_OK;
+}
+
+// Counts and timings of the last inference (synchronises the stream once).
+rt_status surrogate_finish_stats(rt_ctx c) {
+  Surrogate& S = *c->surrogate;
+  if (!S.stats_pending) return RT_OK;
+  std::vector<float> err(S.n_chunks, 0.f);
+  std::vector<unsigned> flag(S.inf_cells, 0u);
+  hipStream_t s = c->stream;
+  hipError_t e = hipMemcpyAsync(err.data(), S.d_err, S.n_chunks * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(flag.data(), S.d_cell_flag, flag.size() * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return sfail(c, RT_EDEVICE, "surrogate statistics: read-back failed");
   S.check_error = 0;
   S.fallback_chunks = 0;
-  S.fallback_cells = (int)n_out;
-  for (int k = 0; ok && k < S.n_chunks; ++k) {
-    S.check_error = std::max(S.check_error, err[k]);
-    if (err[k] > S.tolerance) {
-      ++S.fallback_chunks;
-      dev::KappaTile tc = t;
-      tc.col0 = (int64_t)k * kMlpWidth;
-      tc.col_end = tc.col0 + kMlpWidth;
-      tc.out = c->kappa + tc.col0;  // the tile writes column j - col0
-      const int tile = (int)(tc.col0 / dev::kKappaTilePoints);
-      ok = chk(launch_kappa_tiles(c, tc, (n_cells + dev::kKappaCells - 1) / dev::kKappaCells,
-                                  tile, 1, false, s));
-    }
+  for (float v : err) {
+    S.check_error = std::max(S.check_error, (double)v);
+    if (v > (float)S.tolerance) ++S.fallback_chunks;
   }
-  ok = ok && chk(hipStreamSynchronize(s));
+  S.fallback_cells = (int)std::count(flag.begin(), flag.end(), S.epoch);
   float f1 = 0, f2 = 0, f3 = 0;
-  if (ok && ev[3]) {
-    (void)hipEventElapsedTime(&f1, ev[0], ev[1]);
-    (void)hipEventElapsedTime(&f2, ev[1], ev[2]);
-    (void)hipEventElapsedTime(&f3, ev[2], ev[3]);
-  }
+  (void)hipEventElapsedTime(&f1, S.ev[0], S.ev[1]);
+  (void)hipEventElapsedTime(&f2, S.ev[1], S.ev[2]);
+  (void)hipEventElapsedTime(&f3, S.ev[2], S.ev[3]);
   S.infer_ms = f1;
-  S.check_ms = f3;
-  S.fallback_ms = f2;
-  cleanup();
-  if (!ok) return sfail(c, RT_EDEVICE, "surrogate inference: a HIP call failed");
+  S.check_ms = f2;
+  S.fallback_ms = f3;
+  S.stats_pending = false;
   return RT_OK;
 }
 
@@ -748,8 +1058,8 @@ rt_status rt_surrogate_train(rt_ctx c, const rt_surrogate_cfg* cfg, double* fina
   if (!(cfg->T_min > 0 && cfg->T_max > cfg->T_min && cfg->x_min >= 0 && cfg->x_max > cfg->x_min &&
         cfg->x_max <= 1 && cfg->p_min > 0 && cfg->p_max > cfg->p_min))
     return sfail(c, RT_EINVAL, "rt_surrogate_train: invalid training box");
-  if (cfg->check_cells < 0 || !(cfg->tolerance > 0))
-    return sfail(c, RT_EINVAL, "rt_surrogate_train: check_cells >= 0 and tolerance > 0");
+  if (cfg->check_cells < 0 || cfg->check_cells > kMaxCheckCells || !(cfg->tolerance > 0))
+    return sfail(c, RT_EINVAL, "rt_surrogate_train: 0 <= check_cells <= 256 and tolerance > 0");
   for (int i = 0; i < n; ++i)
     if (!(cfg->T_K[i] > 0) || !(cfg->x_h2o[i] >= 0 && cfg->x_h2o[i] <= 1) || !(cfg->p_atm[i] > 0))
       return sfail(c, RT_EINVAL, "rt_surrogate_train: invalid sample state");
@@ -892,6 +1202,8 @@ rt_status rt_surrogate_train(rt_ctx c, const rt_surrogate_cfg* cfg, double* fina
   if (re != hipSuccess) return fail(RT_EDEVICE, std::string("rt_surrogate_train: ") + hipGetErrorString(re));
   S.train_loss = last_sse / ((double)steps_per_epoch * M * kMlpWidth);
   if (final_loss) *final_loss = S.train_loss;
+  pack_weights(S, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(RT_EDEVICE, "rt_surrogate_train: packing failed");
   cleanup();
   S.trained = true;
 #undef RT_TRY
@@ -902,19 +1214,21 @@ rt_status rt_surrogate_forward(rt_ctx c, int n_rows, const float* inputs, float*
   if (!c || n_rows < 1 || !inputs || !outputs) return RT_EINVAL;
   if (!c->surrogate || !c->surrogate->trained) return sfail(c, RT_ESTATE, "rt_surrogate_forward: no surrogate");
   Surrogate& S = *c->surrogate;
-  const int M = (n_rows + 63) / 64 * 64;
-  Acts a;
-  if (rt_status st = alloc_acts(c, a, M, false)) { a.release(); return st; }
-  std::vector<float> x((size_t)M * 4, 0.f);
-  std::memcpy(x.data(), inputs, (size_t)n_rows * 16);
-  hipError_t e = hipMemcpy(a.X0, x.data(), x.size() * 4, hipMemcpyHostToDevice);
+  float* X0 = nullptr;
+  float* P = nullptr;
+  hipError_t e = dalloc(&X0, (int64_t)n_rows * 4);
+  if (e == hipSuccess) e = dalloc(&P, (int64_t)n_rows * kMlpWidth);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(X0, inputs, (size_t)n_rows * 16, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) {
-    forward(S, a, false, c->stream);
-    e = hipStreamSynchronize(c->stream);
+    launch_fused(c, S, n_rows, X0, P, false, c->stream);
+    e = hipGetLastError();
   }
   if (e == hipSuccess)
-    e = hipMemcpy(outputs, a.P, (size_t)n_rows * kMlpWidth * 4, hipMemcpyDeviceToHost);
-  a.release();
+    e = hipMemcpyAsync(outputs, P, (size_t)n_rows * kMlpWidth * 4, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dfree(X0);
+  dfree(P);
   if (e != hipSuccess) return sfail(c, RT_EDEVICE, std::string("rt_surrogate_forward: ") + hipGetErrorString(e));
   return RT_OK;
 }
@@ -938,6 +1252,7 @@ rt_status rt_surrogate_weights(rt_ctx c, float* out, int64_t n) {
 rt_status rt_surrogate_get_stats(rt_ctx c, rt_surrogate_stats* out) {
   if (!c || !out) return RT_EINVAL;
   if (!c->surrogate || !c->surrogate->trained) return sfail(c, RT_ESTATE, "rt_surrogate_get_stats: no surrogate");
+  if (rt_status st = surrogate_finish_stats(c)) return st;
   const Surrogate& S = *c->surrogate;
   out->check_error = S.check_error;
   out->fallback_chunks = S.fallback_chunks;
@@ -1003,6 +1318,8 @@ rt_status rt_surrogate_load(rt_ctx c, const char* path) {
   int32_t hdr[4];
   std::memcpy(hdr, blob.data() + off, 16); off += 16;
   if (hdr[0] != 1) return sfail(c, RT_EINVAL, "rt_surrogate_load: unknown version");
+  if (hdr[3] < 0 || hdr[3] > kMaxCheckCells)
+    return sfail(c, RT_EINVAL, "rt_surrogate_load: sampled-cell count out of range");
   double box[7];
   std::memcpy(box, blob.data() + off, 56); off += 56;
   uint64_t seed;
@@ -1031,6 +1348,7 @@ rt_status rt_surrogate_load(rt_ctx c, const char* path) {
   RT_SHIP(c, hipMemcpy(S.mean, blob.data() + off, (size_t)S.n_chunks * kMlpWidth * 4, hipMemcpyHostToDevice));
   off += (size_t)S.n_chunks * kMlpWidth * 4;
   RT_SHIP(c, hipMemcpy(S.stdv, blob.data() + off, (size_t)S.n_chunks * kMlpWidth * 4, hipMemcpyHostToDevice));
+  pack_weights(S, c->stream);
   RT_SHIP(c, hipStreamSynchronize(c->stream));
   S.trained = true;
   return RT_OK;
