@@ -285,3 +285,29 @@ def test_quadratic_planck_expansion_path(rt, O):
     _say(f"  quadratic Planck: absorbed max {ra.max():.3e}, emitted {re.max():.3e}")
     assert ra.max() <= REL and re.max() <= REL
     t.close()
+
+
+def test_coherent_order_across_several_batches(rt):
+    """A call larger than one batch of segment scratch (here a 512 x 512 x 1
+    grid, ~127k rays per batch) is ordered batch by batch; the tallies equal
+    those of the same rays traced in pieces small enough to stay in index
+    order."""
+    n = 512
+    g = I.linear_T_grid(n, 0.01, nz=1, T_lo=400.0, T_hi=1400.0)
+    L = I.line_list(40, 1000.0, 1010.0, n_nu=1024)
+    w = I.Workload("wide_512x512x1", g, L, 1 << 17, 0)
+    t = _tracer(rt, w)
+    t.compute_kappa(0)
+    _say(f"several batches: {w.n_rays} rays in one call")
+    t.trace_rays(w.seed, w.n_rays)
+    a1, e1, b1 = t.tally()
+    st = t.stats()
+    assert st["march_launches"] >= 2, "the call must span several batches"
+    t.reset_tally()
+    for b in range(0, w.n_rays, 1 << 14):
+        t.trace_rays(w.seed, w.n_rays, b, 1 << 14)
+    a2, e2, b2 = t.tally()
+    np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(e1, e2, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(b1, b2, rtol=1e-12, atol=0)
+    t.close()
