@@ -195,7 +195,7 @@ def form_batched(rtlbl, I):
     t = rtlbl.Tracer(0)
     t.setup_lines(cases[0].lines)
     big = rtlbl.Tracer.default_tuning()
-    big.chunk_points = 4096
+    big.chunk_points = 4 * rtlbl.MARCH_CHUNK
     big.blocks_per_cu = 4
     big.slots = 8
     ws = torch.empty(t.batch_workspace_size(cases, big), dtype=torch.uint8, device="cuda")

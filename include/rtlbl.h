@@ -119,15 +119,19 @@ rt_status rt_setup_lines(rt_ctx ctx, int n_lines, const double* nu_cm,
                          double dnu_cm, int n_nu);
 
 /* Smallest admissible row pitch (in floats) of the kappa and Planck tables
- * for the current spectral grid: n_nu rounded up to the march chunk (1024);
+ * for the current spectral grid: n_nu rounded up to the march chunk (1536);
  * -1 before rt_setup_lines. */
 int64_t rt_required_pitch(rt_ctx ctx);
+
+/* The march's spectral chunk in points (64 lanes x points per lane): table
+ * pitches and the batched form's chunk_points are multiples of it. */
+int rt_march_chunk(void);
 
 /* Eq. (2) with Eq. (1) per cell: kappa_dev[c*ld + j] = kappa_c(nu_j) in
  * cm^-1, and, when planck_dev is not NULL, Eq. (4): planck_dev[c*ld + j] =
  * B(nu_j, T_c) evaluated in FP64 and stored in FP32.  Both are caller
  * allocated, 16-byte aligned device buffers of nx*ny*nz rows of `ld` floats,
- * ld a multiple of 1024 and >= rt_required_pitch (columns n_nu .. ld-1 are
+ * ld a multiple of 1536 and >= rt_required_pitch (columns n_nu .. ld-1 are
  * written with zeros).  The handle keeps both pointers for rt_trace_rays;
  * the Planck table is needed by the precision form of the march only.
  * mode: rt_kappa_mode. */
@@ -201,7 +205,7 @@ typedef struct {
 } rt_case;
 
 typedef struct {
-  int chunk_points;   /* nu points per (case, chunk) pair, multiple of 1024 */
+  int chunk_points;   /* nu points per (case, chunk) pair, multiple of 1536 */
   int kappa_groups;   /* groups of 8 cells per line-sum work item, >= 1     */
   int march_rays;     /* rays per march work item, multiple of 4            */
   int blocks_per_cu;  /* persistent blocks per compute unit, 1..8           */

@@ -353,6 +353,8 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
   return RT_OK;
 }
 
+int rt_march_chunk(void) { return rt::kChunk; }
+
 int64_t rt_required_pitch(rt_ctx c) {
   if (!c || !c->have_lines) return -1;
   return ((int64_t)c->n_nu + rt::kChunk - 1) / rt::kChunk * rt::kChunk;

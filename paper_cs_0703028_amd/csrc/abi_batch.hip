@@ -33,7 +33,7 @@ rt_status bfail(rt_ctx c, rt_status s, const std::string& m) {
 
 rt_batch_tuning default_tuning() {
   rt_batch_tuning t;
-  t.chunk_points = 2048;
+  t.chunk_points = 2 * kChunk;
   t.kappa_groups = 16;
   t.march_rays = 64;
   t.blocks_per_cu = 2;
@@ -43,7 +43,8 @@ rt_batch_tuning default_tuning() {
 
 rt_status check_tuning(rt_ctx c, const rt_batch_tuning& t) {
   if (t.chunk_points < kChunk || t.chunk_points % kChunk != 0 || t.chunk_points > (1 << 20))
-    return bfail(c, RT_EINVAL, "rt_batch: chunk_points must be a positive multiple of 1024");
+    return bfail(c, RT_EINVAL, "rt_batch: chunk_points must be a positive multiple of " +
+                                   std::to_string(kChunk));
   if (t.kappa_groups < 1 || t.kappa_groups > (1 << 20))
     return bfail(c, RT_EINVAL, "rt_batch: kappa_groups must be >= 1");
   if (t.march_rays < 4 || t.march_rays % 4 != 0 || t.march_rays > (1 << 20))
@@ -312,7 +313,7 @@ std::string shape_key(rt_ctx c, int n_cases, const rt_case* cases) {
     rays += (double)cases[k].n_rays;
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "v2|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
+  std::snprintf(buf, sizeof(buf), "v3|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
                 arch_name(c).c_str(), n_cases, (int)std::lround(std::log2(cells)),
                 (int)std::lround(std::log2(rays)), c->n_nu,
                 (int)std::lround(std::log2((double)std::max(1, c->lines.n))));
@@ -457,7 +458,8 @@ rt_status rt_batch_autotune(rt_ctx c, int n_cases, const rt_case* cases, int kap
   if (rt_status s = check_cases(c, n_cases, cases)) return s;
   const std::string key = shape_key(c, n_cases, cases);
   if (cache_lookup(cache_path, key, best)) return RT_OK;
-  const int64_t trial_points = std::min<int64_t>(4096, ((int64_t)c->n_nu + 1023) / 1024 * 1024);
+  const int64_t trial_points =
+      std::min<int64_t>(4 * kChunk, ((int64_t)c->n_nu + kChunk - 1) / kChunk * kChunk);
   rt_batch_tuning cur = default_tuning();
   double cur_ms = -1;
   auto trial = [&](const rt_batch_tuning& t, double* ms) -> rt_status {
@@ -477,7 +479,7 @@ rt_status rt_batch_autotune(rt_ctx c, int n_cases, const rt_case* cases, int kap
   };
   if (rt_status s = trial(cur, &cur_ms)) return s;
   if (cur_ms < 0) return bfail(c, RT_EINVAL, "rt_batch_autotune: workspace too small for the default tuning");
-  const int chunks[] = {1024, 2048, 4096};
+  const int chunks[] = {kChunk, 2 * kChunk, 4 * kChunk};
   const int groups[] = {4, 16, 64};
   const int rays[] = {16, 64, 256};
   const int bpc[] = {1, 2, 4};

@@ -15,9 +15,10 @@ namespace rt {
 // Fixed-point traversal frame: one cell edge is 2^21 integer units.
 constexpr int64_t kCellUnits = int64_t(1) << 21;
 #ifndef RT_MARCH_POINTS_PER_LANE
-#define RT_MARCH_POINTS_PER_LANE 16
+#define RT_MARCH_POINTS_PER_LANE 24
 #endif
-// march: nu points per wavefront (64 lanes x contiguous points per lane)
+// march: nu points per wavefront (64 lanes x contiguous points per lane); a
+// multiple of the 512-point line-sum tile
 constexpr int kChunk = 64 * RT_MARCH_POINTS_PER_LANE;
 constexpr int kMaxAxis = 1 << 20; // largest admissible cells per axis
 

@@ -92,6 +92,8 @@ def _load():
                                  C.c_double, C.c_double, C.c_double, C.c_int]
     L.rt_required_pitch.argtypes = [vp]
     L.rt_required_pitch.restype = C.c_int64
+    L.rt_march_chunk.argtypes = []
+    L.rt_march_chunk.restype = C.c_int
     L.rt_compute_kappa.argtypes = [vp, C.c_int, vp, vp, C.c_int64]
     L.rt_trace_rays.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int]
     L.rt_trace_explicit.argtypes = [vp, C.c_int, _i64p, _i64p, C.c_double, C.c_int, vp]
@@ -128,6 +130,7 @@ def _load():
 
 
 lib = _load()
+MARCH_CHUNK = int(lib.rt_march_chunk())  # nu points per march chunk
 
 
 class RtError(RuntimeError):

@@ -66,7 +66,7 @@ def test_batch_matches_single_runs_and_oracle(rt):
     t = rt.Tracer(0)
     t.setup_lines(cases[0].lines)
     tun = rt.Tracer.default_tuning()
-    tun.chunk_points = 1024
+    tun.chunk_points = rt.MARCH_CHUNK
     tun.kappa_groups = 2
     tun.march_rays = 16
     print("batch prepare", [c.name for c in cases], flush=True)
@@ -119,7 +119,7 @@ def test_batch_autotune_and_cache(rt, tmp_path):
     t = rt.Tracer(0)
     t.setup_lines(cases[0].lines)
     big = rt.Tracer.default_tuning()
-    big.chunk_points = 4096
+    big.chunk_points = 4 * rt.MARCH_CHUNK
     big.blocks_per_cu = 4
     nbytes = t.batch_workspace_size(cases, big)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -127,7 +127,7 @@ def test_batch_autotune_and_cache(rt, tmp_path):
     print("autotune", flush=True)
     best = t.batch_autotune(cases, rt.KAPPA_PLAIN, ws, path)
     d = best.as_dict()
-    assert d["chunk_points"] % 1024 == 0 and d["march_rays"] % 4 == 0 and d["slots"] >= 2
+    assert d["chunk_points"] % rt.MARCH_CHUNK == 0 and d["march_rays"] % 4 == 0 and d["slots"] >= 2
     assert os.path.exists(path) and '"' in open(path).read()
     best2 = t.batch_autotune(cases, rt.KAPPA_PLAIN, ws, path)
     assert best2.as_dict() == d
