@@ -182,6 +182,18 @@ def form_precision(rtlbl, I):
     tr = np.exp(-k * s.grid.cell_m * 100.0)
     closed = Bw * tr + Bc * (1 - tr)
     out["slab_1m_exit_radiance_max_rel_vs_closed_form"] = _rel(ex, closed)
+    # the same slab with 1,024 random boundary rays, against the oracle
+    t = rtlbl.Tracer(0)
+    t.setup_grid(s.grid)
+    t.setup_lines(s.lines)
+    t.compute_kappa(rtlbl.KAPPA_COMPENSATED)
+    t.trace_rays(s.seed, s.n_rays, 0, s.n_rays, rtlbl.TALLY_F64)
+    a, e, b = t.tally()
+    t.close()
+    ref = O.run(s.grid, s.lines, s.n_rays, seed=s.seed)
+    out["slab_1m_random_rays_err_vs_fp64_oracle_max_rel"] = {
+        "absorbed": _rel(a, ref["absorbed"]), "emitted": _rel(e, ref["emitted"]),
+        "balance": _rel(b, ref["balance"])}
     return out
 
 

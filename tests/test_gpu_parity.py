@@ -311,3 +311,21 @@ def test_coherent_order_across_several_batches(rt):
     np.testing.assert_allclose(e1, e2, rtol=1e-12, atol=0)
     np.testing.assert_allclose(b1, b2, rtol=1e-12, atol=0)
     t.close()
+
+
+def test_slab_random_rays_precision_form(rt, O):
+    """The 1 m isothermal slab under the precision form with 1,024 random
+    boundary rays and hot walls: per-cell tallies and the balance against the
+    FP64 oracle."""
+    w = I.slab_1cell()
+    t = _tracer(rt, w)
+    t.compute_kappa(rt.KAPPA_COMPENSATED)
+    t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, rt.TALLY_F64)
+    ag, eg, bg = t.tally()
+    res = O.run(w.grid, w.lines, w.n_rays, seed=w.seed)
+    ra = _rel(ag, res["absorbed"])
+    re = _rel(eg, res["emitted"])
+    rb = _rel(bg, res["balance"])
+    _say(f"  slab random rays: absorbed {ra.max():.3e}, emitted {re.max():.3e}, balance {rb.max():.3e}")
+    assert ra.max() <= REL and re.max() <= REL and rb.max() <= REL
+    t.close()
