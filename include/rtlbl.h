@@ -146,6 +146,10 @@ rt_status rt_compute_kappa(rt_ctx ctx, int mode, float* kappa_dev,
  * weight pi * A_boundary * dnu / n_rays_total.  Adds to the per-cell
  * absorbed/emitted power and to the energy balance; ranges may be traced in
  * any order and any split (tallies add).  tally_prec: rt_tally_prec.
+ * The rays of a call are traced in batches of up to about 1 GiB of segment
+ * scratch (owned by the handle); a batch of 2^15 rays or more is marched in
+ * a coherent order (rays sorted by direction and position), which changes
+ * only the order of the floating-point additions.
  * Requires rt_compute_kappa. */
 rt_status rt_trace_rays(rt_ctx ctx, uint64_t seed, uint64_t n_rays_total,
                         uint64_t ray_begin, uint64_t ray_count,
