@@ -329,3 +329,58 @@ def test_slab_random_rays_precision_form(rt, O):
     _say(f"  slab random rays: absorbed {ra.max():.3e}, emitted {re.max():.3e}, balance {rb.max():.3e}")
     assert ra.max() <= REL and re.max() <= REL and rb.max() <= REL
     t.close()
+
+
+# ----------------------------------------------------------- degenerate cases
+@pytest.mark.parametrize("case", ["no_lines", "no_gas"])
+def test_transparent_medium_exact(rt, case):
+    """kappa = 0 (an empty line list, or x_H2O = 0 everywhere) with hot walls:
+    nothing is absorbed or emitted, and every ray leaves with exactly what it
+    brought in."""
+    w = I.small_ragged()
+    w.grid.T_wall = 1300.0
+    if case == "no_lines":
+        L = w.lines
+        empty = np.zeros(0)
+        w = I.with_lines(w, nu=empty, S=empty, gamma=empty, n_T=empty, E_lower=empty)
+    else:
+        w.grid.x = np.zeros(w.grid.n_cells)
+    t = _tracer(rt, w)
+    kap, _ = t.compute_kappa(0)
+    assert (kap.cpu().numpy() == 0).all()
+    t.trace_rays(w.seed, w.n_rays)
+    a, e, b = t.tally()
+    assert (a == 0).all() and (e == 0).all()
+    assert b[0] > 0 and b[1] == 0 and b[2] == 0
+    np.testing.assert_allclose(b[3], b[0], rtol=1e-12)
+    t.close()
+
+
+def test_zero_ray_count_is_a_no_op(rt):
+    w = I.small_ragged()
+    t = _tracer(rt, w)
+    t.compute_kappa(0)
+    t.trace_rays(w.seed, w.n_rays, 10, 0)
+    a, e, b = t.tally()
+    assert (a == 0).all() and (e == 0).all() and (b == 0).all()
+    t.close()
+
+
+def test_long_grid_traversal_bit_exact(rt, O):
+    """A 1024 x 16 x 16 grid: grazing rays cross hundreds of cells."""
+    g = I.linear_T_grid(1024, 0.001, ny=16, nz=16)
+    w = I.Workload("long_1024x16x16", g, I.small_ragged().lines, 600, 5)
+    t = _tracer(rt, w)
+    counts, cells, lens, Og, Dg = t.debug_segments(w.seed, 0, 600)
+    Oo, Do, _ = O.rays(w.seed, 0, 600, g.nx, g.ny, g.nz)
+    assert (Og == Oo).all() and (Dg == Do).all()
+    longest = 0
+    for r in range(600):
+        c_o, l_o = O.segments(g.nx, g.ny, g.nz, g.cell_m * 100.0, Oo[r], Do[r])
+        assert counts[r] == len(c_o)
+        assert (cells[r, :counts[r]] == c_o).all()
+        np.testing.assert_array_equal(lens[r, :counts[r]], l_o.astype(np.float32))
+        longest = max(longest, len(c_o))
+    _say(f"  longest traversal {longest} cells")
+    assert longest > 100
+    t.close()
