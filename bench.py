@@ -242,13 +242,20 @@ def form_batched(rtlbl, I):
     }
 
 
-def form_learned(rtlbl, I, epochs=40):
+def form_learned(rtlbl, I, epochs=40, n_lines=None):
     """Learned form on the 8^3 workload: train the MLP on 2^16 line-sum
     spectra, then take kappa from it (range check, sampled check, line-sum
-    fallback) for the plain march; error and speed-up against the line sum."""
+    fallback) for the plain march; error and speed-up against the line sum.
+    n_lines replaces the 500-line list by a denser one over the same
+    1000-1100 cm^-1 (the line sum's cost grows with it, the network's does
+    not)."""
     import numpy as np
     import torch
     w = I.plain_8cube()
+    if n_lines is not None:
+        dense = I.line_list(n_lines, 1000.0, 1100.0, n_nu=w.lines.n_nu)
+        w = I.with_lines(w, **vars(dense))
+        w.name = f"plain_8cube_{n_lines}lines_10k_nu_1024rays"
     t = rtlbl.Tracer(0)
     t.setup_grid(w.grid)
     t.setup_lines(w.lines)
@@ -309,7 +316,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--forms", default="precision,batched,learned",
+    ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--workload", default="plain_32cube")
     ap.add_argument("--copy-probe", action="store_true",
@@ -411,7 +418,8 @@ def main():
     if not args.no_forms:
         rec["forms"] = {}
         for name, fn in (("precision", form_precision), ("batched", form_batched),
-                         ("learned", form_learned)):
+                         ("learned", form_learned),
+                         ("learned_dense_lines", lambda r, i: form_learned(r, i, n_lines=20000))):
             if name not in args.forms.split(","):
                 continue
             try:
