@@ -315,6 +315,44 @@ rt_status rt_surrogate_weights(rt_ctx ctx, float* out, int64_t n);
 
 rt_status rt_surrogate_get_stats(rt_ctx ctx, rt_surrogate_stats* out);
 
+/* ------------------------------------------------------------------------
+ * FP32 arithmetic characterisation of the device (the paper's Section 2
+ * test vectors, Table 2): rounding near ties, fused or unfused multiply-add,
+ * product symmetry and error, overflow inside a composite, subnormals and
+ * NaNs.  rt_arith_eval applies one operation element-wise with the
+ * instruction named below and stores each FP32 result bit for bit; the
+ * expected values and errors are for the caller to work out from exact
+ * arithmetic.  Composites (RT_AR_FMA_ERR, RT_AR_ADD_SUB, RT_AR_SUB_SUB) keep
+ * their intermediate in a register, so extended precision or exponent range
+ * inside the unit would show.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  RT_AR_COPY = 0,     /* x: load and store only (subnormals, NaN payloads)    */
+  RT_AR_ADD = 1,      /* x + y            v_add_f32                            */
+  RT_AR_SUB = 2,      /* x - y            v_sub_f32                            */
+  RT_AR_MUL = 3,      /* x * y            v_mul_f32                            */
+  RT_AR_FMA = 4,      /* x * y + z, one rounding          v_fma_f32            */
+  RT_AR_MUL_ADD = 5,  /* x * y + z, product rounded first v_mul_f32, v_add_f32 */
+  RT_AR_FMA_ERR = 6,  /* fma(x, y, -(x * y)): the product's rounding error     */
+  RT_AR_ADD_SUB = 7,  /* (x + y) - z, intermediate in a register              */
+  RT_AR_SUB_SUB = 8,  /* (x - y) - z, intermediate in a register              */
+  RT_AR_DIV = 9,      /* x / y as the compiler expands it (IEEE division)      */
+  RT_AR_EXP2 = 10,    /* 2^x              v_exp_f32                            */
+  RT_AR_LOG2 = 11,    /* log2 x           v_log_f32                            */
+  RT_AR_RCP = 12,     /* 1 / x            v_rcp_f32                            */
+  RT_AR_RSQ = 13,     /* 1 / sqrt(x)      v_rsq_f32                            */
+  RT_AR_SQRT = 14     /* sqrt(x)          v_sqrt_f32                           */
+} rt_arith_op;
+
+/* out[k] = op(a[k], b[k], c[k]) for k < n, on the handle's device and
+ * stream (asynchronous).  a, b, c and out are device pointers to FP32
+ * arrays of n elements owned by the caller; b must be non-NULL for
+ * two-operand ops and b and c for three-operand ops (a NULL operand an op
+ * does not use is fine).  Returns RT_EINVAL for an unknown op, a missing
+ * operand, n < 0 or NULL out; n == 0 does nothing.  Needs no setup call. */
+rt_status rt_arith_eval(rt_ctx ctx, int op, const float* a, const float* b, const float* c,
+                        float* out, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -355,6 +355,20 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
 
 int rt_march_chunk(void) { return rt::kChunk; }
 
+rt_status rt_arith_eval(rt_ctx c, int op, const float* a, const float* b, const float* z,
+                        float* out, int64_t n) {
+  if (!c) return fail(c, RT_EINVAL, "rt_arith_eval: NULL handle");
+  const int k = rt::arith_operands(op);
+  if (k == 0) return fail(c, RT_EINVAL, "rt_arith_eval: unknown op");
+  if (n < 0) return fail(c, RT_EINVAL, "rt_arith_eval: n < 0");
+  if (n == 0) return RT_OK;
+  if (!out || !a || (k >= 2 && !b) || (k >= 3 && !z))
+    return fail(c, RT_EINVAL, "rt_arith_eval: NULL operand or output");
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, rt::launch_arith(c, op, a, k >= 2 ? b : nullptr, k >= 3 ? z : nullptr, out, n));
+  return RT_OK;
+}
+
 int64_t rt_required_pitch(rt_ctx c) {
   if (!c || !c->have_lines) return -1;
   return ((int64_t)c->n_nu + rt::kChunk - 1) / rt::kChunk * rt::kChunk;

@@ -150,6 +150,11 @@ hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count,
 hipError_t launch_order(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count);
 // whether the plain march needs the second-order term of its Planck expansion
 bool planck_needs_quadratic(double T_min, double T_max, double nu0, double dnu, int n_nu);
+// FP32 arithmetic characterisation (arith.hip): operands each op reads (0 for
+// an unknown op) and the element-wise launch.
+int arith_operands(int op);
+hipError_t launch_arith(rt_ctx c, int op, const float* a, const float* b, const float* z,
+                        float* out, int64_t n);
 hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev);
 hipError_t launch_tally(rt_ctx c);
 hipError_t launch_zero(rt_ctx c);

@@ -23,6 +23,13 @@ LIB_PATH = os.path.join(_HERE, "librtlbl.so")
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE = 0, 1, 2
 TALLY_F32, TALLY_F64 = 0, 1
+# rt_arith_op: name -> (code, operands read)
+ARITH_OPS = {
+    "copy": (0, 1), "add": (1, 2), "sub": (2, 2), "mul": (3, 2), "fma": (4, 3),
+    "mul_add": (5, 3), "fma_err": (6, 2), "add_sub": (7, 3), "sub_sub": (8, 3),
+    "div": (9, 2), "exp2": (10, 1), "log2": (11, 1), "rcp": (12, 1), "rsq": (13, 1),
+    "sqrt": (14, 1),
+}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_cs_0703028_amd.build`")
@@ -117,6 +124,7 @@ def _load():
     L.rt_surrogate_forward.argtypes = [vp, C.c_int, _f32p, _f32p]
     L.rt_surrogate_weights.argtypes = [vp, _f32p, C.c_int64]
     L.rt_surrogate_get_stats.argtypes = [vp, C.POINTER(SurrogateStats)]
+    L.rt_arith_eval.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int64]
     for f in ("rt_surrogate_train", "rt_surrogate_save", "rt_surrogate_load",
               "rt_surrogate_forward", "rt_surrogate_weights", "rt_surrogate_get_stats"):
         getattr(L, f).restype = C.c_int
@@ -124,7 +132,7 @@ def _load():
               "rt_trace_rays", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
               "rt_debug_segments", "rt_get_stats", "rt_batch_default_tuning",
               "rt_batch_workspace_size", "rt_batch_prepare", "rt_batch_launch",
-              "rt_batch_results", "rt_batch_autotune"):
+              "rt_batch_results", "rt_batch_autotune", "rt_arith_eval"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -258,6 +266,20 @@ class Tracer:
 
     def reset_tally(self):
         self._check(lib.rt_reset_tally(self._h))
+
+    def arith_eval(self, op, a, b=None, c=None):
+        """rt_arith_eval on 1-D float32 device tensors of one length; returns
+        the output tensor (computed on this handle's stream)."""
+        code, k = ARITH_OPS[op]
+        ins = [a, b, c][:k]
+        for t in ins:
+            if (t is None or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                    or t.numel() != a.numel()):
+                raise ValueError("arith_eval operands: contiguous float32 device tensors of one length")
+        out = torch.empty_like(a)
+        ptrs = [C.c_void_p(t.data_ptr()) for t in ins] + [None] * (3 - k)
+        self._check(lib.rt_arith_eval(self._h, code, *ptrs, C.c_void_p(out.data_ptr()), a.numel()))
+        return out
 
     def debug_segments(self, seed, begin, count):
         g = self.grid
