@@ -309,6 +309,90 @@ def form_learned(rtlbl, I, epochs=40, n_lines=None):
     }
 
 
+def form_two_gases(rtlbl, I, reps=3):
+    """Eq. (2) with two absorbers on the 32^3 grid: the 20,000 H2O-like lines
+    plus 10,000 CO2-like lines at their own mole fractions.  The kappa table
+    is the sum of the two line sums; reported: line evaluations per second of
+    compute_kappa against the line-sum VALU ceiling."""
+    import torch
+    w = I.plain_32cube_two_gases()
+    t = rtlbl.Tracer(0)
+    t.setup_workload(w)
+    kap = torch.empty((w.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
+    t.compute_kappa(rtlbl.KAPPA_PLAIN, kap, None)          # warm-up
+    torch.cuda.synchronize()
+    s0 = t.stats()
+    for _ in range(reps):
+        t.compute_kappa(rtlbl.KAPPA_PLAIN, kap, None)
+    torch.cuda.synchronize()
+    s1 = t.stats()
+    ms = (s1["kappa_ms"] - s0["kappa_ms"]) / reps
+    evals = (s1["line_evals"] - s0["line_evals"]) / reps
+    rate = evals / (ms * 1e-3)
+    t.close()
+    del kap
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "lines": [int(len(w.lines.nu)), int(len(w.gases[0].lines.nu))],
+            "kappa_ms": ms, "line_evals": evals, "line_evals_per_s": rate,
+            "frac_of_line_sum_ceiling": rate / line_peak_evals_per_s()}
+
+
+def form_arith(rtlbl, I):
+    """FP32 arithmetic of the device (the paper's Table 2 experiments), in
+    brief: which basic operations are correctly rounded on random operands,
+    the outcome of the near-tie vectors 1.5 - 2^-i, and the largest error in
+    ulp of the hardware exp2, log2, rcp, rsq and sqrt instructions over 2^22
+    normal operands each.  References are binary64 (for +, -, *, / the
+    binary64 result rounded to binary32 is the correctly rounded one)."""
+    import numpy as np
+    import torch
+    t = rtlbl.Tracer(0)
+    rng = np.random.default_rng(5)
+    n = 1 << 22
+
+    def run(op, *xs):
+        ts = [torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda() for x in xs]
+        out = t.arith_eval(op, *ts)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    def f64(x):
+        return np.asarray(x, np.float32).astype(np.float64)
+
+    def ulp(v):
+        v = np.abs(v)
+        return np.where(v < 2.0 ** -126, 2.0 ** -149, np.ldexp(1.0, np.frexp(v)[1] - 24))
+
+    def wide(k):
+        return (rng.choice([-1.0, 1.0], k) * np.ldexp(rng.uniform(1, 2, k), rng.integers(-60, 60, k))).astype(np.float32)
+
+    x, y = wide(n), wide(n)
+    exact = {"add": f64(x) + f64(y), "sub": f64(x) - f64(y), "mul": f64(x) * f64(y),
+             "div": f64(x) / f64(y)}
+    rounded = {op: bool(np.array_equal(run(op, x, y).view(np.uint32),
+                                       v.astype(np.float32).view(np.uint32)))
+               for op, v in exact.items()}
+    i = np.arange(1, 41)
+    ties = run("sub", np.full(40, 1.5, np.float32), np.ldexp(1.0, -i).astype(np.float32))
+    pos = np.ldexp(rng.uniform(1, 2, n), rng.integers(-125, 125, n)).astype(np.float32)
+    e2 = rng.uniform(-125.0, 127.9, n).astype(np.float32)
+    refs = {"exp2": (e2, np.exp2(f64(e2))), "log2": (pos, np.log2(f64(pos))),
+            "rcp": (pos, 1.0 / f64(pos)), "rsq": (pos, 1.0 / np.sqrt(f64(pos))),
+            "sqrt": (pos, np.sqrt(f64(pos)))}
+    max_ulp = {}
+    for op, (a, r) in refs.items():
+        max_ulp[op] = round(float(np.max(np.abs(f64(run(op, a)) - r) / ulp(r))), 4)
+    t.close()
+    return {
+        "correctly_rounded": rounded,
+        "one_point_five_minus_2^-i": {"i<=23": "exact" if all(
+            ties[k - 1] == np.float32(1.5 - 2.0 ** -k) for k in range(1, 24)) else "inexact",
+            "i=24": float(ties[23]), "i>=25": float(ties[24])},
+        "max_ulp": max_ulp,
+        "operands": n,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,7 +400,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines",
+    ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines,two_gases,arith",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--workload", default="plain_32cube")
     ap.add_argument("--copy-probe", action="store_true",
@@ -419,7 +503,8 @@ def main():
         rec["forms"] = {}
         for name, fn in (("precision", form_precision), ("batched", form_batched),
                          ("learned", form_learned),
-                         ("learned_dense_lines", lambda r, i: form_learned(r, i, n_lines=20000))):
+                         ("learned_dense_lines", lambda r, i: form_learned(r, i, n_lines=20000)),
+                         ("two_gases", form_two_gases), ("arith", form_arith)):
             if name not in args.forms.split(","):
                 continue
             try:

@@ -56,7 +56,7 @@ typedef enum {
 
 /* Form of the march (Eq. (3)); per-cell accumulators are FP64 in both.
  *   RT_TALLY_F32: plain form.  Planck values evaluated in registers (FP32),
- *     1 - exp(-tau) from the hardware exponential with a degree-3 series
+ *     1 - exp(-tau) from the hardware exponential with a degree-4 series
  *     below tau = 1/16, per-wavefront partial sums in FP32.
  *   RT_TALLY_F64: precision form.  Planck values read from the FP64-derived
  *     table of rt_compute_kappa (required), degree-5 series below tau = 1/4,
@@ -117,6 +117,22 @@ rt_status rt_setup_lines(rt_ctx ctx, int n_lines, const double* nu_cm,
                          const double* n_T, const double* E_lower_cm,
                          double T_ref_K, double cutoff_cm, double nu0_cm,
                          double dnu_cm, int n_nu);
+
+/* A further absorbing gas: Eq. (2) sums over gases, each with its own line
+ * list and density.  gas in 1..3 (gas 0 is the one of rt_setup_grid's x_h2o
+ * and rt_setup_lines).  x is the gas's mole fraction per cell (host, nx*ny*nz
+ * doubles in [0, 1], copied); the lines are given as for rt_setup_lines
+ * (E_lower_cm may be NULL for this gas alone) and placed on gas 0's spectral
+ * grid with its cutoff and T_ref.  n_lines == 0 removes the gas (x may then
+ * be NULL).  rt_compute_kappa in the plain and compensated modes then writes
+ * the sum over gases (each gas's line sum is added to the table in turn);
+ * the surrogate mode and the batched form take gas 0 only and return
+ * RT_EUNSUPPORTED while a further gas is set.  Needs rt_setup_grid and
+ * rt_setup_lines first (RT_ESTATE); calling either of them again removes
+ * gases 1..3.  Invalidates a previous rt_compute_kappa. */
+rt_status rt_setup_gas(rt_ctx ctx, int gas, const double* x, int n_lines, const double* nu_cm,
+                       const double* S_ref, const double* gamma_ref_cm, const double* n_T,
+                       const double* E_lower_cm);
 
 /* Smallest admissible row pitch (in floats) of the kappa and Planck tables
  * for the current spectral grid: n_nu rounded up to the march chunk (1536);

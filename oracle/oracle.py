@@ -3,13 +3,16 @@
 Test infrastructure only: the test-suite, the smoke check and the CPU-baseline
 leg of the benchmark may import this module; the library product never does.
 Nothing here performs any of the method's arithmetic -- every number comes from
-``rt_oracle.c``; this file only marshals numpy arrays in and out.
+``rt_oracle.c``; this file only marshals numpy arrays in and out -- except the
+outer sum over gases of Eq. (2) in ``kappa_gases``, a plain FP64 addition of
+the per-gas line sums in gas order.
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
 import subprocess
+from dataclasses import replace
 
 import numpy as np
 
@@ -153,6 +156,20 @@ def kappa(grid, lines, cell_list=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("cutoff/dnu is not an integer")
     return out
+
+
+def kappa_gases(grid, lines, gases=(), cell_list=None) -> np.ndarray:
+    """Eq. (2) with its outer sum over gases: gas 0 is (grid.x, lines); each
+    further gas (an object with .x per cell and .lines on the same spectral
+    grid) adds its own line sum at its own mole fraction."""
+    total = kappa(grid, lines, cell_list)
+    for g in gases:
+        L = g.lines
+        if (L.nu0, L.dnu, L.n_nu, L.cutoff, L.T_ref) != (lines.nu0, lines.dnu, lines.n_nu,
+                                                        lines.cutoff, lines.T_ref):
+            raise ValueError("every gas must use the first gas's spectral grid, cutoff and T_ref")
+        total = total + kappa(replace(grid, x=np.asarray(g.x, np.float64)), L, cell_list)
+    return total
 
 
 def planck(nu, T) -> float:

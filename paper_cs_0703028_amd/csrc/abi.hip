@@ -51,11 +51,28 @@ bool finite_all(const double* a, int64_t n) {
   return true;
 }
 
-void free_lines(rt_ctx c) {
-  rt::LineSet& L = c->lines;
+void free_lineset(rt::LineSet& L) {
   dev_free(L.m); dev_free(L.phi); dev_free(L.wlo); dev_free(L.whi); dev_free(L.S);
   dev_free(L.E2); dev_free(L.nu); dev_free(L.gamma); dev_free(L.nexp);
   L.n = 0;
+}
+
+void free_lines(rt_ctx c) { free_lineset(c->lines); }
+
+int n_gases(rt_ctx c) {
+  int n = 1;
+  for (const auto& g : c->gas) n += g.active ? 1 : 0;
+  return n;
+}
+
+// Removes gases 1..kMaxGases-1 (their lines and per-cell arrays).
+void free_gases(rt_ctx c) {
+  for (auto& g : c->gas) {
+    free_lineset(g.lines);
+    dev_free(g.x);
+    dev_free(g.G);
+    g = rt::ExtraGas();
+  }
 }
 
 void free_cells(rt_ctx c) {
@@ -173,6 +190,7 @@ rt_status rt_destroy(rt_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   free_lines(c);
+  free_gases(c);
   free_cells(c);
   dev_free(c->d_T); dev_free(c->d_x); dev_free(c->d_p);
   dev_free(c->d_bwall);
@@ -214,6 +232,7 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   dev_free(c->d_T); dev_free(c->d_x); dev_free(c->d_p);
   dev_free(c->d_abs); dev_free(c->d_emi);
   free_cells(c);
+  free_gases(c);
   c->have_grid = false;
   c->have_kappa = false;
   c->cells_valid = false;
@@ -246,43 +265,32 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   return RT_OK;
 }
 
-rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* S,
-                         const double* gamma, const double* n_T, const double* E,
-                         double T_ref, double cutoff, double nu0, double dnu, int n_nu) {
-  if (!c) return fail(c, RT_EINVAL, "rt_setup_lines: NULL handle");
-  if (n_lines < 0) return fail(c, RT_EINVAL, "rt_setup_lines: n_lines must be >= 0");
-  if (n_nu < 1) return fail(c, RT_EINVAL, "rt_setup_lines: n_nu must be >= 1");
-  if (!(dnu > 0) || !std::isfinite(dnu) || !(nu0 > 0) || !std::isfinite(nu0))
-    return fail(c, RT_EINVAL, "rt_setup_lines: dnu and nu0 must be finite and > 0");
-  if (!(T_ref > 0) || !std::isfinite(T_ref)) return fail(c, RT_EINVAL, "rt_setup_lines: T_ref must be > 0");
-  if (!(cutoff >= 0) || !std::isfinite(cutoff)) return fail(c, RT_EINVAL, "rt_setup_lines: cutoff must be >= 0");
-  const double Kd = cutoff / dnu;
-  const double Kr = std::floor(Kd + 0.5);
-  if (std::fabs(Kd - Kr) > 1e-9 * std::max(Kr, 1.0))
-    return fail(c, RT_EINVAL, "rt_setup_lines: cutoff/dnu must be an integer");
-  if ((double)n_nu + 2.0 * Kr + 2.0 >= 16777216.0)
-    return fail(c, RT_EINVAL, "rt_setup_lines: n_nu + 2*cutoff/dnu must stay below 2^24");
+// Validates one line list, keeps the lines whose window [m - K + [phi > 0],
+// m + K] meets [0, n_nu - 1], sorts them by r = (nu - nu0)/dnu = m + phi and
+// uploads them into L (device arrays allocated here; L must be empty).
+// evals: in-grid window points summed over the kept lines.
+rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, const double* S,
+                      const double* gamma, const double* n_T, const double* E, double T_ref,
+                      int K, double nu0, double dnu, int n_nu, rt::LineSet& L, double& evals) {
+  const std::string w(who);
+  if (n_lines < 0) return fail(c, RT_EINVAL, w + ": n_lines must be >= 0");
   if (n_lines > 0 && (!nu || !S || !gamma || !n_T))
-    return fail(c, RT_EINVAL, "rt_setup_lines: NULL line array");
+    return fail(c, RT_EINVAL, w + ": NULL line array");
   if (n_lines > 0) {
     if (!finite_all(nu, n_lines) || !finite_all(S, n_lines) || !finite_all(gamma, n_lines) ||
         !finite_all(n_T, n_lines) || (E && !finite_all(E, n_lines)))
-      return fail(c, RT_EINVAL, "rt_setup_lines: non-finite line parameter");
+      return fail(c, RT_EINVAL, w + ": non-finite line parameter");
     for (int i = 0; i < n_lines; ++i) {
-      if (!(S[i] >= 0)) return fail(c, RT_EINVAL, "rt_setup_lines: S_ref must be >= 0");
-      if (!(gamma[i] > 0)) return fail(c, RT_EINVAL, "rt_setup_lines: gamma_ref must be > 0");
-      if (E && !(E[i] >= 0)) return fail(c, RT_EINVAL, "rt_setup_lines: E_lower must be >= 0");
+      if (!(S[i] >= 0)) return fail(c, RT_EINVAL, w + ": S_ref must be >= 0");
+      if (!(gamma[i] > 0)) return fail(c, RT_EINVAL, w + ": gamma_ref must be > 0");
+      if (E && !(E[i] >= 0)) return fail(c, RT_EINVAL, w + ": E_lower must be >= 0");
     }
   }
-  const int K = (int)Kr;
   const double c2 = rt::second_radiation_cm_K();
-
-  // grid coordinate r = (nu - nu0)/dnu = m + phi; keep the lines whose
-  // window [m - K + [phi > 0], m + K] meets [0, n_nu - 1]; sort by r.
   struct Rec { double r; int64_t m; double phi; int src; };
   std::vector<Rec> recs;
   recs.reserve(n_lines);
-  double evals = 0;
+  evals = 0;
   for (int i = 0; i < n_lines; ++i) {
     const double r = (nu[i] - nu0) / dnu;
     const double fm = std::floor(r);
@@ -314,13 +322,6 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
     hg[k] = (float)gamma[i];
     hn[k] = (float)n_T[i];
   }
-  if (rt_status s = set_device(c)) return s;
-  RT_HIP(c, hipStreamSynchronize(c->stream));
-  free_lines(c);
-  c->have_lines = false;
-  c->have_kappa = false;
-  c->cells_valid = false;
-  rt::LineSet& L = c->lines;
   RT_HIP(c, dev_alloc(&L.m, nl));
   RT_HIP(c, dev_alloc(&L.phi, nl));
   RT_HIP(c, dev_alloc(&L.wlo, nl));
@@ -342,6 +343,39 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
     RT_HIP(c, hipMemcpy(L.nexp, hn.data(), nl * sizeof(float), hipMemcpyHostToDevice));
   }
   L.n = nl;
+  return RT_OK;
+}
+
+rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* S,
+                         const double* gamma, const double* n_T, const double* E,
+                         double T_ref, double cutoff, double nu0, double dnu, int n_nu) {
+  if (!c) return fail(c, RT_EINVAL, "rt_setup_lines: NULL handle");
+  if (n_lines < 0) return fail(c, RT_EINVAL, "rt_setup_lines: n_lines must be >= 0");
+  if (n_nu < 1) return fail(c, RT_EINVAL, "rt_setup_lines: n_nu must be >= 1");
+  if (!(dnu > 0) || !std::isfinite(dnu) || !(nu0 > 0) || !std::isfinite(nu0))
+    return fail(c, RT_EINVAL, "rt_setup_lines: dnu and nu0 must be finite and > 0");
+  if (!(T_ref > 0) || !std::isfinite(T_ref)) return fail(c, RT_EINVAL, "rt_setup_lines: T_ref must be > 0");
+  if (!(cutoff >= 0) || !std::isfinite(cutoff)) return fail(c, RT_EINVAL, "rt_setup_lines: cutoff must be >= 0");
+  const double Kd = cutoff / dnu;
+  const double Kr = std::floor(Kd + 0.5);
+  if (std::fabs(Kd - Kr) > 1e-9 * std::max(Kr, 1.0))
+    return fail(c, RT_EINVAL, "rt_setup_lines: cutoff/dnu must be an integer");
+  if ((double)n_nu + 2.0 * Kr + 2.0 >= 16777216.0)
+    return fail(c, RT_EINVAL, "rt_setup_lines: n_nu + 2*cutoff/dnu must stay below 2^24");
+  const int K = (int)Kr;
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, hipStreamSynchronize(c->stream));
+  free_lines(c);
+  free_gases(c);  // their lines were placed on the previous spectral grid
+  c->have_lines = false;
+  c->have_kappa = false;
+  c->cells_valid = false;
+  double evals = 0;
+  if (rt_status s = build_lines(c, "rt_setup_lines", n_lines, nu, S, gamma, n_T, E, T_ref, K,
+                                nu0, dnu, n_nu, c->lines, evals)) {
+    free_lines(c);
+    return s;
+  }
   c->have_E = E != nullptr;
   c->n_nu = n_nu;
   c->K = K;
@@ -350,6 +384,54 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
   c->T_ref = T_ref;
   c->line_evals_per_cell = evals;
   c->have_lines = true;
+  return RT_OK;
+}
+
+rt_status rt_setup_gas(rt_ctx c, int gas, const double* x, int n_lines, const double* nu,
+                       const double* S, const double* gamma, const double* n_T,
+                       const double* E) {
+  if (!c) return fail(c, RT_EINVAL, "rt_setup_gas: NULL handle");
+  if (gas < 1 || gas >= rt::kMaxGases)
+    return fail(c, RT_EINVAL, "rt_setup_gas: gas must be in 1.." + std::to_string(rt::kMaxGases - 1));
+  if (!c->have_grid || !c->have_lines)
+    return fail(c, RT_ESTATE, "rt_setup_gas: call rt_setup_grid and rt_setup_lines first");
+  if (n_lines < 0) return fail(c, RT_EINVAL, "rt_setup_gas: n_lines must be >= 0");
+  if (n_lines > 0) {
+    if (!x) return fail(c, RT_EINVAL, "rt_setup_gas: NULL mole fractions");
+    for (int64_t k = 0; k < c->n_cells; ++k)
+      if (!(x[k] >= 0 && x[k] <= 1))
+        return fail(c, RT_EINVAL, "rt_setup_gas: mole fractions must be in [0, 1]");
+  }
+  if (rt_status s = set_device(c)) return s;
+  RT_HIP(c, hipStreamSynchronize(c->stream));
+  rt::ExtraGas& g = c->gas[gas - 1];
+  free_lineset(g.lines);
+  dev_free(g.x);
+  dev_free(g.G);
+  g = rt::ExtraGas();
+  c->have_kappa = false;
+  c->cells_valid = false;
+  if (n_lines == 0) return RT_OK;  // gas removed
+  double evals = 0;
+  rt_status st = build_lines(c, "rt_setup_gas", n_lines, nu, S, gamma, n_T, E, c->T_ref, c->K,
+                             c->nu0, c->dnu, c->n_nu, g.lines, evals);
+  if (st == RT_OK) {
+    hipError_t e = dev_alloc(&g.x, (size_t)c->n_cells);
+    if (e == hipSuccess) e = dev_alloc(&g.G, (size_t)c->n_cells);
+    if (e == hipSuccess)
+      e = hipMemcpy(g.x, x, (size_t)c->n_cells * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = hip_fail(c, e, "rt_setup_gas: device arrays");
+  }
+  if (st != RT_OK) {
+    free_lineset(g.lines);
+    dev_free(g.x);
+    dev_free(g.G);
+    g = rt::ExtraGas();
+    return st;
+  }
+  g.have_E = E != nullptr;
+  g.line_evals_per_cell = evals;
+  g.active = true;
   return RT_OK;
 }
 
@@ -383,6 +465,8 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   if (mode == RT_KAPPA_SURROGATE &&
       (!c->surrogate || !rt::surrogate_ready(c)))
     return fail(c, RT_ESTATE, "rt_compute_kappa: no trained surrogate for this spectral grid");
+  if (mode == RT_KAPPA_SURROGATE && n_gases(c) > 1)
+    return fail(c, RT_EUNSUPPORTED, "rt_compute_kappa: the surrogate covers gas 0 only");
   if (!kappa_dev) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL kappa buffer");
   if (ld < rt_required_pitch(c) || ld % rt::kChunk != 0)
     return fail(c, RT_EINVAL, "rt_compute_kappa: ld must be a multiple of the march chunk (rt_required_pitch) and >= it");
@@ -401,6 +485,8 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   if (rt_status s = record_begin(c, c->kappa_events)) return s;
   if (!c->cells_valid) {
     RT_HIP(c, rt::launch_cell_params(c));
+    for (int g = 1; g < rt::kMaxGases; ++g)
+      if (c->gas[g - 1].active) RT_HIP(c, rt::launch_gas_factor(c, g));
     c->cells_valid = true;
   }
   if (mode == RT_KAPPA_SURROGATE) {
@@ -410,7 +496,12 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   }
   if (rt_status s = record_end(c, c->kappa_events)) return s;
   RT_HIP(c, rt::launch_planck(c));  // wall row always; cell table if requested
-  if (mode != RT_KAPPA_SURROGATE) c->stats.line_evals += c->line_evals_per_cell * (double)c->n_cells;
+  if (mode != RT_KAPPA_SURROGATE) {
+    double per_cell = c->line_evals_per_cell;
+    for (const auto& g : c->gas)
+      if (g.active) per_cell += g.line_evals_per_cell;
+    c->stats.line_evals += per_cell * (double)c->n_cells;
+  }
   c->have_kappa = true;
   return RT_OK;
 }

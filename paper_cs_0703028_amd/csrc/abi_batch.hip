@@ -285,6 +285,9 @@ rt_status materialize(rt_ctx c, int n_cases, const rt_case* cases, BatchPlan& pl
 
 rt_status prepare_impl(rt_ctx c, int n_cases, const rt_case* cases, int kappa_mode,
                        const rt_batch_tuning& t, void* ws, int64_t bytes, int64_t limit_points) {
+  for (const auto& g : c->gas)
+    if (g.active)
+      return bfail(c, RT_EUNSUPPORTED, "batched form: one gas only (gas 0); remove gases 1.. first");
   release_plan(c);
   BatchPlan* pl = new (std::nothrow) BatchPlan();
   if (!pl) return bfail(c, RT_ENOMEM, "rt_batch: out of host memory");

@@ -103,6 +103,7 @@ struct KappaTile {
   int64_t col_end;
   const int32_t* cell_list = nullptr;  // logical cell i -> cell_list[i] when set
   int compact_rows = 0;                // with a list: write row i instead of cell_list[i]
+  int accumulate = 0;                  // add to the row instead of storing (a further gas)
 };
 
 // Optional device-side gating of a launch of line-sum tiles, decided per
@@ -245,7 +246,8 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
       const int64_t j = wj0 + 64 * p + lane;
       if (j >= a.col0 && j < a.col_end) {
         const float v = COMP ? acc[p][c] + cmp[p][c] : acc[p][c];
-        a.out[cell * a.ld_out + (j - a.col0)] = (j < a.n_nu) ? v : 0.f;
+        float* o = a.out + cell * a.ld_out + (j - a.col0);
+        *o = (j < a.n_nu) ? (a.accumulate ? *o + v : v) : 0.f;
       }
     }
   }

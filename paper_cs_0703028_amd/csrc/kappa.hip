@@ -16,6 +16,13 @@ using namespace dev;
 // ---------------------------------------------------------------- cells
 // u = x p / (k_B T) [cm^-3]; q = (T_ref/T)^1.5 (partition-function ratio of
 // Eq. (1)); G = u q / (pi dnu) with energies, u / (pi dnu) without.
+__device__ inline float cell_G(double T, double x, double p, double T_ref, double dnu,
+                               int have_E) {
+  const double u = x * p * kAtm / (kBoltzmann * T) * 1e-6;
+  const double q = have_E ? pow(T_ref / T, 1.5) : 1.0;
+  return (float)(u * q / (M_PI * dnu));
+}
+
 __global__ void cell_params_kernel(int64_t n, const double* __restrict__ T,
                                    const double* __restrict__ x,
                                    const double* __restrict__ p, double T_ref,
@@ -25,13 +32,20 @@ __global__ void cell_params_kernel(int64_t n, const double* __restrict__ T,
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   double Tc = T[c];
-  double u = x[c] * p[c] * kAtm / (kBoltzmann * Tc) * 1e-6;
-  double q = have_E ? pow(T_ref / Tc, 1.5) : 1.0;
-  G[c] = (float)(u * q / (M_PI * dnu));
+  G[c] = cell_G(Tc, x[c], p[c], T_ref, dnu, have_E);
   beta[c] = 1.0 / T_ref - 1.0 / Tc;
   theta[c] = c2 / Tc;
   lam2[c] = (float)log2(T_ref / Tc);
   P[c] = (float)(p[c] / dnu);
+}
+
+// G of a further gas: its own mole fraction and partition-ratio choice.
+__global__ void gas_factor_kernel(int64_t n, const double* __restrict__ T,
+                                  const double* __restrict__ x, const double* __restrict__ p,
+                                  double T_ref, double dnu, int have_E, float* G) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  G[c] = cell_G(T[c], x[c], p[c], T_ref, dnu, have_E);
 }
 
 struct KappaArgs {
@@ -113,6 +127,14 @@ hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const dou
   return hipGetLastError();
 }
 
+hipError_t launch_gas_factor(rt_ctx c, int g) {
+  const ExtraGas& gs = c->gas[g - 1];
+  const int64_t n = c->n_cells;
+  hipLaunchKernelGGL(gas_factor_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                     n, c->d_T, gs.x, c->d_p, c->T_ref, c->dnu, gs.have_E ? 1 : 0, gs.G);
+  return hipGetLastError();
+}
+
 hipError_t launch_kappa(rt_ctx c, bool compensated) {
   KappaArgs a;
   a.t.L = c->lines;
@@ -130,13 +152,27 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
   const int64_t groups = (c->n_cells + kKappaCells - 1) / kKappaCells;
   const int64_t blocks = groups * a.n_tiles;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (compensated)
-    hipLaunchKernelGGL((kappa_linesum_kernel<true>), dim3((unsigned)blocks), dim3(kKappaThreads),
-                       0, c->stream, a);
-  else
-    hipLaunchKernelGGL((kappa_linesum_kernel<false>), dim3((unsigned)blocks), dim3(kKappaThreads),
-                       0, c->stream, a);
-  return hipGetLastError();
+  auto launch = [&]() {
+    if (compensated)
+      hipLaunchKernelGGL((kappa_linesum_kernel<true>), dim3((unsigned)blocks), dim3(kKappaThreads),
+                         0, c->stream, a);
+    else
+      hipLaunchKernelGGL((kappa_linesum_kernel<false>), dim3((unsigned)blocks),
+                         dim3(kKappaThreads), 0, c->stream, a);
+    return hipGetLastError();
+  };
+  hipError_t e = launch();
+  // further gases add their line sums, each with its own lines and G
+  for (int g = 1; g < kMaxGases && e == hipSuccess; ++g) {
+    const ExtraGas& gs = c->gas[g - 1];
+    if (!gs.active) continue;
+    a.t.L = gs.lines;
+    a.t.C.G = gs.G;
+    a.t.have_E = gs.have_E ? 1 : 0;
+    a.t.accumulate = 1;
+    e = launch();
+  }
+  return e;
 }
 
 hipError_t launch_kappa_tiles(rt_ctx c, const KappaTile& t, int64_t n_cell_groups,

@@ -53,6 +53,18 @@ struct CellSet {
   float* P = nullptr;       // p / dnu
 };
 
+// A further absorbing gas: lines, mole fraction per cell (FP64, device) and
+// the per-cell factor u q / (pi dnu) it gives (FP32, device).
+constexpr int kMaxGases = 4;
+struct ExtraGas {
+  bool active = false;
+  bool have_E = false;
+  LineSet lines;
+  double* x = nullptr;
+  float* G = nullptr;
+  double line_evals_per_cell = 0;
+};
+
 struct Stats {
   double line_evals = 0;
   double kappa_ms = 0;
@@ -94,6 +106,11 @@ struct rt_ctx_s {
   double nu0 = 0, dnu = 0, T_ref = 0;
   rt::LineSet lines;
   double line_evals_per_cell = 0;
+
+  // further absorbing gases (the outer sum over gases of Eq. (2)): gas g in
+  // 1..kMaxGases-1 has its own line list on gas 0's spectral grid, cutoff
+  // and T_ref, and its own mole fraction per cell
+  rt::ExtraGas gas[rt::kMaxGases - 1];
 
   // derived per-cell parameters and tables
   rt::CellSet cells;
@@ -143,6 +160,8 @@ constexpr int64_t kOrderMinRays = int64_t(1) << 15;
 
 // kernel launchers (defined in the .hip files)
 hipError_t launch_cell_params(rt_ctx c);
+// per-cell factor G of extra gas g (after launch_cell_params' other tables)
+hipError_t launch_gas_factor(rt_ctx c, int g);
 hipError_t launch_kappa(rt_ctx c, bool compensated);
 hipError_t launch_planck(rt_ctx c);
 hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,

@@ -33,6 +33,7 @@ STREAM_CASES = 7
 STREAM_TRAIN = 8
 STREAM_INIT = 9
 STREAM_CHECK = 10
+STREAM_XGAS = 11   # mole fractions of further gases
 
 T_REF = 296.0
 
@@ -75,6 +76,14 @@ class Lines:
 
 
 @dataclass
+class Gas:
+    """A further absorbing gas: mole fraction per cell and its line list (on
+    the first gas's spectral grid)."""
+    x: np.ndarray
+    lines: Lines
+
+
+@dataclass
 class Workload:
     name: str
     grid: Grid
@@ -82,6 +91,7 @@ class Workload:
     n_rays: int
     seed: int = 0
     notes: dict = field(default_factory=dict)
+    gases: tuple = ()   # further gases (Gas), summed into kappa by Eq. (2)
 
 
 def line_list(n_lines: int, nu_lo: float, nu_hi: float, *, seed: int = 0,
@@ -190,3 +200,33 @@ def surrogate_samples(n: int = 1 << 16, seed: int = 0, box=SURROGATE_BOX):
 
 def with_lines(w: Workload, **kw) -> Workload:
     return replace(w, lines=replace(w.lines, **kw))
+
+
+# A second, CO2-like absorber beside the first (H2O-like) one: its own line
+# list drawn by the same laws from other streams (seed offset), weaker median
+# strength and a steeper half-width temperature exponent, and its own mole
+# fraction field.  The paper's Eq. (2) sums the gases; its listing pairs H2O
+# with CO2.
+GAS2_SEED_OFFSET = 1_000_003
+
+
+def second_gas(w: Workload, n_lines: int, nu_lo: float, nu_hi: float, x_lo: float,
+               x_hi: float) -> Workload:
+    L = w.lines
+    lines = line_list(n_lines, nu_lo, nu_hi, seed=w.seed + GAS2_SEED_OFFSET, nu0=L.nu0,
+                      dnu=L.dnu, n_nu=L.n_nu, cutoff=L.cutoff, s_median=3e-22,
+                      gamma_lo=0.06, gamma_hi=0.09, n_exp=0.75)
+    x = rng(w.seed, STREAM_XGAS).uniform(x_lo, x_hi, w.grid.n_cells)
+    return replace(w, name=w.name + "_plus_co2like", gases=w.gases + (Gas(x=x, lines=lines),))
+
+
+def small_ragged_two_gases(seed: int = 3) -> Workload:
+    return second_gas(small_ragged(seed), 300, 990.0, 1035.0, 0.01, 0.15)
+
+
+def plain_8cube_two_gases(seed: int = 0) -> Workload:
+    return second_gas(plain_8cube(seed), 200, 1000.0, 1100.0, 0.02, 0.1)
+
+
+def plain_32cube_two_gases(seed: int = 0) -> Workload:
+    return second_gas(plain_32cube(seed), 10000, 1000.0, 1500.0, 0.05, 0.15)

@@ -125,6 +125,7 @@ def _load():
     L.rt_surrogate_weights.argtypes = [vp, _f32p, C.c_int64]
     L.rt_surrogate_get_stats.argtypes = [vp, C.POINTER(SurrogateStats)]
     L.rt_arith_eval.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int64]
+    L.rt_setup_gas.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp, vp, vp, vp]
     for f in ("rt_surrogate_train", "rt_surrogate_save", "rt_surrogate_load",
               "rt_surrogate_forward", "rt_surrogate_weights", "rt_surrogate_get_stats"):
         getattr(L, f).restype = C.c_int
@@ -132,7 +133,7 @@ def _load():
               "rt_trace_rays", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
               "rt_debug_segments", "rt_get_stats", "rt_batch_default_tuning",
               "rt_batch_workspace_size", "rt_batch_prepare", "rt_batch_launch",
-              "rt_batch_results", "rt_batch_autotune", "rt_arith_eval"):
+              "rt_batch_results", "rt_batch_autotune", "rt_arith_eval", "rt_setup_gas"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -201,6 +202,7 @@ class Tracer:
         self._check(lib.rt_setup_grid(self._h, grid.nx, grid.ny, grid.nz, grid.cell_m, T, x, p,
                                       grid.T_wall))
         self.grid = grid
+        self.gases = {}   # the library drops further gases with a new grid
 
     def setup_lines(self, lines):
         n = len(lines.nu)
@@ -209,6 +211,31 @@ class Tracer:
                                        _f64(lines.gamma), _f64(lines.n_T), _ptr(E), lines.T_ref,
                                        lines.cutoff, lines.nu0, lines.dnu, lines.n_nu))
         self.lines = lines
+        self.gases = {}
+
+    def setup_gas(self, gas, g=None):
+        """Further gas `gas` (1..3) from an inputs.Gas (mole fraction per cell
+        and lines on the first gas's spectral grid); g=None removes it."""
+        if g is None:
+            self._check(lib.rt_setup_gas(self._h, gas, None, 0, None, None, None, None, None))
+            self.gases.pop(gas, None)
+            return
+        L = g.lines
+        n = len(L.nu)
+        x = _f64(g.x)
+        if x.size != self.grid.nx * self.grid.ny * self.grid.nz:
+            raise ValueError("mole fractions must have nx*ny*nz entries")
+        E = None if L.E_lower is None else _f64(L.E_lower)
+        self._check(lib.rt_setup_gas(self._h, gas, _ptr(x), n, _ptr(_f64(L.nu)), _ptr(_f64(L.S)),
+                                     _ptr(_f64(L.gamma)), _ptr(_f64(L.n_T)), _ptr(E)))
+        self.gases[gas] = g
+
+    def setup_workload(self, w):
+        """setup_grid, setup_lines and every further gas of an inputs.Workload."""
+        self.setup_grid(w.grid)
+        self.setup_lines(w.lines)
+        for k, g in enumerate(w.gases, start=1):
+            self.setup_gas(k, g)
 
     def required_pitch(self) -> int:
         ld = lib.rt_required_pitch(self._h)

@@ -1,0 +1,123 @@
+"""Several absorbing gases (the outer sum of Eq. (2)) through the C ABI,
+against the FP64 oracle's sum of per-gas line sums.  Bars as for one gas:
+kappa and per-cell absorbed and emitted power within 1e-5 relative, exact
+zeros where the oracle has zeros."""
+import numpy as np
+import pytest
+
+from paper_cs_0703028_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rt():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_cs_0703028_amd import rtlbl
+    return rtlbl
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+def _rel(g, o):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    nz = o != 0
+    assert (g[~nz] == 0).all(), "GPU nonzero where the oracle is exactly zero"
+    return np.abs(g[nz] - o[nz]) / np.abs(o[nz])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("wl", ["small_ragged_two_gases", "plain_8cube_two_gases"])
+def test_two_gas_kappa(rt, O, wl, mode):
+    w = getattr(I, wl)()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    print(f"two-gas kappa {wl} mode {mode}", flush=True)
+    kap, _ = t.compute_kappa(mode)
+    n_nu = w.lines.n_nu
+    kg = kap.cpu().numpy()
+    ko = O.kappa_gases(w.grid, w.lines, w.gases)
+    assert (kg[:, n_nu:] == 0).all()
+    r = _rel(kg[:, :n_nu], ko)
+    print(f"  kappa rel err max {r.max():.3e} median {np.median(r):.3e}", flush=True)
+    assert r.max() <= REL
+    # line evaluations count both gases' windows
+    one = rt.Tracer(0)
+    one.setup_grid(w.grid)
+    one.setup_lines(w.lines)
+    one.compute_kappa(mode)
+    assert t.stats()["line_evals"] > one.stats()["line_evals"]
+    one.close()
+    t.close()
+
+
+@pytest.mark.parametrize("wl,T_wall", [("plain_8cube_two_gases", 0.0),
+                                       ("small_ragged_two_gases", 1250.0)])
+def test_two_gas_tallies(rt, O, wl, T_wall):
+    w = getattr(I, wl)()
+    w.grid.T_wall = T_wall
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    print(f"two-gas tallies {wl} T_wall {T_wall}", flush=True)
+    t.compute_kappa(0)
+    t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, 0)
+    ag, eg, bg = t.tally()
+    g = w.grid
+    Or, Dr, _ = O.rays(w.seed, 0, w.n_rays, g.nx, g.ny, g.nz)
+    kap = O.kappa_gases(g, w.lines, w.gases)
+    B = O.planck_rows(g, w.lines)
+    wt = O.ray_weight(g, w.lines, w.n_rays)
+    a, e, bal, _ = O.march(g, w.lines, Or, Dr, wt, kap, B)
+    ra, re = _rel(ag, a), _rel(eg, e)
+    print(f"  absorbed max {ra.max():.3e}, emitted max {re.max():.3e}", flush=True)
+    assert ra.max() <= REL and re.max() <= REL
+    for k in range(4):
+        if bal[k] == 0:
+            assert bg[k] == 0
+        else:
+            assert abs(bg[k] - bal[k]) <= REL * abs(bal[k])
+    t.close()
+
+
+def test_gas_removal_and_refusals(rt):
+    w = I.small_ragged_two_gases()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    k2 = t.compute_kappa(0)[0].cpu().numpy()
+    t.setup_gas(1, None)                       # removed: back to gas 0 alone
+    k1 = t.compute_kappa(0)[0].cpu().numpy()
+    ref = rt.Tracer(0)
+    ref.setup_grid(w.grid)
+    ref.setup_lines(w.lines)
+    k0 = ref.compute_kappa(0)[0].cpu().numpy()
+    assert np.array_equal(k1, k0) and not np.array_equal(k2, k0)
+    t.setup_gas(1, w.gases[0])
+    t.setup_lines(w.lines)                     # a new line list drops gases 1..3
+    assert np.array_equal(t.compute_kappa(0)[0].cpu().numpy(), k0)
+    for bad in (0, 4, -1):
+        with pytest.raises(rt.RtError) as e:
+            t.setup_gas(bad, w.gases[0])
+        assert e.value.status == rt.RT_EINVAL
+    fresh = rt.Tracer(0)
+    fresh.setup_grid(w.grid)
+    with pytest.raises(rt.RtError) as e:       # no line list yet
+        fresh.setup_gas(1, w.gases[0])
+    assert e.value.status == rt.RT_ESTATE
+    # the batched form takes one gas
+    t.setup_gas(1, w.gases[0])
+    import torch
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rt.RtError) as e:
+        t.batch_prepare([w], workspace=ws)
+    assert e.value.status == rt.RT_EUNSUPPORTED
+    for h in (t, ref, fresh):
+        h.close()
