@@ -337,6 +337,45 @@ def form_two_gases(rtlbl, I, reps=3):
             "frac_of_line_sum_ceiling": rate / line_peak_evals_per_s()}
 
 
+def form_table16(rtlbl, I, reps=3):
+    """The paper's own kappa formulation (16 tabulated points per line,
+    multiply-adds only) on the 32^3 workload beside the plain line sum: the
+    compute_kappa time of each, and how far the per-cell absorbed power of the
+    same 2^20 rays moves when the march reads the 16-point kappa."""
+    import numpy as np
+    import torch
+    w = I.plain_32cube()
+    t = rtlbl.Tracer(0)
+    t.setup_workload(w)
+    kap = torch.empty((w.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
+    out = {}
+    tallies = {}
+    for name, mode in (("plain", rtlbl.KAPPA_PLAIN), ("table16", rtlbl.KAPPA_TABLE16)):
+        t.compute_kappa(mode, kap, None)                 # warm-up
+        torch.cuda.synchronize()
+        s0 = t.stats()
+        for _ in range(reps):
+            t.compute_kappa(mode, kap, None)
+        s1 = t.stats()
+        out[f"kappa_ms_{name}"] = (s1["kappa_ms"] - s0["kappa_ms"]) / reps
+        t.reset_tally()
+        t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, rtlbl.TALLY_F32)
+        tallies[name] = t.tally()[0]
+    a0, a1 = tallies["plain"], tallies["table16"]
+    m = a0 > 0
+    rel = np.abs(a1[m] - a0[m]) / a0[m]
+    out.update({
+        "workload": w.name,
+        "speedup_over_plain_line_sum": out["kappa_ms_plain"] / out["kappa_ms_table16"],
+        "absorbed_rel_diff_vs_plain": {"max": float(rel.max()), "median": float(np.median(rel))},
+        "total_absorbed_rel_diff": float(abs(a1.sum() - a0.sum()) / a0.sum()),
+    })
+    t.close()
+    del kap
+    torch.cuda.empty_cache()
+    return out
+
+
 def form_arith(rtlbl, I):
     """FP32 arithmetic of the device (the paper's Table 2 experiments), in
     brief: which basic operations are correctly rounded on random operands,
@@ -400,7 +439,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines,two_gases,arith",
+    ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines,two_gases,table16,arith",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--workload", default="plain_32cube")
     ap.add_argument("--copy-probe", action="store_true",
@@ -504,7 +543,8 @@ def main():
         for name, fn in (("precision", form_precision), ("batched", form_batched),
                          ("learned", form_learned),
                          ("learned_dense_lines", lambda r, i: form_learned(r, i, n_lines=20000)),
-                         ("two_gases", form_two_gases), ("arith", form_arith)):
+                         ("two_gases", form_two_gases), ("table16", form_table16),
+                         ("arith", form_arith)):
             if name not in args.forms.split(","):
                 continue
             try:

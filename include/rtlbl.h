@@ -50,8 +50,16 @@ typedef enum {
 typedef enum {
   RT_KAPPA_PLAIN = 0,        /* FP32 line sum                               */
   RT_KAPPA_COMPENSATED = 1,  /* FP32 line sum with compensated summation    */
-  RT_KAPPA_SURROGATE = 2     /* learned form (rt_surrogate_train/load), with
+  RT_KAPPA_SURROGATE = 2,    /* learned form (rt_surrogate_train/load), with
                                 line-sum fallback and a sampled check       */
+  RT_KAPPA_TABLE16 = 3       /* the paper's own formulation (Section 3 and its
+                                listing): each line contributes at the 16 grid
+                                points m-7 .. m+8 around its centre through a
+                                profile tabulated once at the reference state
+                                (Lorentz, gamma_ref, 1 atm), scaled per cell by
+                                the density and the Eq. (1) strength ratio;
+                                multiply-adds only, no per-cell half width.  An
+                                approximation of the plain sum, every gas. */
 } rt_kappa_mode;
 
 /* Form of the march (Eq. (3)); per-cell accumulators are FP64 in both.

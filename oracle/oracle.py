@@ -63,6 +63,10 @@ def lib():
                                 _f64p, _f64p, _f64p, _f64p, C.c_void_p, C.c_double,
                                 C.c_double, C.c_double, C.c_double, C.c_int, _f64p]
         L.orc_kappa.restype = C.c_int
+        L.orc_kappa_table16.argtypes = [C.c_int, _i32p, _f64p, _f64p, _f64p, C.c_int,
+                                        _f64p, _f64p, _f64p, C.c_void_p, C.c_double,
+                                        C.c_double, C.c_double, C.c_int, _f64p]
+        L.orc_kappa_table16.restype = C.c_int
         L.orc_planck.argtypes = [C.c_double, C.c_double]
         L.orc_planck.restype = C.c_double
         L.orc_planck_rows.argtypes = [C.c_int, _i32p, _f64p, C.c_double, C.c_double,
@@ -155,6 +159,20 @@ def kappa(grid, lines, cell_list=None) -> np.ndarray:
                          lines.dnu, lines.n_nu, out)
     if rc != 0:
         raise ValueError("cutoff/dnu is not an integer")
+    return out
+
+
+def kappa_table16(grid, lines, cell_list=None) -> np.ndarray:
+    """The paper's 16-point tabulated-profile kappa rows (rt_oracle.c)."""
+    if cell_list is None:
+        cell_list = np.arange(grid.n_cells, dtype=np.int32)
+    cell_list = np.ascontiguousarray(cell_list, np.int32)
+    out = np.zeros((len(cell_list), lines.n_nu), np.float64)
+    E = lines.E_lower
+    Ep = None if E is None else np.ascontiguousarray(E, np.float64).ctypes.data_as(C.c_void_p)
+    lib().orc_kappa_table16(len(cell_list), cell_list, _f(grid.T), _f(grid.x), _f(grid.p),
+                            len(lines.nu), _f(lines.nu), _f(lines.S), _f(lines.gamma), Ep,
+                            lines.T_ref, lines.nu0, lines.dnu, lines.n_nu, out)
     return out
 
 

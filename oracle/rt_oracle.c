@@ -361,6 +361,44 @@ int orc_kappa(int n_cells_listed, const int32_t* cell_list, const double* T,
   return 0;
 }
 
+/* The paper's own formulation of Eq. (2) (its Section 3 and listing): every
+ * line contributes at the 16 grid points j = m - 7 .. m + 8, m = floor(r),
+ * r = (nu - nu0)/dnu, with its Lorentz shape at the reference state
+ * (gamma_ref, 1 atm) -- a profile the paper tabulates once per line --
+ * scaled per cell by the density u and the Eq. (1) strength ratio s:
+ * kappa_c(nu_j) = u_c sum_i S_i s_ci gamma_i / (pi ((j - r_i)^2 dnu^2 + gamma_i^2)).
+ * There is no per-cell half width and no cutoff beyond the 16 points. */
+int orc_kappa_table16(int n_cells_listed, const int32_t* cell_list, const double* T,
+                      const double* x, const double* p, int n_lines,
+                      const double* nu_line, const double* S_ref,
+                      const double* gamma_ref, const double* E_lower /* NULL: ratio 1 */,
+                      double T_ref, double nu0, double dnu, int n_nu, double* out) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int row = 0; row < n_cells_listed; ++row) {
+    int c = cell_list[row];
+    double* kap = out + (size_t)row * (size_t)n_nu;
+    for (int j = 0; j < n_nu; ++j) kap[j] = 0.0;
+    double u = orc_density(T[c], x[c], p[c]);
+    for (int i = 0; i < n_lines; ++i) {
+      double r = (nu_line[i] - nu0) / dnu;
+      double fm = floor(r);
+      if (!(fabs(fm) < 4.0e15)) continue;
+      long m = (long)fm;
+      if (m + 8 < 0 || m - 7 > (long)(n_nu - 1)) continue;
+      double s = orc_strength_ratio(T[c], T_ref, nu_line[i],
+                                    E_lower ? E_lower[i] : 0.0, E_lower != NULL);
+      double g = gamma_ref[i];
+      for (long j = m - 7; j <= m + 8; ++j) {
+        if (j < 0 || j > (long)(n_nu - 1)) continue;
+        double delta = ((double)j - r) * dnu;
+        kap[j] += S_ref[i] * s * g / (M_PI * (delta * delta + g * g));
+      }
+    }
+    for (int j = 0; j < n_nu; ++j) kap[j] *= u;
+  }
+  return 0;
+}
+
 /* Eq. (4) in its wavenumber form: B(nu, T) = c1 nu^3 / (exp(c2 nu/T) - 1)
  * in W m^-2 sr^-1 (cm^-1)^-1, nu in cm^-1; 0 for T = 0 (cold wall). */
 double orc_planck(double nu, double T) {

@@ -53,8 +53,10 @@ bool finite_all(const double* a, int64_t n) {
 
 void free_lineset(rt::LineSet& L) {
   dev_free(L.m); dev_free(L.phi); dev_free(L.wlo); dev_free(L.whi); dev_free(L.S);
-  dev_free(L.E2); dev_free(L.nu); dev_free(L.gamma); dev_free(L.nexp);
+  dev_free(L.E2); dev_free(L.nu); dev_free(L.gamma); dev_free(L.nexp); dev_free(L.prof16);
+  dev_free(L.tile16);
   L.n = 0;
+  L.n_tiles16 = 0;
 }
 
 void free_lines(rt_ctx c) { free_lineset(c->lines); }
@@ -307,6 +309,17 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   std::vector<int32_t> hm(nl), hwlo(nl), hwhi(nl);
   std::vector<float> hphi(nl), hS(nl), hg(nl), hn(nl);
   std::vector<double> hE2(nl), hnu(nl);
+  std::vector<float> hprof((size_t)nl * 16);
+  for (int k = 0; k < nl; ++k) {
+    // the 16 tabulated points j = m - 7 .. m + 8, at distance j - r from the
+    // centre, of the reference-state Lorentz shape
+    const Rec& q16 = recs[k];
+    const double g = gamma[q16.src];
+    for (int t = 0; t < 16; ++t) {
+      const double d = ((double)(t - 7) - q16.phi) * dnu;
+      hprof[(size_t)k * 16 + t] = (float)(g / (M_PI * (d * d + g * g)));
+    }
+  }
   for (int k = 0; k < nl; ++k) {
     const Rec& q = recs[k];
     const int i = q.src;
@@ -331,7 +344,21 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   RT_HIP(c, dev_alloc(&L.nu, nl));
   RT_HIP(c, dev_alloc(&L.gamma, nl));
   RT_HIP(c, dev_alloc(&L.nexp, nl));
+  RT_HIP(c, dev_alloc(&L.prof16, (size_t)nl * 16));
+  // per 256-point tile, the lines with m in [256 t - 8, 256 t + 255 + 7]
+  const int n_t16 = (n_nu + 255) / 256;
+  std::vector<int2> ht16(n_t16);
+  for (int t = 0, lo = 0, hi = 0; t < n_t16; ++t) {
+    while (lo < nl && hm[lo] < 256 * t - 8) ++lo;
+    if (hi < lo) hi = lo;
+    while (hi < nl && hm[hi] <= 256 * t + 262) ++hi;
+    ht16[t] = make_int2(lo, hi);
+  }
+  RT_HIP(c, dev_alloc(&L.tile16, (size_t)n_t16));
+  RT_HIP(c, hipMemcpy(L.tile16, ht16.data(), (size_t)n_t16 * sizeof(int2), hipMemcpyHostToDevice));
+  L.n_tiles16 = n_t16;
   if (nl > 0) {
+    RT_HIP(c, hipMemcpy(L.prof16, hprof.data(), (size_t)nl * 16 * sizeof(float), hipMemcpyHostToDevice));
     RT_HIP(c, hipMemcpy(L.m, hm.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice));
     RT_HIP(c, hipMemcpy(L.phi, hphi.data(), nl * sizeof(float), hipMemcpyHostToDevice));
     RT_HIP(c, hipMemcpy(L.wlo, hwlo.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -460,11 +487,15 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   if (!c) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL handle");
   if (!c->have_grid || !c->have_lines)
     return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_setup_grid and rt_setup_lines first");
-  if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED && mode != RT_KAPPA_SURROGATE)
+  if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED && mode != RT_KAPPA_SURROGATE &&
+      mode != RT_KAPPA_TABLE16)
     return fail(c, RT_EINVAL, "rt_compute_kappa: unknown mode");
   if (mode == RT_KAPPA_SURROGATE &&
       (!c->surrogate || !rt::surrogate_ready(c)))
     return fail(c, RT_ESTATE, "rt_compute_kappa: no trained surrogate for this spectral grid");
+  if (mode == RT_KAPPA_TABLE16 && c->K < 8)
+    return fail(c, RT_EUNSUPPORTED, "rt_compute_kappa: the 16-point form needs cutoff >= 8 dnu "
+                                    "(its points must lie within the kept lines' windows)");
   if (mode == RT_KAPPA_SURROGATE && n_gases(c) > 1)
     return fail(c, RT_EUNSUPPORTED, "rt_compute_kappa: the surrogate covers gas 0 only");
   if (!kappa_dev) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL kappa buffer");
@@ -491,12 +522,19 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   }
   if (mode == RT_KAPPA_SURROGATE) {
     if (rt_status s = rt::surrogate_kappa(c)) return s;
+  } else if (mode == RT_KAPPA_TABLE16) {
+    RT_HIP(c, rt::launch_kappa_table16(c));
   } else {
     RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
   }
   if (rt_status s = record_end(c, c->kappa_events)) return s;
   RT_HIP(c, rt::launch_planck(c));  // wall row always; cell table if requested
-  if (mode != RT_KAPPA_SURROGATE) {
+  if (mode == RT_KAPPA_TABLE16) {
+    double lines = c->lines.n;
+    for (const auto& g : c->gas)
+      if (g.active) lines += g.lines.n;
+    c->stats.line_evals += 16.0 * lines * (double)c->n_cells;
+  } else if (mode != RT_KAPPA_SURROGATE) {
     double per_cell = c->line_evals_per_cell;
     for (const auto& g : c->gas)
       if (g.active) per_cell += g.line_evals_per_cell;

@@ -104,7 +104,107 @@ __global__ void wall_table_kernel(double T_wall, int n_nu, int64_t ld, double nu
   bw[j] = v;
 }
 
+// The paper's own formulation of Eq. (2) (Section 3 and its listing): line i
+// contributes u S_i s_i(T) f_i(j) at the 16 grid points j = m_i - 7 .. m_i + 8,
+// f_i the reference-state Lorentz shape tabulated once per line (prof16);
+// u S s is the plain line sum's amplitude without the half width (G pi dnu S
+// and the Eq. (1) factors).  One block per (8 cells, 256 points); the lines
+// whose 16 points meet the block's points (tile16, found once per line list)
+// are staged in LDS 128 at a time: m, the 16 values and the amplitude for
+// each of the 8 cells.  Each thread owns one point of the 8 cells and sums
+// over the staged lines that meet its wavefront's 64 points, one
+// multiply-add per cell where its point is among a line's 16.  ACC adds to
+// the rows (a further gas).
+constexpr int kT16Points = 256;
+constexpr int kT16Cells = 8;
+constexpr int kT16Stage = 128;
+template <bool ACC>
+__global__ __launch_bounds__(kT16Points) void kappa_table16_kernel(
+    LineSet L, CellSet C, int have_E, int64_t n_cells, int n_nu, int64_t ld, int n_tiles,
+    double pi_dnu, float* __restrict__ out) {
+  __shared__ int s_m[kT16Stage];
+  __shared__ float s_tab[kT16Stage * 16];
+  __shared__ float s_amp[kT16Stage * kT16Cells];
+  const int tile = blockIdx.x % n_tiles;
+  const int64_t cell0 = (int64_t)(blockIdx.x / n_tiles) * kT16Cells;
+  const int tid = threadIdx.x;
+  const int j = tile * kT16Points + tid;
+  const int2 range = tile < L.n_tiles16 ? L.tile16[tile] : make_int2(0, 0);
+  const int wj = __builtin_amdgcn_readfirstlane(tile * kT16Points + (tid & ~63));
+  float acc[kT16Cells];
+#pragma unroll
+  for (int c = 0; c < kT16Cells; ++c) acc[c] = 0.f;
+  for (int base = range.x; base < range.y; base += kT16Stage) {
+    const int nt = min(kT16Stage, range.y - base);
+    __syncthreads();
+    for (int q = tid; q < nt * kT16Cells; q += kT16Points) {
+      const int li = q / kT16Cells, cc = q % kT16Cells;
+      const int i = base + li;
+      const int64_t cell = min(cell0 + cc, n_cells - 1);
+      float amp = (float)((double)C.G[cell] * pi_dnu) * L.S[i];
+      if (have_E) {
+        amp *= exp_split(L.E2[i] * C.beta[cell]);
+        amp *= one_minus_exp_neg_d(L.nu[i] * C.theta[cell]);
+      }
+      s_amp[li * kT16Cells + cc] = amp;
+      if (cc == 0) s_m[li] = L.m[i];
+    }
+    for (int q = tid; q < nt * 16; q += kT16Points) s_tab[q] = L.prof16[(int64_t)base * 16 + q];
+    __syncthreads();
+    // staged lines meeting this wavefront's points: m in [wj - 8, wj + 70]
+    int l0 = 0, l1 = nt;
+    {
+      int a = 0, b = nt;
+      while (a < b) { const int mid = (a + b) >> 1; if (s_m[mid] < wj - 8) a = mid + 1; else b = mid; }
+      l0 = a;
+      b = nt;
+      while (a < b) { const int mid = (a + b) >> 1; if (s_m[mid] <= wj + 70) a = mid + 1; else b = mid; }
+      l1 = a;
+    }
+    for (int li = l0; li < l1; ++li) {
+      const int t = j - s_m[li] + 7;
+      if (t >= 0 && t < 16) {
+        const float f = s_tab[li * 16 + t];
+#pragma unroll
+        for (int c = 0; c < kT16Cells; ++c) acc[c] = fmaf(s_amp[li * kT16Cells + c], f, acc[c]);
+      }
+    }
+  }
+  if (j < ld) {
+#pragma unroll
+    for (int c = 0; c < kT16Cells; ++c) {
+      const int64_t cell = cell0 + c;
+      if (cell >= n_cells) break;
+      float* o = out + cell * ld + j;
+      const float v = j < n_nu ? acc[c] : 0.f;
+      *o = ACC ? *o + v : v;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_kappa_table16(rt_ctx c) {
+  const int n_tiles = (int)((c->ld + kT16Points - 1) / kT16Points);
+  const int64_t blocks = (c->n_cells + kT16Cells - 1) / kT16Cells * n_tiles;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const double pi_dnu = M_PI * c->dnu;
+  hipLaunchKernelGGL((kappa_table16_kernel<false>), dim3((unsigned)blocks), dim3(kT16Points), 0,
+                     c->stream, c->lines, c->cells, c->have_E ? 1 : 0, c->n_cells, c->n_nu,
+                     c->ld, n_tiles, pi_dnu, c->kappa);
+  hipError_t e = hipGetLastError();
+  for (int g = 1; g < kMaxGases && e == hipSuccess; ++g) {
+    const ExtraGas& gs = c->gas[g - 1];
+    if (!gs.active) continue;
+    CellSet cg = c->cells;
+    cg.G = gs.G;
+    hipLaunchKernelGGL((kappa_table16_kernel<true>), dim3((unsigned)blocks), dim3(kT16Points), 0,
+                       c->stream, gs.lines, cg, gs.have_E ? 1 : 0, c->n_cells, c->n_nu, c->ld,
+                       n_tiles, pi_dnu, c->kappa);
+    e = hipGetLastError();
+  }
+  return e;
+}
 
 hipError_t launch_cell_params(rt_ctx c) {
   const int64_t n = c->n_cells;

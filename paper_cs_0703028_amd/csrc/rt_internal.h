@@ -42,6 +42,14 @@ struct LineSet {
   double* nu = nullptr;   // centre, cm^-1
   float* gamma = nullptr; // half width at T_ref, 1 atm
   float* nexp = nullptr;  // half-width temperature exponent
+  // the paper's tabulated profile: per line, the Lorentz shape at the
+  // reference state, gamma_ref / (pi ((j - r)^2 dnu^2 + gamma_ref^2)), at the
+  // 16 grid points j = m - 7 .. m + 8 (FP64, stored FP32), [n][16]
+  float* prof16 = nullptr;
+  // lines whose 16 points meet 256-point tile t of the grid: [lo, hi) of the
+  // sorted list, int2 per tile (t = 0 .. n_tiles16 - 1)
+  int2* tile16 = nullptr;
+  int n_tiles16 = 0;
 };
 
 // Per-cell derived parameters (device), from FP64 on the device.
@@ -163,6 +171,9 @@ hipError_t launch_cell_params(rt_ctx c);
 // per-cell factor G of extra gas g (after launch_cell_params' other tables)
 hipError_t launch_gas_factor(rt_ctx c, int g);
 hipError_t launch_kappa(rt_ctx c, bool compensated);
+// The paper's kappa formulation (16 tabulated points per line, multiply-adds
+// only), every gas, into c->kappa.
+hipError_t launch_kappa_table16(rt_ctx c);
 hipError_t launch_planck(rt_ctx c);
 hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,
                          int64_t* rays_out, bool count_work, const uint32_t* perm);

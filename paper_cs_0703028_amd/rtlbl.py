@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtlbl.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE = 0, 1, 2
+KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE, KAPPA_TABLE16 = 0, 1, 2, 3
 TALLY_F32, TALLY_F64 = 0, 1
 # rt_arith_op: name -> (code, operands read)
 ARITH_OPS = {
