@@ -225,7 +225,35 @@ def form_batched(rtlbl, I):
     st = t.stats()
     t.close()
     bal = np.array([r[2] for r in res])
+    # The same 64 cases one after another through the single-case calls
+    # (compute_kappa into a full table, then trace_rays): the unfused
+    # reference at these cases' own ray densities.
+    u = rtlbl.Tracer(0)
+    u.setup_lines(cases[0].lines)
+    ld = u.required_pitch()
+    kap = torch.empty((max(c.grid.n_cells for c in cases), ld), dtype=torch.float32,
+                      device="cuda")
+    worst = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, c in enumerate(cases):
+        u.setup_grid(c.grid)
+        u.compute_kappa(rtlbl.KAPPA_PLAIN, kap[:c.grid.n_cells], None)
+        u.trace_rays(c.seed, c.n_rays)
+        a_single = u.tally()[0]
+        a_batch = res[k][0]
+        m = a_single > 0
+        worst = max(worst, float(np.max(np.abs(a_batch[m] - a_single[m]) / a_single[m])))
+    unfused_s = time.perf_counter() - t0
+    su = u.stats()
+    u.close()
+    del kap
+    torch.cuda.empty_cache()
     return {
+        "unfused_case_by_case": {
+            "s_wall": unfused_s, "kappa_ms": su["kappa_ms"], "trace_ms": su["trace_ms"],
+            "batched_speedup": unfused_s / dt,
+            "absorbed_max_rel_diff_batched_vs_case_by_case": worst},
         "workload": "64 cases, 16^3-48^3 cells, 2^14-2^18 rays, 5,000 lines, 20,000 nu",
         "cells": int(sum(c.grid.n_cells for c in cases)),
         "rays": int(sum(c.n_rays for c in cases)),

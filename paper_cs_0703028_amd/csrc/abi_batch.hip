@@ -316,7 +316,7 @@ std::string shape_key(rt_ctx c, int n_cases, const rt_case* cases) {
     rays += (double)cases[k].n_rays;
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "v3|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
+  std::snprintf(buf, sizeof(buf), "v4|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
                 arch_name(c).c_str(), n_cases, (int)std::lround(std::log2(cells)),
                 (int)std::lround(std::log2(rays)), c->n_nu,
                 (int)std::lround(std::log2((double)std::max(1, c->lines.n))));
@@ -482,24 +482,33 @@ rt_status rt_batch_autotune(rt_ctx c, int n_cases, const rt_case* cases, int kap
   };
   if (rt_status s = trial(cur, &cur_ms)) return s;
   if (cur_ms < 0) return bfail(c, RT_EINVAL, "rt_batch_autotune: workspace too small for the default tuning");
+  // coordinate descent, repeated while a pass improves (at most 3 passes):
+  // the best value of one parameter moves when the others change
   const int chunks[] = {kChunk, 2 * kChunk, 4 * kChunk};
-  const int groups[] = {4, 16, 64};
+  const int groups[] = {16, 32, 64, 128};
   const int rays[] = {16, 64, 256};
-  const int bpc[] = {1, 2, 4};
+  const int bpc[] = {2, 4, 8};
   const int slots[] = {2, 4, 8};
-  for (int param = 0; param < 5; ++param) {
-    for (int v = 0; v < 3; ++v) {
-      rt_batch_tuning t = cur;
-      if (param == 0) t.chunk_points = chunks[v];
-      if (param == 1) t.kappa_groups = groups[v];
-      if (param == 2) t.march_rays = rays[v];
-      if (param == 3) t.blocks_per_cu = bpc[v];
-      if (param == 4) t.slots = slots[v];
-      if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
-      double ms = -1;
-      if (rt_status s = trial(t, &ms)) return s;
-      if (ms > 0 && ms < cur_ms) { cur = t; cur_ms = ms; }
+  const int* values[5] = {chunks, groups, rays, bpc, slots};
+  const int n_values[5] = {3, 4, 3, 3, 3};
+  for (int pass = 0; pass < 3; ++pass) {
+    bool improved = false;
+    for (int param = 0; param < 5; ++param) {
+      for (int v = 0; v < n_values[param]; ++v) {
+        rt_batch_tuning t = cur;
+        const int x = values[param][v];
+        if (param == 0) t.chunk_points = x;
+        if (param == 1) t.kappa_groups = x;
+        if (param == 2) t.march_rays = x;
+        if (param == 3) t.blocks_per_cu = x;
+        if (param == 4) t.slots = x;
+        if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
+        double ms = -1;
+        if (rt_status s = trial(t, &ms)) return s;
+        if (ms > 0 && ms < cur_ms) { cur = t; cur_ms = ms; improved = true; }
+      }
     }
+    if (!improved) break;
   }
   release_plan(c);
   *best = cur;
