@@ -290,7 +290,7 @@ def form_learned(rtlbl, I, epochs=40, n_lines=None):
     T, x, p = I.surrogate_samples(1 << 16, seed=0)
     t0 = time.perf_counter()
     loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=epochs, batch=1024, lr=1e-3,
-                             seed=0, check_cells=32, tolerance=1e-3)
+                             seed=0, check_cells=32, tolerance=5e-4)
     train_s = time.perf_counter() - t0
     kap = torch.empty((w.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
 
