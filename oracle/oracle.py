@@ -67,6 +67,19 @@ def lib():
                                         _f64p, _f64p, _f64p, C.c_void_p, C.c_double,
                                         C.c_double, C.c_double, C.c_int, _f64p]
         L.orc_kappa_table16.restype = C.c_int
+        L.orc_mean_strength.argtypes = [C.c_double, C.c_int, _f64p, _f64p, C.c_void_p,
+                                        C.c_double, C.c_double, C.c_double, C.c_double,
+                                        C.c_int]
+        L.orc_mean_strength.restype = C.c_double
+        L.orc_kappa_adaptive.argtypes = [C.c_int, _i32p, C.c_int, _f64p, _f64p, _f64p, C.c_int,
+                                         _f64p, _f64p, _f64p, _f64p, C.c_void_p, C.c_double,
+                                         C.c_double, C.c_double, C.c_double, C.c_int,
+                                         C.c_double, C.c_int, _f64p]
+        L.orc_kappa_adaptive.restype = C.c_int
+        L.orc_adaptive_evals.argtypes = [C.c_int, _f64p, _f64p, C.c_int, _f64p, _f64p, _f64p,
+                                         _f64p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_int, C.c_double, C.c_int]
+        L.orc_adaptive_evals.restype = C.c_double
         L.orc_planck.argtypes = [C.c_double, C.c_double]
         L.orc_planck.restype = C.c_double
         L.orc_planck_rows.argtypes = [C.c_int, _i32p, _f64p, C.c_double, C.c_double,
@@ -174,6 +187,48 @@ def kappa_table16(grid, lines, cell_list=None) -> np.ndarray:
                             len(lines.nu), _f(lines.nu), _f(lines.S), _f(lines.gamma), Ep,
                             lines.T_ref, lines.nu0, lines.dnu, lines.n_nu, out)
     return out
+
+
+ADAPTIVE_GROUP = 8   # cells sharing one line window in the adaptive form
+
+
+def mean_strength(T, lines) -> float:
+    """sbar = sum_i S_i s_i(T) / (n_nu dnu) over the lines meeting the grid:
+    the band-mean kappa of a cell divided by its density u."""
+    E = None if lines.E_lower is None else np.ascontiguousarray(lines.E_lower, np.float64)
+    Ep = None if E is None else E.ctypes.data_as(C.c_void_p)
+    return lib().orc_mean_strength(T, len(lines.nu), _f(lines.nu), _f(lines.S), Ep,
+                                   lines.T_ref, lines.cutoff, lines.nu0, lines.dnu, lines.n_nu)
+
+
+def kappa_adaptive(grid, lines, eps, cell_list=None, group=ADAPTIVE_GROUP) -> np.ndarray:
+    """kappa rows of the adaptive-window form (rt_oracle.c)."""
+    if cell_list is None:
+        cell_list = np.arange(grid.n_cells, dtype=np.int32)
+    cell_list = np.ascontiguousarray(cell_list, np.int32)
+    out = np.zeros((len(cell_list), lines.n_nu), np.float64)
+    E = None if lines.E_lower is None else np.ascontiguousarray(lines.E_lower, np.float64)
+    Ep = None if E is None else E.ctypes.data_as(C.c_void_p)
+    rc = lib().orc_kappa_adaptive(len(cell_list), cell_list, grid.n_cells, _f(grid.T), _f(grid.x),
+                                  _f(grid.p), len(lines.nu), _f(lines.nu), _f(lines.S),
+                                  _f(lines.gamma), _f(lines.n_T), Ep, lines.T_ref, lines.cutoff,
+                                  lines.nu0, lines.dnu, lines.n_nu, float(eps), int(group), out)
+    if rc != 0:
+        raise ValueError(f"orc_kappa_adaptive: bad arguments ({rc})")
+    return out
+
+
+def adaptive_evals(grid, lines, eps, group=ADAPTIVE_GROUP) -> int:
+    """(cell, line, point) evaluations the adaptive form keeps on the grid."""
+    E = None if lines.E_lower is None else np.ascontiguousarray(lines.E_lower, np.float64)
+    Ep = None if E is None else E.ctypes.data_as(C.c_void_p)
+    v = lib().orc_adaptive_evals(grid.n_cells, _f(grid.T), _f(grid.p), len(lines.nu),
+                                 _f(lines.nu), _f(lines.S), _f(lines.gamma), _f(lines.n_T), Ep,
+                                 lines.T_ref, lines.cutoff, lines.nu0, lines.dnu, lines.n_nu,
+                                 float(eps), int(group))
+    if v < 0:
+        raise ValueError(f"orc_adaptive_evals: bad arguments ({v})")
+    return int(v)
 
 
 def kappa_gases(grid, lines, gases=(), cell_list=None) -> np.ndarray:

@@ -25,6 +25,10 @@
  *   planck     Stefan-Boltzmann integral, Wien and Rayleigh-Jeans limits
  *   march      slab transmissivity, kappa = 0 pass-through, thick limit,
  *              per-ray energy balance
+ *   adaptive   vanishing tolerance gives the plain sum; one isolated line
+ *              keeps exactly the points where its plain value reaches the
+ *              threshold; nesting in the tolerance; the dropped remainder
+ *              within its bound; brute-force value-criterion counts
  */
 #include <math.h>
 #include <stdint.h>
@@ -397,6 +401,178 @@ int orc_kappa_table16(int n_cells_listed, const int32_t* cell_list, const double
     for (int j = 0; j < n_nu; ++j) kap[j] *= u;
   }
   return 0;
+}
+
+/* ======================================================================
+ * Adaptive line windows: the paper's announced next version (its
+ * conclusion), in which the number of points evaluated per line follows the
+ * local temperature and the line's intensity.  Reading used here:
+ *   - reference level of cell c: the band mean of its untruncated line sum,
+ *     kbar_c = u_c sbar_c, sbar_c = sum_i S_i s_ci / (n_nu dnu), over the
+ *     lines whose hard-cutoff window meets the grid;
+ *   - line i keeps point j in cell c while its Lorentz value there is at
+ *     least eps kbar_c: u S s g / (pi (D^2 + g^2)) >= eps u sbar, i.e.
+ *     D^2 <= W2 = S s g / (pi eps sbar) - g^2 (u cancels), a half width of
+ *     w_ci = sqrt(W2) / dnu grid points, none at all when W2 < 0;
+ *   - the window is shared by each run of `group` consecutive cells
+ *     (c / group): the widest w_ci of its cells, never beyond the hard
+ *     cutoff K.  Every cell therefore keeps at least the points its own
+ *     rule asks for;
+ *   - point j is kept when it is in the hard window (the plain sum's exact
+ *     test) and fabs(j - r_i) <= min(K, w), both in binary64.
+ * When every line has zero strength (sbar = 0) the hard window is kept.
+ * ==================================================================== */
+static int orc_meets_grid(double r, double K, int n_nu) {
+  return r >= -K && r <= (double)(n_nu - 1) + K;
+}
+
+double orc_mean_strength(double T, int n_lines, const double* nu_line, const double* S_ref,
+                         const double* E_lower, double T_ref, double cutoff_cm, double nu0,
+                         double dnu, int n_nu) {
+  double K = floor(cutoff_cm / dnu + 0.5);
+  double sum = 0.0;
+  for (int i = 0; i < n_lines; ++i) {
+    double r = (nu_line[i] - nu0) / dnu;
+    if (!orc_meets_grid(r, K, n_nu)) continue;
+    double s = orc_strength_ratio(T, T_ref, nu_line[i], E_lower ? E_lower[i] : 0.0,
+                                  E_lower != NULL);
+    sum += S_ref[i] * s;
+  }
+  return sum / ((double)n_nu * dnu);
+}
+
+/* w_ci in grid points, -1 when the line keeps no point in this cell */
+static double orc_window_points(double T, double p, double sbar, int i, const double* nu_line,
+                                const double* S_ref, const double* gamma_ref, const double* n_T,
+                                const double* E_lower, double T_ref, double dnu, double eps,
+                                double K) {
+  if (sbar == 0.0) return K;
+  double s = orc_strength_ratio(T, T_ref, nu_line[i], E_lower ? E_lower[i] : 0.0,
+                                E_lower != NULL);
+  double g = orc_half_width(gamma_ref[i], n_T[i], T, T_ref, p);
+  double num = S_ref[i] * s * g;
+  double den = M_PI * eps * sbar;
+  double W2 = num / den - g * g;
+  if (W2 < 0.0) return -1.0;
+  return sqrt(W2) / dnu;
+}
+
+/* the group's shared half width of line i, min(K, max over its cells) */
+static double orc_group_window(int grp, int group, int n_cells, const double* T,
+                               const double* p, const double* sbar_grp, int i,
+                               const double* nu_line, const double* S_ref,
+                               const double* gamma_ref, const double* n_T,
+                               const double* E_lower, double T_ref, double dnu, double eps,
+                               double K) {
+  double w = -1.0;
+  for (int k = 0; k < group; ++k) {
+    int c = grp * group + k;
+    if (c >= n_cells) break;
+    double wc = orc_window_points(T[c], p[c], sbar_grp[k], i, nu_line, S_ref, gamma_ref, n_T,
+                                  E_lower, T_ref, dnu, eps, K);
+    if (wc > w) w = wc;
+  }
+  return w < K ? w : K;
+}
+
+static int orc_kept(double jd, double r, double K, double hw) {
+  return (jd - K <= r && r <= jd + K) && hw >= 0.0 && fabs(jd - r) <= hw;
+}
+
+/* kappa rows of the adaptive form for the listed cells (n_cells: the whole
+ * grid, whose T, x, p are indexed by cell); lines in input order for every
+ * j, as in orc_kappa.  Returns -1 on a non-integer cutoff/dnu, -2 on bad
+ * eps or group. */
+int orc_kappa_adaptive(int n_cells_listed, const int32_t* cell_list, int n_cells,
+                       const double* T, const double* x, const double* p, int n_lines,
+                       const double* nu_line, const double* S_ref, const double* gamma_ref,
+                       const double* n_T, const double* E_lower, double T_ref,
+                       double cutoff_cm, double nu0, double dnu, int n_nu, double eps,
+                       int group, double* out) {
+  double Kd = cutoff_cm / dnu;
+  double K = floor(Kd + 0.5);
+  if (fabs(Kd - K) > 1e-9 * (K > 1.0 ? K : 1.0)) return -1;
+  if (!(eps > 0.0) || group < 1 || group > 64) return -2;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int row = 0; row < n_cells_listed; ++row) {
+    int c = cell_list[row];
+    int grp = c / group;
+    double sbar[64];
+    for (int k = 0; k < group; ++k) {
+      int cc = grp * group + k;
+      sbar[k] = cc < n_cells ? orc_mean_strength(T[cc], n_lines, nu_line, S_ref, E_lower,
+                                                 T_ref, cutoff_cm, nu0, dnu, n_nu)
+                             : 0.0;
+    }
+    double* kap = out + (size_t)row * (size_t)n_nu;
+    for (int j = 0; j < n_nu; ++j) kap[j] = 0.0;
+    double u = orc_density(T[c], x[c], p[c]);
+    for (int i = 0; i < n_lines; ++i) {
+      double r = (nu_line[i] - nu0) / dnu;
+      if (!orc_meets_grid(r, K, n_nu)) continue;
+      double hw = orc_group_window(grp, group, n_cells, T, p, sbar, i, nu_line, S_ref,
+                                   gamma_ref, n_T, E_lower, T_ref, dnu, eps, K);
+      if (hw < 0.0) continue;
+      double s = orc_strength_ratio(T[c], T_ref, nu_line[i],
+                                    E_lower ? E_lower[i] : 0.0, E_lower != NULL);
+      double g = orc_half_width(gamma_ref[i], n_T[i], T[c], T_ref, p[c]);
+      double jlo_d = ceil(r - K) - 1.0, jhi_d = floor(r + K) + 1.0;
+      long jlo = jlo_d < 0.0 ? 0 : (long)jlo_d;
+      long jhi = jhi_d > (double)(n_nu - 1) ? n_nu - 1 : (long)jhi_d;
+      for (long j = jlo; j <= jhi; ++j) {
+        double jd = (double)j;
+        if (!orc_kept(jd, r, K, hw)) continue;
+        double delta = (jd - r) * dnu;
+        kap[j] += S_ref[i] * s * g / (M_PI * (delta * delta + g * g));
+      }
+    }
+    for (int j = 0; j < n_nu; ++j) kap[j] *= u;
+  }
+  return 0;
+}
+
+/* Number of (cell, line, grid point) evaluations the adaptive form keeps
+ * over the whole grid.  The kept points of a line are contiguous around its
+ * centre (fabs(j - r) grows monotonically away from r), so each side is
+ * counted by walking outward from the centre until a point is not kept. */
+double orc_adaptive_evals(int n_cells, const double* T, const double* p, int n_lines,
+                          const double* nu_line, const double* S_ref, const double* gamma_ref,
+                          const double* n_T, const double* E_lower, double T_ref,
+                          double cutoff_cm, double nu0, double dnu, int n_nu, double eps,
+                          int group) {
+  double Kd = cutoff_cm / dnu;
+  double K = floor(Kd + 0.5);
+  if (fabs(Kd - K) > 1e-9 * (K > 1.0 ? K : 1.0)) return -1.0;
+  if (!(eps > 0.0) || group < 1 || group > 64) return -2.0;
+  int n_groups = (n_cells + group - 1) / group;
+  double total = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+  for (int grp = 0; grp < n_groups; ++grp) {
+    double sbar[64];
+    int members = 0;
+    for (int k = 0; k < group; ++k) {
+      int cc = grp * group + k;
+      if (cc < n_cells) ++members;
+      sbar[k] = cc < n_cells ? orc_mean_strength(T[cc], n_lines, nu_line, S_ref, E_lower,
+                                                 T_ref, cutoff_cm, nu0, dnu, n_nu)
+                             : 0.0;
+    }
+    double kept = 0.0;
+    for (int i = 0; i < n_lines; ++i) {
+      double r = (nu_line[i] - nu0) / dnu;
+      if (!orc_meets_grid(r, K, n_nu)) continue;
+      double hw = orc_group_window(grp, group, n_cells, T, p, sbar, i, nu_line, S_ref,
+                                   gamma_ref, n_T, E_lower, T_ref, dnu, eps, K);
+      if (hw < 0.0) continue;
+      double c0 = floor(r);
+      for (double jd = c0 + 1.0; orc_kept(jd, r, K, hw); jd += 1.0)
+        if (jd >= 0.0 && jd <= (double)(n_nu - 1)) kept += 1.0;
+      for (double jd = c0; orc_kept(jd, r, K, hw); jd -= 1.0)
+        if (jd >= 0.0 && jd <= (double)(n_nu - 1)) kept += 1.0;
+    }
+    total += kept * (double)members;
+  }
+  return total;
 }
 
 /* Eq. (4) in its wavenumber form: B(nu, T) = c1 nu^3 / (exp(c2 nu/T) - 1)
