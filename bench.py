@@ -404,6 +404,57 @@ def form_table16(rtlbl, I, reps=3):
     return out
 
 
+def form_adaptive(rtlbl, I, eps_list=(1e-3, 1e-4, 3e-5, 1e-5, 1e-6), reps=3):
+    """Adaptive line windows (the paper's announced next version: points per
+    line set by the local temperature and the line's intensity) on the 32^3
+    workload beside the plain line sum: for each tolerance eps, the
+    compute_kappa time (band means, windows and windowed sum), the fraction
+    of line evaluations kept, and how far the per-cell absorbed power of the
+    same 2^20 rays moves from the plain sum's."""
+    import numpy as np
+    import torch
+    w = I.plain_32cube()
+    t = rtlbl.Tracer(0)
+    t.setup_workload(w)
+    kap = torch.empty((w.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
+
+    def timed(mode):
+        t.compute_kappa(mode, kap, None)                 # warm-up
+        torch.cuda.synchronize()
+        t.reset_tally()
+        for _ in range(reps):
+            t.compute_kappa(mode, kap, None)
+        s = t.stats()
+        return s["kappa_ms"] / reps, s["line_evals"] / reps
+
+    def absorbed():
+        t.reset_tally()
+        t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, rtlbl.TALLY_F32)
+        return t.tally()[0]
+
+    ms0, ev0 = timed(rtlbl.KAPPA_PLAIN)
+    a0 = absorbed()
+    m = a0 > 0
+    rows = []
+    for eps in eps_list:
+        t.set_line_tolerance(eps)
+        ms, ev = timed(rtlbl.KAPPA_ADAPTIVE)
+        a1 = absorbed()
+        rel = np.abs(a1[m] - a0[m]) / a0[m]
+        rows.append({
+            "eps": eps,
+            "kappa_ms": ms,
+            "evals_kept": ev / ev0,
+            "speedup_over_plain_line_sum": ms0 / ms,
+            "absorbed_rel_diff_vs_plain": {"max": float(rel.max()), "median": float(np.median(rel))},
+            "total_absorbed_rel_diff": float(abs(a1.sum() - a0.sum()) / a0.sum()),
+        })
+    t.close()
+    del kap
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "kappa_ms_plain": ms0, "line_evals_plain": ev0, "tolerances": rows}
+
+
 def form_arith(rtlbl, I):
     """FP32 arithmetic of the device (the paper's Table 2 experiments), in
     brief: which basic operations are correctly rounded on random operands,
@@ -467,7 +518,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines,two_gases,table16,arith",
+    ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines,two_gases,table16,"
+                                       "adaptive,arith",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--workload", default="plain_32cube")
     ap.add_argument("--copy-probe", action="store_true",
@@ -572,7 +624,7 @@ def main():
                          ("learned", form_learned),
                          ("learned_dense_lines", lambda r, i: form_learned(r, i, n_lines=20000)),
                          ("two_gases", form_two_gases), ("table16", form_table16),
-                         ("arith", form_arith)):
+                         ("adaptive", form_adaptive), ("arith", form_arith)):
             if name not in args.forms.split(","):
                 continue
             try:

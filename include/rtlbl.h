@@ -52,7 +52,7 @@ typedef enum {
   RT_KAPPA_COMPENSATED = 1,  /* FP32 line sum with compensated summation    */
   RT_KAPPA_SURROGATE = 2,    /* learned form (rt_surrogate_train/load), with
                                 line-sum fallback and a sampled check       */
-  RT_KAPPA_TABLE16 = 3       /* the paper's own formulation (Section 3 and its
+  RT_KAPPA_TABLE16 = 3,      /* the paper's own formulation (Section 3 and its
                                 listing): each line contributes at the 16 grid
                                 points m-7 .. m+8 around its centre through a
                                 profile tabulated once at the reference state
@@ -60,7 +60,17 @@ typedef enum {
                                 the density and the Eq. (1) strength ratio;
                                 multiply-adds only, no per-cell half width.  An
                                 approximation of the plain sum, every gas. */
+  RT_KAPPA_ADAPTIVE = 4      /* the paper's announced next version (its
+                                conclusion): the points evaluated per line
+                                follow the local temperature and the line's
+                                intensity.  The FP32 line sum of the plain
+                                mode over adaptive windows: see
+                                rt_set_line_tolerance.  Gas 0 only. */
 } rt_kappa_mode;
+
+/* Cells sharing one line window in RT_KAPPA_ADAPTIVE: cell c belongs to the
+ * run c / RT_ADAPTIVE_GROUP of consecutive cells (x fastest). */
+#define RT_ADAPTIVE_GROUP 8
 
 /* Form of the march (Eq. (3)); per-cell accumulators are FP64 in both.
  *   RT_TALLY_F32: plain form.  Planck values evaluated in registers (FP32),
@@ -161,6 +171,29 @@ int rt_march_chunk(void);
  * mode: rt_kappa_mode. */
 rt_status rt_compute_kappa(rt_ctx ctx, int mode, float* kappa_dev,
                            float* planck_dev, int64_t ld);
+
+/* Tolerance eps of RT_KAPPA_ADAPTIVE, 0 < eps < 1 (finite), kept by the
+ * handle until changed.  The windows (decided in binary64, from the
+ * conclusion's announced adaptive evaluation of the lines):
+ *   - reference level of cell c: the band mean of its untruncated line sum,
+ *     u_c sbar_c with sbar_c = sum_i S_i s_ci / (n_nu dnu) over the lines
+ *     whose hard-cutoff window meets the grid (s_ci the Eq. (1) ratio);
+ *   - line i keeps point j in cell c while its Lorentz value there is at
+ *     least eps u_c sbar_c, i.e. within w_ci = sqrt(S_i s_ci g / (pi eps
+ *     sbar_c) - g^2) / dnu grid points of its centre (g = gamma_ci; no point
+ *     when the root is imaginary);
+ *   - the window is shared by the RT_ADAPTIVE_GROUP cells of a run: the
+ *     widest w_ci among them, capped by the hard cutoff, so each cell keeps
+ *     at least what its own rule asks for;
+ *   - point j is kept when it lies in the plain mode's window and
+ *     |j - r_i| <= that half width, r_i = (nu_i - nu0)/dnu.
+ * With sbar_c = 0 (no line strength at all) the plain window is kept.
+ * Every dropped term of cell c is below eps u_c sbar_c.  rt_get_stats
+ * counts the kept (cell, line, point) evaluations as line_evals.  The
+ * windows are recomputed by every rt_compute_kappa in this mode, in a
+ * table the handle owns: 4 bytes per (run of cells, kept line).
+ * Needs cutoff/dnu <= 32767.  Returns RT_EINVAL for eps outside (0, 1). */
+rt_status rt_set_line_tolerance(rt_ctx ctx, double eps);
 
 /* Monte-Carlo rays (Section 3: the host directs the rays and averages their
  * effect).  Traces rays ray_begin .. ray_begin+ray_count-1 of a set of

@@ -533,8 +533,23 @@ int orc_kappa_adaptive(int n_cells_listed, const int32_t* cell_list, int n_cells
 
 /* Number of (cell, line, grid point) evaluations the adaptive form keeps
  * over the whole grid.  The kept points of a line are contiguous around its
- * centre (fabs(j - r) grows monotonically away from r), so each side is
- * counted by walking outward from the centre until a point is not kept. */
+ * centre (fabs(j - r) grows monotonically away from r, and the hard window
+ * is an interval), so on each side of c0 = floor(r) the last kept offset is
+ * found by bisection on the kept test itself; offsets beyond K + 1 are
+ * never kept. */
+static long orc_last_kept(double c0, int dir, double r, double K, double hw) {
+  /* largest t >= t0 with c0 + dir t kept, t0 = 1 above and 0 below the
+   * centre; t0 - 1 when none is */
+  long t0 = dir > 0 ? 1 : 0;
+  if (!orc_kept(c0 + dir * (double)t0, r, K, hw)) return t0 - 1;
+  long lo = t0, hi = (long)K + 2;     /* kept at lo, not kept at hi */
+  while (hi - lo > 1) {
+    long mid = lo + (hi - lo) / 2;
+    if (orc_kept(c0 + dir * (double)mid, r, K, hw)) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 double orc_adaptive_evals(int n_cells, const double* T, const double* p, int n_lines,
                           const double* nu_line, const double* S_ref, const double* gamma_ref,
                           const double* n_T, const double* E_lower, double T_ref,
@@ -565,10 +580,17 @@ double orc_adaptive_evals(int n_cells, const double* T, const double* p, int n_l
                                    gamma_ref, n_T, E_lower, T_ref, dnu, eps, K);
       if (hw < 0.0) continue;
       double c0 = floor(r);
-      for (double jd = c0 + 1.0; orc_kept(jd, r, K, hw); jd += 1.0)
-        if (jd >= 0.0 && jd <= (double)(n_nu - 1)) kept += 1.0;
-      for (double jd = c0; orc_kept(jd, r, K, hw); jd -= 1.0)
-        if (jd >= 0.0 && jd <= (double)(n_nu - 1)) kept += 1.0;
+      double top = (double)(n_nu - 1);
+      /* above: c0 + 1 .. c0 + tu; below: c0 - tl .. c0; each clipped to the grid */
+      long tu = orc_last_kept(c0, +1, r, K, hw), tl = orc_last_kept(c0, -1, r, K, hw);
+      if (tu >= 1) {
+        double a0 = fmax(c0 + 1.0, 0.0), a1 = fmin(c0 + (double)tu, top);
+        if (a1 >= a0) kept += a1 - a0 + 1.0;
+      }
+      if (tl >= 0) {
+        double b0 = fmax(c0 - (double)tl, 0.0), b1 = fmin(c0, top);
+        if (b1 >= b0) kept += b1 - b0 + 1.0;
+      }
     }
     total += kept * (double)members;
   }

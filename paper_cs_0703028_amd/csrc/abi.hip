@@ -55,6 +55,8 @@ void free_lineset(rt::LineSet& L) {
   dev_free(L.m); dev_free(L.phi); dev_free(L.wlo); dev_free(L.whi); dev_free(L.S);
   dev_free(L.E2); dev_free(L.nu); dev_free(L.gamma); dev_free(L.nexp); dev_free(L.prof16);
   dev_free(L.tile16);
+  dev_free(L.r64); dev_free(L.S64); dev_free(L.g64); dev_free(L.n64);
+  dev_free(L.aE); dev_free(L.eE_ref); dev_free(L.bN); dev_free(L.eN_ref);
   L.n = 0;
   L.n_tiles16 = 0;
 }
@@ -179,6 +181,8 @@ rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream) {
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_slots), 2 * rt::kSlots * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_balance), 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_segcount), sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_adapt_evals), sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->d_adapt_evals, 0, sizeof(unsigned long long));
   if (e != hipSuccess) {
     rt_destroy(c);
     return fail(nullptr, RT_ENOMEM, std::string("rt_create: ") + hipGetErrorString(e));
@@ -198,6 +202,7 @@ rt_status rt_destroy(rt_ctx c) {
   dev_free(c->d_bwall);
   dev_free(c->d_abs); dev_free(c->d_emi); dev_free(c->d_slots); dev_free(c->d_balance);
   dev_free(c->d_segcount);
+  dev_free(c->d_sbar); dev_free(c->d_win); dev_free(c->d_adapt_evals); dev_free(c->d_und);
   dev_free(c->d_segs); dev_free(c->d_counts); dev_free(c->d_rays_explicit); dev_free(c->d_exit);
   dev_free(c->d_keys); dev_free(c->d_perm); dev_free(c->d_hist);
   free_events(c->trace_events); free_events(c->march_events); free_events(c->kappa_events);
@@ -309,6 +314,7 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   std::vector<int32_t> hm(nl), hwlo(nl), hwhi(nl);
   std::vector<float> hphi(nl), hS(nl), hg(nl), hn(nl);
   std::vector<double> hE2(nl), hnu(nl);
+  std::vector<double> hr64(nl), hS64(nl), hg64(nl), hn64(nl), haE(nl), heE(nl), hbN(nl), heN(nl);
   std::vector<float> hprof((size_t)nl * 16);
   for (int k = 0; k < nl; ++k) {
     // the 16 tabulated points j = m - 7 .. m + 8, at distance j - r from the
@@ -334,6 +340,17 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
     hnu[k] = nu[i];
     hg[k] = (float)gamma[i];
     hn[k] = (float)n_T[i];
+    // binary64 data of the adaptive windows, with the definition's own
+    // operations: -c2 E / T is (-c2 E) / T, and the reference-state factors
+    // exp(-c2 E / T_ref) and expm1(-c2 nu / T_ref) are per-line constants
+    hr64[k] = q.r;
+    hS64[k] = S[i];
+    hg64[k] = gamma[i];
+    hn64[k] = n_T[i];
+    haE[k] = E ? -c2 * E[i] : 0.0;
+    heE[k] = std::exp(haE[k] / T_ref);
+    hbN[k] = -c2 * nu[i];
+    heN[k] = std::expm1(hbN[k] / T_ref);
   }
   RT_HIP(c, dev_alloc(&L.m, nl));
   RT_HIP(c, dev_alloc(&L.phi, nl));
@@ -345,6 +362,15 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   RT_HIP(c, dev_alloc(&L.gamma, nl));
   RT_HIP(c, dev_alloc(&L.nexp, nl));
   RT_HIP(c, dev_alloc(&L.prof16, (size_t)nl * 16));
+  {
+    double** d64[8] = {&L.r64, &L.S64, &L.g64, &L.n64, &L.aE, &L.eE_ref, &L.bN, &L.eN_ref};
+    const std::vector<double>* h64[8] = {&hr64, &hS64, &hg64, &hn64, &haE, &heE, &hbN, &heN};
+    for (int k = 0; k < 8; ++k) {
+      RT_HIP(c, dev_alloc(d64[k], nl));
+      if (nl > 0)
+        RT_HIP(c, hipMemcpy(*d64[k], h64[k]->data(), nl * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
   // per 256-point tile, the lines with m in [256 t - 8, 256 t + 255 + 7]
   const int n_t16 = (n_nu + 255) / 256;
   std::vector<int2> ht16(n_t16);
@@ -483,13 +509,28 @@ int64_t rt_required_pitch(rt_ctx c) {
   return ((int64_t)c->n_nu + rt::kChunk - 1) / rt::kChunk * rt::kChunk;
 }
 
+rt_status rt_set_line_tolerance(rt_ctx c, double eps) {
+  if (!c) return fail(c, RT_EINVAL, "rt_set_line_tolerance: NULL handle");
+  if (!(eps > 0 && eps < 1)) return fail(c, RT_EINVAL, "rt_set_line_tolerance: eps must be in (0, 1)");
+  c->line_tol = eps;
+  return RT_OK;
+}
+
 rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_dev, int64_t ld) {
   if (!c) return fail(c, RT_EINVAL, "rt_compute_kappa: NULL handle");
   if (!c->have_grid || !c->have_lines)
     return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_setup_grid and rt_setup_lines first");
   if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED && mode != RT_KAPPA_SURROGATE &&
-      mode != RT_KAPPA_TABLE16)
+      mode != RT_KAPPA_TABLE16 && mode != RT_KAPPA_ADAPTIVE)
     return fail(c, RT_EINVAL, "rt_compute_kappa: unknown mode");
+  if (mode == RT_KAPPA_ADAPTIVE) {
+    if (!(c->line_tol > 0))
+      return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_set_line_tolerance before the adaptive mode");
+    if (n_gases(c) > 1)
+      return fail(c, RT_EUNSUPPORTED, "rt_compute_kappa: the adaptive windows cover gas 0 only");
+    if (c->K > 32767)
+      return fail(c, RT_EUNSUPPORTED, "rt_compute_kappa: the adaptive windows need cutoff/dnu <= 32767");
+  }
   if (mode == RT_KAPPA_SURROGATE &&
       (!c->surrogate || !rt::surrogate_ready(c)))
     return fail(c, RT_ESTATE, "rt_compute_kappa: no trained surrogate for this spectral grid");
@@ -510,6 +551,31 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     RT_HIP(c, dev_alloc(&c->d_bwall, (size_t)ld));
     c->bwall_len = ld;
   }
+  if (mode == RT_KAPPA_ADAPTIVE) {
+    const int64_t runs = (c->n_cells + RT_ADAPTIVE_GROUP - 1) / RT_ADAPTIVE_GROUP;
+    const int64_t win = runs * (int64_t)std::max(c->lines.n, 1);
+    if (c->sbar_cap < c->n_cells) {  // sbar, partition ratio, screening factor per cell
+      dev_free(c->d_sbar);
+      c->sbar_cap = 0;
+      RT_HIP(c, dev_alloc(&c->d_sbar, (size_t)(3 * c->n_cells)));
+      c->sbar_cap = c->n_cells;
+    }
+    // room for 1/16 of the windows to be left to binary64 (about 0.3% are
+    // at eps = 1e-5 on a 32^3 grid); any beyond are found by a scan
+    const int64_t und = std::max<int64_t>(4096, win / 16);
+    if (c->und_cap < und) {
+      dev_free(c->d_und);
+      c->und_cap = 0;
+      RT_HIP(c, dev_alloc(&c->d_und, (size_t)(und + 1)));
+      c->und_cap = und;
+    }
+    if (c->win_cap < win) {
+      dev_free(c->d_win);
+      c->win_cap = 0;
+      RT_HIP(c, dev_alloc(&c->d_win, (size_t)win));
+      c->win_cap = win;
+    }
+  }
   c->kappa = kappa_dev;
   c->planck = planck_dev;
   c->ld = ld;
@@ -524,6 +590,8 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     if (rt_status s = rt::surrogate_kappa(c)) return s;
   } else if (mode == RT_KAPPA_TABLE16) {
     RT_HIP(c, rt::launch_kappa_table16(c));
+  } else if (mode == RT_KAPPA_ADAPTIVE) {
+    RT_HIP(c, rt::launch_kappa_adaptive(c));
   } else {
     RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
   }
@@ -534,7 +602,8 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     for (const auto& g : c->gas)
       if (g.active) lines += g.lines.n;
     c->stats.line_evals += 16.0 * lines * (double)c->n_cells;
-  } else if (mode != RT_KAPPA_SURROGATE) {
+  } else if (mode != RT_KAPPA_SURROGATE && mode != RT_KAPPA_ADAPTIVE) {
+    // (the adaptive windows count their kept evaluations on the device)
     double per_cell = c->line_evals_per_cell;
     for (const auto& g : c->gas)
       if (g.active) per_cell += g.line_evals_per_cell;
@@ -672,6 +741,7 @@ rt_status rt_reset_tally(rt_ctx c) {
   if (!c->have_grid) return fail(c, RT_ESTATE, "rt_reset_tally: call rt_setup_grid first");
   if (rt_status s = set_device(c)) return s;
   RT_HIP(c, rt::launch_zero(c));
+  RT_HIP(c, hipMemsetAsync(c->d_adapt_evals, 0, sizeof(unsigned long long), c->stream));
   double tmp = 0;
   if (rt_status s = drain_events(c, c->trace_events, &tmp)) return s;
   if (rt_status s = drain_events(c, c->march_events, &tmp)) return s;
@@ -737,11 +807,13 @@ rt_status rt_get_stats(rt_ctx c, rt_stats* out) {
   if (rt_status s = drain_events(c, c->kappa_events, &c->stats.kappa_ms)) return s;
   if (rt_status s = drain_events(c, c->trace_events, &c->stats.trace_ms)) return s;
   if (rt_status s = drain_events(c, c->march_events, &c->stats.march_ms)) return s;
-  unsigned long long segs = 0;
+  unsigned long long segs = 0, kept = 0;
   if (c->d_segcount)
     RT_HIP(c, hipMemcpy(&segs, c->d_segcount, sizeof(segs), hipMemcpyDeviceToHost));
+  if (c->d_adapt_evals)
+    RT_HIP(c, hipMemcpy(&kept, c->d_adapt_evals, sizeof(kept), hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof(*out));
-  out->line_evals = c->stats.line_evals;
+  out->line_evals = c->stats.line_evals + (double)kept;
   out->kappa_ms = c->stats.kappa_ms;
   out->segments = (double)segs;
   out->updates = (double)segs * (double)c->n_nu;

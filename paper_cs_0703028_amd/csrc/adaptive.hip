@@ -1,0 +1,521 @@
+// adaptive.hip -- adaptive line windows on gfx950: the paper's announced
+// next version (its conclusion), in which the number of points evaluated per
+// line follows the local temperature and the line's intensity.
+//
+//   adaptive_sbar_kernel   : per cell, sbar = sum_i S_i s_i / (n_nu dnu)
+//                            (band mean of the untruncated line sum over the
+//                            density) and the partition ratio q, in binary64
+//   adaptive_window_kernel : per (run of 8 cells, line), the shared window
+//                            [lo, hi] around m_i, packed as two 16-bit
+//                            offsets, wherever FP32 bounds on the half width
+//                            already fix it; counts the kept evaluations
+//   adaptive_window_list_kernel, adaptive_window_scan_kernel : the rest, in
+//                            binary64 with the definition's operations (the
+//                            screening lists them; the scan takes any the
+//                            list had no room for)
+//   kappa_adaptive_kernel  : the plain FP32 line sum of Eq. (2) over those
+//                            windows.  Each wavefront sums only the staged
+//                            lines whose window meets its 128 points, first
+//                            those covering all of them (no membership
+//                            test), then the rest
+//
+// A line keeps point j of cell c while its Lorentz value there is at least
+// eps u_c sbar_c: |j - r_i| <= w_ci = sqrt(S s g / (pi eps sbar) - g^2)/dnu
+// (no point when the root is imaginary).  The run's window is the widest of
+// its cells', capped by the hard cutoff, and intersected with the plain
+// window [m - K + [phi > 0], m + K].  The same decision in the same
+// precision is what makes the windows, and so the kept terms, those of the
+// definition; only the transcendental functions' last bits can differ.
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace rt {
+namespace {
+
+using namespace dev;
+
+static_assert(kKappaCells == RT_ADAPTIVE_GROUP, "a line-sum block holds one run of cells");
+static_assert(kLineTile <= 256, "staged line indices are kept in bytes");
+
+constexpr int kAdThreads = 256;
+constexpr int kAdRec = 4 + 2 * kKappaCells;  // floats per staged line
+
+// Eq. (1) strength ratio in binary64: q exp(-c2 E / T) / exp(-c2 E / T_ref)
+// * expm1(-c2 nu / T) / expm1(-c2 nu / T_ref), the reference-state factors
+// per line, q = (T_ref / T)^1.5 per cell.
+__device__ inline double sratio64(const LineSet& L, int i, double T, double q, int have_E) {
+#pragma clang fp contract(off)
+  if (!have_E) return 1.0;
+  const double boltz = exp(L.aE[i] / T) / L.eE_ref[i];
+  const double stim = expm1(L.bN[i] / T) / L.eN_ref[i];
+  return q * boltz * stim;
+}
+
+// Per cell: sbar = sum_i S_i s_ci / (n_nu dnu) (binary64, the lines in their
+// sorted order), q = (T_ref/T)^1.5 and 1/(pi eps sbar dnu), the factor that
+// turns S s g / dnu into the screening's ratio in grid units.  Block 0 also
+// clears the count of undecided windows.
+__global__ __launch_bounds__(kAdThreads) void adaptive_sbar_kernel(LineSet L, const double* __restrict__ T,
+                                                                   double T_ref, int have_E, double band,
+                                                                   double pi_eps_dnu, int64_t n_cells,
+                                                                   double* __restrict__ cellv,
+                                                                   unsigned long long* __restrict__ und) {
+#pragma clang fp contract(off)
+  __shared__ double red[kAdThreads];
+  const int64_t c = blockIdx.x;
+  if (c == 0 && threadIdx.x == 0) *und = 0;
+  const double Tc = T[c];
+  const double q = have_E ? pow(T_ref / Tc, 1.5) : 1.0;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < L.n; i += kAdThreads) acc += L.S64[i] * sratio64(L, i, Tc, q, have_E);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kAdThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double sb = red[0] / band;
+    cellv[c] = sb;
+    cellv[n_cells + c] = q;
+    cellv[2 * n_cells + c] = 1.0 / (pi_eps_dnu * sb);
+  }
+}
+
+struct WindowArgs {
+  LineSet L;
+  CellSet C;
+  const double* T;
+  const double* p;
+  const double* sbar;
+  const double* q;
+  const double* inv_den;  // 1/(pi eps sbar dnu) per cell
+  int64_t n_cells;
+  int64_t n_runs;
+  int have_E;
+  double T_ref, dnu, eps;
+  int K, n_nu;
+  uint32_t* win;
+  unsigned long long* kept;
+  unsigned long long* und;  // [0]: undecided count, [1 .. und_cap]: their indices
+  int64_t und_cap;
+};
+
+// A window entry not decided by the screening pass (lo offset 32767 with hi
+// offset -32768: no real window, whose offsets lie in [-K, K] with K <= 32767).
+constexpr uint32_t kUndecided = 0x80007fffu;
+
+// Half width in grid points of line i in cell c, -1 for none, in binary64
+// with the definition's operations.
+__device__ inline double window_points(const WindowArgs& a, int i, int64_t c) {
+#pragma clang fp contract(off)
+  const double sb = a.sbar[c];
+  if (sb == 0.0) return (double)a.K;
+  const double Tc = a.T[c];
+  const double s = sratio64(a.L, i, Tc, a.q[c], a.have_E);
+  const double g = a.L.g64[i] * a.p[c] * pow(a.T_ref / Tc, a.L.n64[i]);
+  const double num = a.L.S64[i] * s * g;
+  const double den = M_PI * a.eps * sb;
+  const double W2 = num / den - g * g;
+  if (W2 < 0.0) return -1.0;
+  return sqrt(W2) / a.dnu;
+}
+
+// Bounds [lo, hi] on window_points(a, i, c), in grid units, from FP32
+// arithmetic: ratio = S s gp / (pi eps sbar dnu) and gp = g / dnu, so that
+// w = sqrt(ratio - gp^2).  Relative errors: S / (1 - exp(-c2 nu/T_ref)),
+// gamma, p/dnu, q, the FP64 product S/(pi eps sbar dnu) each 6e-8 (one FP32
+// rounding); the Boltzmann factor 2.2e-7 (exp_split, |argument| < 80, result
+// normal); the stimulated-emission factor 6.5e-7 (one_minus_exp_neg_d, at
+// most 3.5 times exp_split's error where it subtracts); 2^(n log2(T_ref/T))
+// 6.2e-7 (|argument| < 4, off by 1.8e-7 relative, plus 1 ulp); four FP32
+// products 2.4e-7.  Hence ratio within 2.1e-6 and gp^2 within 1.4e-6 of
+// their exact values, and W2 = ratio - gp^2 (rounded once more) within
+// 2.2e-6 (ratio + gp^2); the bound used is 5e-6 (ratio + gp^2).  The square
+// root (1 ulp) and the scalings are covered by the factors 1 -+ 1e-6.
+// -1 stands for "no point".  Returns false outside those ranges (then
+// binary64 decides).
+__device__ inline bool window_bounds(const WindowArgs& a, int i, int64_t c, float& lo, float& hi) {
+  const double sb = a.sbar[c];
+  if (sb == 0.0) {
+    lo = hi = (float)a.K;
+    return true;
+  }
+  const float t = (float)((double)a.L.S[i] * a.inv_den[c]);
+  if (!(t == 0.f || (t > 1e-30f && t < 1e30f))) return false;
+  float s = 1.f;
+  if (a.have_E) {
+    const double yb = -a.L.aE[i] * a.C.beta[c];       // -c2 E (1/T_ref - 1/T)
+    const double ys = a.L.nu[i] * a.C.theta[c];       // c2 nu / T
+    if (!(fabs(yb) < 80.0) || !(ys < 80.0)) return false;
+    s = (float)a.q[c] * exp_split(yb) * one_minus_exp_neg_d(ys);
+  }
+  const float yg = a.L.nexp[i] * a.C.lam2[c];         // n log2(T_ref / T)
+  if (!(fabsf(yg) < 4.f)) return false;
+  const float gp = a.L.gamma[i] * a.C.P[c] * fast_exp2(yg);
+  const float ratio = t * s * gp;
+  const float g2 = gp * gp;
+  const float W2 = ratio - g2;
+  const float err = 5e-6f * (ratio + g2);
+  if (!(ratio < 1e30f)) return false;
+  hi = W2 + err < 0.f ? -1.f : __builtin_sqrtf(W2 + err) * (1.f + 1e-6f);
+  lo = W2 - err < 0.f ? -1.f : __builtin_sqrtf(W2 - err) * (1.f - 1e-6f);
+  return true;
+}
+
+// The kept points of a line with half width hw: {j : |j - r| <= hw} (an
+// interval, |j - r| growing away from r) within the plain window
+// [wlo, whi].  The ends from the rounded r +- hw are off by at most one and
+// are settled by the test itself.  False when empty.
+__device__ inline bool kept_interval(double r, double hw, int wlo, int whi, int& lo, int& hi) {
+  if (hw < 0.0) return false;
+  auto in = [&](int j) { return fabs((double)j - r) <= hw; };
+  int h = (int)floor(r + hw);
+  if (in(h + 1)) ++h;
+  else if (!in(h)) --h;
+  int l = (int)ceil(r - hw);
+  if (in(l - 1)) --l;
+  else if (!in(l)) ++l;
+  if (!(l <= h && in(l) && in(h))) return false;
+  lo = l > wlo ? l : wlo;
+  hi = h < whi ? h : whi;
+  return lo <= hi;
+}
+
+// Packs the window and returns the kept in-grid evaluations of the run.
+__device__ inline unsigned long long store_window(const WindowArgs& a, int64_t idx, int i,
+                                                  bool any, int lo, int hi, int members) {
+  const int m = a.L.m[i];
+  int lo_off = 1, hi_off = 0;  // empty
+  unsigned long long kept = 0;
+  if (any) {
+    lo_off = (int)(lo - m);
+    hi_off = (int)(hi - m);
+    const int g0 = lo > 0 ? lo : 0;
+    const int g1 = hi < a.n_nu - 1 ? hi : a.n_nu - 1;
+    if (g1 >= g0) kept = (unsigned long long)(g1 - g0 + 1) * (unsigned long long)members;
+  }
+  a.win[idx] = (uint32_t)(uint16_t)(int16_t)lo_off | ((uint32_t)(uint16_t)(int16_t)hi_off << 16);
+  return kept;
+}
+
+__device__ inline void add_block_count(unsigned long long v, unsigned long long* total) {
+  __shared__ unsigned long long red[kAdThreads];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = kAdThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(total, red[0]);
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Screening pass over (run, line): the run's half width lies between the
+// largest lower and the largest upper bound of its cells; when the kept
+// points are the same at both ends they are those of the binary64 value
+// (the kept set grows with hw), else the entry is marked undecided and
+// listed for the binary64 pass.  A fixed grid walks the work items (run of
+// cells, 256 lines), so that the run -- and every cell quantity -- is the
+// same across a block; counts stay in registers and undecided indices are
+// gathered in LDS, leaving a few global atomics per block (same-address
+// atomics serialise in L2).
+constexpr int kUndBuf = 1024;
+__global__ __launch_bounds__(kAdThreads) void adaptive_window_kernel(WindowArgs a, int line_blocks,
+                                                                     int64_t items) {
+  __shared__ unsigned long long ubuf[kUndBuf];
+  __shared__ unsigned ucount;
+  __shared__ unsigned long long ubase;
+  const int nl = a.L.n;
+  if (threadIdx.x == 0) ucount = 0;
+  __syncthreads();
+  unsigned long long kept = 0;
+  auto flush = [&]() {
+    __syncthreads();
+    const unsigned n = ucount;
+    if (n > 0) {
+      if (threadIdx.x == 0) ubase = atomicAdd(a.und, (unsigned long long)n);
+      __syncthreads();
+      for (unsigned k = threadIdx.x; k < n; k += kAdThreads)
+        if (ubase + k < (unsigned long long)a.und_cap) a.und[1 + ubase + k] = ubuf[k];
+      __syncthreads();
+      if (threadIdx.x == 0) ucount = 0;
+    }
+    __syncthreads();
+  };
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const int64_t run = item / line_blocks;
+    const int i = (int)(item - run * line_blocks) * kAdThreads + (int)threadIdx.x;
+    const int64_t c0 = run * RT_ADAPTIVE_GROUP;
+    const int members = (int)min<int64_t>(RT_ADAPTIVE_GROUP, a.n_cells - c0);
+    if (i < nl) {
+      const int64_t idx = run * nl + i;
+      float wl = -1.f, wu = -1.f;
+      bool ok = true;
+      for (int k = 0; k < members && ok; ++k) {
+        float l, h;
+        ok = window_bounds(a, i, c0 + k, l, h);
+        wl = fmaxf(wl, l);
+        wu = fmaxf(wu, h);
+      }
+      const double K = (double)a.K;
+      const double r = a.L.r64[i];
+      const int wlo = a.L.wlo[i], whi = a.L.whi[i];
+      int l0 = 0, h0 = 0, l1 = 0, h1 = 0;
+      const bool e0 = ok && kept_interval(r, fmin((double)wl, K), wlo, whi, l0, h0);
+      const bool e1 = ok && kept_interval(r, fmin((double)wu, K), wlo, whi, l1, h1);
+      if (ok && e0 == e1 && (!e0 || (l0 == l1 && h0 == h1))) {
+        kept += store_window(a, idx, i, e0, l0, h0, members);
+      } else {
+        a.win[idx] = kUndecided;
+        ubuf[atomicAdd(&ucount, 1u)] = (unsigned long long)idx;  // < kUndBuf: flushed below
+      }
+    }
+    __syncthreads();
+    if (ucount > (unsigned)(kUndBuf - kAdThreads)) flush();
+  }
+  flush();
+  add_block_count(kept, a.kept);
+}
+
+// The binary64 decision of one undecided entry.
+__device__ inline unsigned long long decide_exact(const WindowArgs& a, int64_t idx) {
+#pragma clang fp contract(off)
+  const int nl = a.L.n;
+  const int64_t run = idx / nl;
+  const int i = (int)(idx - run * nl);
+  const int64_t c0 = run * RT_ADAPTIVE_GROUP;
+  const int members = (int)min<int64_t>(RT_ADAPTIVE_GROUP, a.n_cells - c0);
+  double w = -1.0;
+  for (int k = 0; k < members; ++k) {
+    const double wc = window_points(a, i, c0 + k);
+    if (wc > w) w = wc;
+  }
+  const double hw = w < (double)a.K ? w : (double)a.K;
+  int lo = 0, hi = 0;
+  const bool any = kept_interval(a.L.r64[i], hw, a.L.wlo[i], a.L.whi[i], lo, hi);
+  return store_window(a, idx, i, any, lo, hi, members);
+}
+
+// Binary64 pass over the listed undecided entries (grid-stride).
+__global__ __launch_bounds__(kAdThreads) void adaptive_window_list_kernel(WindowArgs a) {
+  const unsigned long long n = min(*a.und, (unsigned long long)a.und_cap);
+  unsigned long long kept = 0;
+  for (unsigned long long k = (unsigned long long)blockIdx.x * kAdThreads + threadIdx.x; k < n;
+       k += (unsigned long long)gridDim.x * kAdThreads)
+    kept += decide_exact(a, (int64_t)a.und[1 + k]);
+  add_block_count(kept, a.kept);
+}
+
+// Entries beyond the list's capacity (none unless more than und_cap were
+// undecided): a scan of the whole table, each block leaving at once when
+// the list held them all.
+__global__ __launch_bounds__(kAdThreads) void adaptive_window_scan_kernel(WindowArgs a) {
+  if (*a.und <= (unsigned long long)a.und_cap) return;
+  const int64_t idx = (int64_t)blockIdx.x * kAdThreads + threadIdx.x;
+  unsigned long long kept = 0;
+  if (idx < a.n_runs * a.L.n && a.win[idx] == kUndecided) kept = decide_exact(a, idx);
+  add_block_count(kept, a.kept);
+}
+
+// One block: points [j0, j0 + 512) of the run of 8 cells `run`, as the plain
+// line-sum tile (dev::kappa_tile) with a window per (run, line).  Staged
+// record per line: m, phi, lo, hi (offsets from m) and, per cell, the
+// Lorentz amplitude and squared half width in grid units.
+__global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile a,
+                                                                       const uint32_t* __restrict__ win,
+                                                                       int n_tiles) {
+  constexpr int C = kKappaCells, P = kKappaPoints;
+  __shared__ float4 lds4[kLineTile * kAdRec / 4];
+  __shared__ uint8_t lists[kKappaThreads / 64][kLineTile];
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int tile = blockIdx.x % n_tiles;
+  const int64_t run = blockIdx.x / n_tiles;
+  const int j0 = tile * kKappaTilePoints;
+  const int64_t cell0 = run * C;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int span = 64 * P;
+  const int wj0 = j0 + wave * span;
+  const int nl = a.L.n;
+  const int blk_first = first_ge(a.L.whi, nl, j0);
+  const int blk_end = first_gt(a.L.wlo, nl, j0 + kKappaTilePoints - 1);
+  const uint32_t* wrow = win + run * (int64_t)nl;
+
+  float jf[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) jf[p] = (float)(wj0 + 64 * p + lane);
+  float acc[P][C];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[p][c] = 0.f;
+
+  auto add_line = [&](auto full_tag, int l) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    const float* rec = lds + l * kAdRec;
+    const float4 h = *reinterpret_cast<const float4*>(rec);
+    float dv[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const float t = jf[p] - h.x;
+      const float d = t - h.y;
+      if (FULL) {
+        dv[p] = d;
+      } else {
+        const bool in = (t >= h.z) & (t <= h.w);
+        dv[p] = in ? d : __builtin_inff();
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; c += 2) {
+      const float4 ag = *reinterpret_cast<const float4*>(rec + 4 + 2 * c);
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        acc[p][c] = fmaf(ag.x, fast_rcp(fmaf(dv[p], dv[p], ag.y)), acc[p][c]);
+        acc[p][c + 1] = fmaf(ag.z, fast_rcp(fmaf(dv[p], dv[p], ag.w)), acc[p][c + 1]);
+      }
+    }
+  };
+
+  for (int base = blk_first; base < blk_end; base += kLineTile) {
+    const int nt = min(kLineTile, blk_end - base);
+    __syncthreads();
+    for (int q = tid; q < nt * C; q += kKappaThreads) {
+      const int li = q / C, cc = q % C;
+      const int i = base + li;
+      int64_t cell = cell0 + cc;
+      if (cell >= a.n_cells) cell = a.n_cells - 1;
+      float* rec = lds + li * kAdRec;
+      if (cc == 0) {
+        const uint32_t w = wrow[i];
+        rec[0] = (float)a.L.m[i];
+        rec[1] = a.L.phi[i];
+        rec[2] = (float)(int16_t)(uint16_t)(w & 0xffffu);
+        rec[3] = (float)(int16_t)(uint16_t)(w >> 16);
+      }
+      const float gp = a.L.gamma[i] * a.C.P[cell] * fast_exp2(a.L.nexp[i] * a.C.lam2[cell]);
+      float amp = a.C.G[cell] * a.L.S[i] * gp;
+      if (a.have_E) {
+        amp *= exp_split(a.L.E2[i] * a.C.beta[cell]);
+        amp *= one_minus_exp_neg_d(a.L.nu[i] * a.C.theta[cell]);
+      }
+      rec[4 + 2 * cc] = amp;
+      rec[5 + 2 * cc] = gp * gp;
+    }
+    __syncthreads();
+    // this wavefront's lines: those whose window meets [wj0, wj0 + span);
+    // indices of lines covering all of it from the front of the list, the
+    // others from the back
+    int nf = 0, np = 0;
+    for (int l0 = 0; l0 < nt; l0 += 64) {
+      const int l = l0 + lane;
+      bool meet = false, full = false;
+      if (l < nt) {
+        const float4 h = *reinterpret_cast<const float4*>(lds + l * kAdRec);
+        const int m = (int)h.x, w0 = m + (int)h.z, w1 = m + (int)h.w;
+        meet = w0 <= w1 && w0 <= wj0 + span - 1 && w1 >= wj0;
+        full = meet && w0 <= wj0 && w1 >= wj0 + span - 1;
+      }
+      const uint64_t bf = __ballot(full), bp = __ballot(meet && !full);
+      if (full) lists[wave][nf + lanes_below(bf)] = (uint8_t)l;
+      if (meet && !full) lists[wave][kLineTile - 1 - (np + lanes_below(bp))] = (uint8_t)l;
+      nf += __popcll(bf);
+      np += __popcll(bp);
+    }
+    __syncthreads();
+    for (int e = 0; e < nf; ++e) add_line(std::true_type(), lists[wave][e]);
+    for (int e = 0; e < np; ++e) add_line(std::false_type(), lists[wave][kLineTile - 1 - e]);
+  }
+
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t cell = cell0 + c;
+    if (cell >= a.n_cells) break;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t j = wj0 + 64 * p + lane;
+      if (j < a.ld_out) a.out[cell * a.ld_out + j] = (j < a.n_nu) ? acc[p][c] : 0.f;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_kappa_adaptive(rt_ctx c) {
+  const LineSet& L = c->lines;
+  const int64_t runs = (c->n_cells + RT_ADAPTIVE_GROUP - 1) / RT_ADAPTIVE_GROUP;
+  const int n_tiles = (int)((c->ld + kKappaTilePoints - 1) / kKappaTilePoints);
+  const int64_t blocks = runs * n_tiles;
+  const int64_t pairs = runs * (int64_t)L.n;
+  const int64_t wblocks = (pairs + kAdThreads - 1) / kAdThreads;
+  const int line_blocks = (L.n + kAdThreads - 1) / kAdThreads;
+  const int64_t sblocks = runs * line_blocks;
+  if (blocks > 0x7fffffffLL || wblocks > 0x7fffffffLL || sblocks > 0x7fffffffLL ||
+      c->n_cells > 0x7fffffffLL)
+    return hipErrorInvalidValue;
+  double* cellv = c->d_sbar;  // [3][cells]: sbar, q, 1/(pi eps sbar dnu)
+  hipLaunchKernelGGL(adaptive_sbar_kernel, dim3((unsigned)c->n_cells), dim3(kAdThreads), 0, c->stream,
+                     L, c->d_T, c->T_ref, c->have_E ? 1 : 0, (double)c->n_nu * c->dnu,
+                     M_PI * c->line_tol * c->dnu, c->n_cells, cellv, c->d_und);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (pairs > 0) {
+    WindowArgs w;
+    w.L = L;
+    w.C = c->cells;
+    w.T = c->d_T;
+    w.p = c->d_p;
+    w.sbar = cellv;
+    w.q = cellv + c->n_cells;
+    w.inv_den = cellv + 2 * c->n_cells;
+    w.n_cells = c->n_cells;
+    w.n_runs = runs;
+    w.have_E = c->have_E ? 1 : 0;
+    w.T_ref = c->T_ref;
+    w.dnu = c->dnu;
+    w.eps = c->line_tol;
+    w.K = c->K;
+    w.n_nu = c->n_nu;
+    w.win = c->d_win;
+    w.kept = c->d_adapt_evals;
+    w.und = c->d_und;
+    w.und_cap = c->und_cap;
+    const int64_t sgrid = std::min<int64_t>(sblocks, 4096);
+    hipLaunchKernelGGL(adaptive_window_kernel, dim3((unsigned)sgrid), dim3(kAdThreads), 0, c->stream, w,
+                       line_blocks, sblocks);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t lblocks = std::min<int64_t>((c->und_cap + kAdThreads - 1) / kAdThreads, 4096);
+    hipLaunchKernelGGL(adaptive_window_list_kernel, dim3((unsigned)lblocks), dim3(kAdThreads), 0,
+                       c->stream, w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(adaptive_window_scan_kernel, dim3((unsigned)wblocks), dim3(kAdThreads), 0,
+                       c->stream, w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  KappaTile t;
+  t.L = L;
+  t.C = c->cells;
+  t.n_cells = c->n_cells;
+  t.n_nu = c->n_nu;
+  t.K = c->K;
+  t.have_E = c->have_E ? 1 : 0;
+  t.out = c->kappa;
+  t.ld_out = c->ld;
+  t.col0 = 0;
+  t.col_end = c->ld;
+  hipLaunchKernelGGL(kappa_adaptive_kernel, dim3((unsigned)blocks), dim3(kKappaThreads), 0, c->stream, t,
+                     c->d_win, n_tiles);
+  return hipGetLastError();
+}
+
+}  // namespace rt

@@ -50,6 +50,17 @@ struct LineSet {
   // sorted list, int2 per tile (t = 0 .. n_tiles16 - 1)
   int2* tile16 = nullptr;
   int n_tiles16 = 0;
+  // binary64 line data for the adaptive windows, decided in binary64 with
+  // the same operations as the definition: r = (nu - nu0)/dnu, S_ref,
+  // gamma_ref, n_T, a = -c2 E, exp(a / T_ref), b = -c2 nu, expm1(b / T_ref)
+  double* r64 = nullptr;
+  double* S64 = nullptr;
+  double* g64 = nullptr;
+  double* n64 = nullptr;
+  double* aE = nullptr;
+  double* eE_ref = nullptr;
+  double* bN = nullptr;
+  double* eN_ref = nullptr;
 };
 
 // Per-cell derived parameters (device), from FP64 on the device.
@@ -120,6 +131,21 @@ struct rt_ctx_s {
   // and T_ref, and its own mole fraction per cell
   rt::ExtraGas gas[rt::kMaxGases - 1];
 
+  // adaptive line windows (RT_KAPPA_ADAPTIVE): tolerance (0 = not set),
+  // per-cell sbar, partition ratio and screening factor (FP64, [3][cells]),
+  // window table
+  // [run of cells][line] (owned) and the device count of kept evaluations
+  // since the last reset
+  double line_tol = 0;
+  double* d_sbar = nullptr;
+  int64_t sbar_cap = 0;
+  uint32_t* d_win = nullptr;
+  int64_t win_cap = 0;
+  // windows the FP32 screening leaves to binary64: [0] count, then indices
+  unsigned long long* d_und = nullptr;
+  int64_t und_cap = 0;
+  unsigned long long* d_adapt_evals = nullptr;
+
   // derived per-cell parameters and tables
   rt::CellSet cells;
   bool cells_valid = false;
@@ -174,6 +200,10 @@ hipError_t launch_kappa(rt_ctx c, bool compensated);
 // The paper's kappa formulation (16 tabulated points per line, multiply-adds
 // only), every gas, into c->kappa.
 hipError_t launch_kappa_table16(rt_ctx c);
+// Adaptive line windows for gas 0 into c->kappa: per-cell band means, the
+// window table (c->d_win, sized by the caller) and the windowed line sum;
+// adds the kept evaluations to *c->d_adapt_evals.
+hipError_t launch_kappa_adaptive(rt_ctx c);
 hipError_t launch_planck(rt_ctx c);
 hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,
                          int64_t* rays_out, bool count_work, const uint32_t* perm);

@@ -21,7 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtlbl.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE, KAPPA_TABLE16 = 0, 1, 2, 3
+KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE, KAPPA_TABLE16, KAPPA_ADAPTIVE = 0, 1, 2, 3, 4
+ADAPTIVE_GROUP = 8   # RT_ADAPTIVE_GROUP: cells sharing one line window
 TALLY_F32, TALLY_F64 = 0, 1
 # rt_arith_op: name -> (code, operands read)
 ARITH_OPS = {
@@ -102,6 +103,7 @@ def _load():
     L.rt_march_chunk.argtypes = []
     L.rt_march_chunk.restype = C.c_int
     L.rt_compute_kappa.argtypes = [vp, C.c_int, vp, vp, C.c_int64]
+    L.rt_set_line_tolerance.argtypes = [vp, C.c_double]
     L.rt_trace_rays.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int]
     L.rt_trace_explicit.argtypes = [vp, C.c_int, _i64p, _i64p, C.c_double, C.c_int, vp]
     L.rt_tally.argtypes = [vp, vp, vp, vp]
@@ -250,6 +252,10 @@ class Tracer:
         dev = torch.device("cuda", self.device)
         return (torch.empty((n, ld), dtype=torch.float32, device=dev),
                 torch.empty((n, ld), dtype=torch.float32, device=dev))
+
+    def set_line_tolerance(self, eps):
+        """Tolerance of the adaptive line windows (KAPPA_ADAPTIVE), 0 < eps < 1."""
+        self._check(lib.rt_set_line_tolerance(self._h, float(eps)))
 
     def compute_kappa(self, mode=KAPPA_PLAIN, kappa=None, planck=None):
         """Fills `kappa` (and `planck` when given) on the device.  With no

@@ -1,0 +1,156 @@
+"""Adaptive line windows (RT_KAPPA_ADAPTIVE) through the C ABI against the
+FP64 oracle: kappa within 1e-5 relative with exact zeros where the oracle is
+zero (window membership is integer work, decided in binary64 on both
+sides), the kept-evaluation count equal to the oracle's, the march over the
+adaptive table, the full 32^3 workload on sampled runs of cells, and the
+error paths."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from paper_cs_0703028_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rt():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_cs_0703028_amd import rtlbl
+    return rtlbl
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+def _rel(g, o):
+    nz = o != 0
+    assert (g[~nz] == 0).all(), "GPU nonzero where the oracle is exactly zero"
+    return np.abs(g[nz] - o[nz]) / np.abs(o[nz])
+
+
+@pytest.mark.parametrize("wl", ["small_ragged", "plain_8cube"])
+@pytest.mark.parametrize("eps", [1e-3, 1e-5])
+def test_adaptive_kappa_and_count_match_oracle(rt, O, wl, eps):
+    w = getattr(I, wl)()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    t.set_line_tolerance(eps)
+    print(f"adaptive kappa {wl} eps {eps:g}", flush=True)
+    t.reset_tally()
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    n_nu = w.lines.n_nu
+    kg = kap.cpu().numpy().astype(np.float64)
+    ko = O.kappa_adaptive(w.grid, w.lines, eps)
+    assert (kg[:, n_nu:] == 0).all()
+    r = _rel(kg[:, :n_nu], ko)
+    kept = t.stats()["line_evals"]
+    want = O.adaptive_evals(w.grid, w.lines, eps)
+    print(f"  rel err max {r.max():.3e} median {np.median(r):.3e}; kept {kept:.0f} "
+          f"(oracle {want})", flush=True)
+    assert r.max() <= REL
+    assert kept == want
+    # a second call recomputes the windows and adds its count
+    kap2, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE, kappa=kap)
+    assert np.array_equal(kap2.cpu().numpy(), kg.astype(np.float32))
+    assert t.stats()["line_evals"] == 2 * want
+    t.close()
+
+
+def test_vanishing_tolerance_gives_the_plain_sum(rt, O):
+    w = I.small_ragged()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    t.set_line_tolerance(1e-300)
+    t.reset_tally()
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    kept = t.stats()["line_evals"]
+    r = _rel(kap.cpu().numpy().astype(np.float64)[:, :w.lines.n_nu], O.kappa(w.grid, w.lines))
+    print(f"eps 1e-300: rel err vs plain oracle max {r.max():.3e}", flush=True)
+    assert r.max() <= REL
+    t.reset_tally()
+    t.compute_kappa(rt.KAPPA_PLAIN)
+    assert kept == t.stats()["line_evals"]
+    t.close()
+
+
+def test_adaptive_tallies_match_oracle_march(rt, O):
+    w = I.plain_8cube()
+    eps = 1e-4
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    t.set_line_tolerance(eps)
+    t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, 0)
+    ag, eg, _ = t.tally()
+    g = w.grid
+    Or, Dr, _ = O.rays(w.seed, 0, w.n_rays, g.nx, g.ny, g.nz)
+    kap = O.kappa_adaptive(g, w.lines, eps)
+    a, e, _, _ = O.march(g, w.lines, Or, Dr, O.ray_weight(g, w.lines, w.n_rays), kap,
+                         O.planck_rows(g, w.lines))
+    ra, re = _rel(ag, a), _rel(eg, e)
+    print(f"adaptive tallies: absorbed max {ra.max():.3e}, emitted max {re.max():.3e}", flush=True)
+    assert ra.max() <= REL and re.max() <= REL
+    t.close()
+
+
+def test_full_size_32cube_sampled_runs(rt, O):
+    """The 32^3 workload (20,000 lines, 50,000 points) at eps = 1e-5, in the
+    launch configuration the benchmark times: three runs of 8 cells (the
+    coldest, the hottest and one more) against the oracle row by row, and
+    the whole grid's kept-evaluation count against the oracle's."""
+    w = I.plain_32cube()
+    eps = 1e-5
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    t.set_line_tolerance(eps)
+    t.reset_tally()
+    print("adaptive 32^3 kappa", flush=True)
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    kept = t.stats()["line_evals"]
+    g = w.grid
+    runs = sorted({int(np.argmin(g.T)) // 8, int(np.argmax(g.T)) // 8, 1717})
+    cells = np.array([8 * r + k for r in runs for k in range(8)], np.int32)
+    kg = kap[cells.tolist()].cpu().numpy().astype(np.float64)[:, :w.lines.n_nu]
+    ko = O.kappa_adaptive(g, w.lines, eps, cells)
+    r = _rel(kg, ko)
+    print(f"  sampled rows: rel err max {r.max():.3e}", flush=True)
+    assert r.max() <= REL
+    print("  oracle count of kept evaluations (about 15 s)", flush=True)
+    want = O.adaptive_evals(g, w.lines, eps)
+    t.reset_tally()
+    t.compute_kappa(rt.KAPPA_PLAIN, kappa=kap)
+    plain = t.stats()["line_evals"]
+    print(f"  kept {kept:.0f} of {plain:.0f} ({kept / plain:.3f})", flush=True)
+    assert kept == want
+    t.close()
+
+
+def test_adaptive_error_paths(rt):
+    w = I.small_ragged()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    with pytest.raises(rt.RtError) as e:
+        t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    assert e.value.status == rt.RT_ESTATE
+    for bad in (0.0, -1e-3, 1.0, float("nan"), float("inf")):
+        with pytest.raises(rt.RtError) as e:
+            t.set_line_tolerance(bad)
+        assert e.value.status == rt.RT_EINVAL
+    t.close()
+    w2 = I.small_ragged_two_gases()
+    t = rt.Tracer(0)
+    t.setup_workload(w2)
+    t.set_line_tolerance(1e-4)
+    with pytest.raises(rt.RtError) as e:
+        t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    assert e.value.status == rt.RT_EUNSUPPORTED
+    t.close()
