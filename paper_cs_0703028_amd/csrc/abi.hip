@@ -56,7 +56,7 @@ void free_lineset(rt::LineSet& L) {
   dev_free(L.E2); dev_free(L.nu); dev_free(L.gamma); dev_free(L.nexp); dev_free(L.prof16);
   dev_free(L.tile16);
   dev_free(L.r64); dev_free(L.S64); dev_free(L.g64); dev_free(L.n64);
-  dev_free(L.aE); dev_free(L.eE_ref); dev_free(L.bN); dev_free(L.eN_ref);
+  dev_free(L.aE); dev_free(L.rN);
   L.n = 0;
   L.n_tiles16 = 0;
 }
@@ -314,7 +314,7 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   std::vector<int32_t> hm(nl), hwlo(nl), hwhi(nl);
   std::vector<float> hphi(nl), hS(nl), hg(nl), hn(nl);
   std::vector<double> hE2(nl), hnu(nl);
-  std::vector<double> hr64(nl), hS64(nl), hg64(nl), hn64(nl), haE(nl), heE(nl), hbN(nl), heN(nl);
+  std::vector<double> hr64(nl), hS64(nl), hg64(nl), hn64(nl), haE(nl), hrN(nl);
   std::vector<float> hprof((size_t)nl * 16);
   for (int k = 0; k < nl; ++k) {
     // the 16 tabulated points j = m - 7 .. m + 8, at distance j - r from the
@@ -340,17 +340,15 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
     hnu[k] = nu[i];
     hg[k] = (float)gamma[i];
     hn[k] = (float)n_T[i];
-    // binary64 data of the adaptive windows, with the definition's own
-    // operations: -c2 E / T is (-c2 E) / T, and the reference-state factors
-    // exp(-c2 E / T_ref) and expm1(-c2 nu / T_ref) are per-line constants
+    // binary64 data of the adaptive windows: the centre in grid units as
+    // placed above, the line constants, -c2 E and the reciprocal of the
+    // reference-state factor expm1(-c2 nu / T_ref) of Eq. (1)
     hr64[k] = q.r;
     hS64[k] = S[i];
     hg64[k] = gamma[i];
     hn64[k] = n_T[i];
     haE[k] = E ? -c2 * E[i] : 0.0;
-    heE[k] = std::exp(haE[k] / T_ref);
-    hbN[k] = -c2 * nu[i];
-    heN[k] = std::expm1(hbN[k] / T_ref);
+    hrN[k] = 1.0 / std::expm1(-c2 * nu[i] / T_ref);
   }
   RT_HIP(c, dev_alloc(&L.m, nl));
   RT_HIP(c, dev_alloc(&L.phi, nl));
@@ -363,9 +361,9 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   RT_HIP(c, dev_alloc(&L.nexp, nl));
   RT_HIP(c, dev_alloc(&L.prof16, (size_t)nl * 16));
   {
-    double** d64[8] = {&L.r64, &L.S64, &L.g64, &L.n64, &L.aE, &L.eE_ref, &L.bN, &L.eN_ref};
-    const std::vector<double>* h64[8] = {&hr64, &hS64, &hg64, &hn64, &haE, &heE, &hbN, &heN};
-    for (int k = 0; k < 8; ++k) {
+    double** d64[6] = {&L.r64, &L.S64, &L.g64, &L.n64, &L.aE, &L.rN};
+    const std::vector<double>* h64[6] = {&hr64, &hS64, &hg64, &hn64, &haE, &hrN};
+    for (int k = 0; k < 6; ++k) {
       RT_HIP(c, dev_alloc(d64[k], nl));
       if (nl > 0)
         RT_HIP(c, hipMemcpy(*d64[k], h64[k]->data(), nl * sizeof(double), hipMemcpyHostToDevice));
@@ -554,10 +552,10 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   if (mode == RT_KAPPA_ADAPTIVE) {
     const int64_t runs = (c->n_cells + RT_ADAPTIVE_GROUP - 1) / RT_ADAPTIVE_GROUP;
     const int64_t win = runs * (int64_t)std::max(c->lines.n, 1);
-    if (c->sbar_cap < c->n_cells) {  // sbar, partition ratio, screening factor per cell
+    if (c->sbar_cap < c->n_cells) {  // per cell: 3 doubles, then an 8-float record
       dev_free(c->d_sbar);
       c->sbar_cap = 0;
-      RT_HIP(c, dev_alloc(&c->d_sbar, (size_t)(3 * c->n_cells)));
+      RT_HIP(c, dev_alloc(&c->d_sbar, (size_t)(7 * c->n_cells)));
       c->sbar_cap = c->n_cells;
     }
     // room for 1/16 of the windows to be left to binary64 (about 0.3% are

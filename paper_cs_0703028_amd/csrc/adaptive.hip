@@ -39,36 +39,42 @@ static_assert(kKappaCells == RT_ADAPTIVE_GROUP, "a line-sum block holds one run 
 static_assert(kLineTile <= 256, "staged line indices are kept in bytes");
 
 constexpr int kAdThreads = 256;
+constexpr int kCellF = 8;  // floats per cell in the screening's cell record
 constexpr int kAdRec = 4 + 2 * kKappaCells;  // floats per staged line
 
-// Eq. (1) strength ratio in binary64: q exp(-c2 E / T) / exp(-c2 E / T_ref)
-// * expm1(-c2 nu / T) / expm1(-c2 nu / T_ref), the reference-state factors
-// per line, q = (T_ref / T)^1.5 per cell.
-__device__ inline double sratio64(const LineSet& L, int i, double T, double q, int have_E) {
+// Eq. (1) strength ratio in binary64: q exp(-c2 E/T) / exp(-c2 E/T_ref)
+// * expm1(-c2 nu/T) / expm1(-c2 nu/T_ref), taken as
+// q exp(c2 E (1/T_ref - 1/T)) expm1(-nu c2/T) / expm1(-c2 nu/T_ref) with the
+// per-cell beta = 1/T_ref - 1/T, theta = c2/T and q = (T_ref/T)^1.5 and the
+// per-line reciprocal of expm1(-c2 nu/T_ref): the same value in the same
+// precision, one exponential and one expm1 per (cell, line).
+__device__ inline double sratio64(const LineSet& L, int i, const CellSet& C, int64_t c, double q,
+                                  int have_E) {
 #pragma clang fp contract(off)
   if (!have_E) return 1.0;
-  const double boltz = exp(L.aE[i] / T) / L.eE_ref[i];
-  const double stim = expm1(L.bN[i] / T) / L.eN_ref[i];
-  return q * boltz * stim;
+  return q * exp(-L.aE[i] * C.beta[c]) * (expm1(-L.nu[i] * C.theta[c]) * L.rN[i]);
 }
 
 // Per cell: sbar = sum_i S_i s_ci / (n_nu dnu) (binary64, the lines in their
 // sorted order), q = (T_ref/T)^1.5 and 1/(pi eps sbar dnu), the factor that
-// turns S s g / dnu into the screening's ratio in grid units.  Block 0 also
+// turns S s g / dnu into the screening's ratio in grid units; and the
+// screening's FP32 record of the cell (kCellF floats: that factor, q,
+// 1/T_ref - 1/T, c2/T, log2(T_ref/T), p/dnu, sbar == 0).  Block 0 also
 // clears the count of undecided windows.
-__global__ __launch_bounds__(kAdThreads) void adaptive_sbar_kernel(LineSet L, const double* __restrict__ T,
+__global__ __launch_bounds__(kAdThreads) void adaptive_sbar_kernel(LineSet L, CellSet C,
+                                                                   const double* __restrict__ T,
                                                                    double T_ref, int have_E, double band,
                                                                    double pi_eps_dnu, int64_t n_cells,
                                                                    double* __restrict__ cellv,
+                                                                   float* __restrict__ cellf,
                                                                    unsigned long long* __restrict__ und) {
 #pragma clang fp contract(off)
   __shared__ double red[kAdThreads];
   const int64_t c = blockIdx.x;
   if (c == 0 && threadIdx.x == 0) *und = 0;
-  const double Tc = T[c];
-  const double q = have_E ? pow(T_ref / Tc, 1.5) : 1.0;
+  const double q = have_E ? pow(T_ref / T[c], 1.5) : 1.0;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < L.n; i += kAdThreads) acc += L.S64[i] * sratio64(L, i, Tc, q, have_E);
+  for (int i = threadIdx.x; i < L.n; i += kAdThreads) acc += L.S64[i] * sratio64(L, i, C, c, q, have_E);
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int h = kAdThreads / 2; h > 0; h >>= 1) {
@@ -77,9 +83,19 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_sbar_kernel(LineSet L, co
   }
   if (threadIdx.x == 0) {
     const double sb = red[0] / band;
+    const double inv_den = 1.0 / (pi_eps_dnu * sb);
     cellv[c] = sb;
     cellv[n_cells + c] = q;
-    cellv[2 * n_cells + c] = 1.0 / (pi_eps_dnu * sb);
+    cellv[2 * n_cells + c] = inv_den;
+    float* f = cellf + kCellF * c;
+    f[0] = (float)inv_den;
+    f[1] = (float)q;
+    f[2] = (float)C.beta[c];
+    f[3] = (float)C.theta[c];
+    f[4] = C.lam2[c];
+    f[5] = C.P[c];
+    f[6] = sb == 0.0 ? 1.f : 0.f;
+    f[7] = 0.f;
   }
 }
 
@@ -91,6 +107,7 @@ struct WindowArgs {
   const double* sbar;
   const double* q;
   const double* inv_den;  // 1/(pi eps sbar dnu) per cell
+  const float* cellf;     // the screening's FP32 cell records
   int64_t n_cells;
   int64_t n_runs;
   int have_E;
@@ -113,7 +130,7 @@ __device__ inline double window_points(const WindowArgs& a, int i, int64_t c) {
   const double sb = a.sbar[c];
   if (sb == 0.0) return (double)a.K;
   const double Tc = a.T[c];
-  const double s = sratio64(a.L, i, Tc, a.q[c], a.have_E);
+  const double s = sratio64(a.L, i, a.C, c, a.q[c], a.have_E);
   const double g = a.L.g64[i] * a.p[c] * pow(a.T_ref / Tc, a.L.n64[i]);
   const double num = a.L.S64[i] * s * g;
   const double den = M_PI * a.eps * sb;
@@ -124,43 +141,69 @@ __device__ inline double window_points(const WindowArgs& a, int i, int64_t c) {
 
 // Bounds [lo, hi] on window_points(a, i, c), in grid units, from FP32
 // arithmetic: ratio = S s gp / (pi eps sbar dnu) and gp = g / dnu, so that
-// w = sqrt(ratio - gp^2).  Relative errors: S / (1 - exp(-c2 nu/T_ref)),
-// gamma, p/dnu, q, the FP64 product S/(pi eps sbar dnu) each 6e-8 (one FP32
-// rounding); the Boltzmann factor 2.2e-7 (exp_split, |argument| < 80, result
-// normal); the stimulated-emission factor 6.5e-7 (one_minus_exp_neg_d, at
-// most 3.5 times exp_split's error where it subtracts); 2^(n log2(T_ref/T))
-// 6.2e-7 (|argument| < 4, off by 1.8e-7 relative, plus 1 ulp); four FP32
-// products 2.4e-7.  Hence ratio within 2.1e-6 and gp^2 within 1.4e-6 of
-// their exact values, and W2 = ratio - gp^2 (rounded once more) within
-// 2.2e-6 (ratio + gp^2); the bound used is 5e-6 (ratio + gp^2).  The square
-// root (1 ulp) and the scalings are covered by the factors 1 -+ 1e-6.
-// -1 stands for "no point".  Returns false outside those ranges (then
-// binary64 decides).
-__device__ inline bool window_bounds(const WindowArgs& a, int i, int64_t c, float& lo, float& hi) {
-  const double sb = a.sbar[c];
-  if (sb == 0.0) {
+// w = sqrt(ratio - gp^2).  Every FP32 input is one rounding (6e-8) from its
+// binary64 value and so is every product; v_exp_f32 is within 1 ulp (1.2e-7).
+// Relative errors (y_b = c2 E (1/T_ref - 1/T), y_s = c2 nu / T,
+// y_g = n log2(T_ref/T), each off by 1.8e-7 of itself):
+//   exp(y_b): 4.3e-7 |y_b| + 1.2e-7 (the log2(e) scaling adds 6e-8 |y_b|);
+//   1 - exp(-y_s): 5.5e-7 by its series below 1/4, else at most 3.5 times
+//     the error of exp(-y_s) there, 6.3e-7, plus the subtraction: 7e-7;
+//   2^y_g: 1.25e-7 |y_g| + 1.2e-7;
+//   t = S / (1 - exp(-c2 nu/T_ref)) / (pi eps sbar dnu), q, gamma, p/dnu and
+//   the six products: 6e-8 each.
+// So ratio is within 1.5e-6 + 4.3e-7 |y_b| + 1.25e-7 |y_g| and gp^2 within
+// 8e-7 + 2.5e-7 |y_g| of their exact values, W2 = ratio - gp^2 (one more
+// rounding) within the larger sum times (ratio + gp^2); twice that is the
+// bound used.  The square root (1 ulp) and the scalings are covered by the
+// factors 1 -+ 1e-6.  -1 stands for "no point".  Returns false outside the
+// ranges where this holds (then binary64 decides).
+struct CellF {
+  float inv_den, q, beta, theta, lam2, P;
+  bool zero;
+};
+
+__device__ inline bool window_bounds(const WindowArgs& a, int i, const CellF& cf, float& lo, float& hi) {
+  if (cf.zero) {
     lo = hi = (float)a.K;
     return true;
   }
-  const float t = (float)((double)a.L.S[i] * a.inv_den[c]);
-  if (!(t == 0.f || (t > 1e-30f && t < 1e30f))) return false;
-  float s = 1.f;
+  const float S = a.L.S[i];
+  if (!(S == 0.f || S >= 1.2e-38f)) return false;       // normal or zero
+  const float t = S * cf.inv_den;
+  if (!(t < 1e30f)) return false;
+  float s = 1.f, eb = 0.f;
   if (a.have_E) {
-    const double yb = -a.L.aE[i] * a.C.beta[c];       // -c2 E (1/T_ref - 1/T)
-    const double ys = a.L.nu[i] * a.C.theta[c];       // c2 nu / T
-    if (!(fabs(yb) < 80.0) || !(ys < 80.0)) return false;
-    s = (float)a.q[c] * exp_split(yb) * one_minus_exp_neg_d(ys);
+    const float yb = (float)a.L.E2[i] * cf.beta;        // c2 E (1/T_ref - 1/T)
+    const float ys = (float)a.L.nu[i] * cf.theta;       // c2 nu / T
+    if (!(fabsf(yb) < 80.f) || !(ys < 80.f)) return false;
+    const float boltz = fast_exp2(yb * 1.44269504f);
+    float stim;
+    if (ys < 0.25f) {
+      float p = fmaf(ys, -1.0f / 720.0f, 1.0f / 120.0f);
+      p = fmaf(ys, p, -1.0f / 24.0f);
+      p = fmaf(ys, p, 1.0f / 6.0f);
+      p = fmaf(ys, p, -0.5f);
+      p = fmaf(ys, p, 1.0f);
+      stim = ys * p;
+    } else {
+      stim = 1.0f - fast_exp2(-ys * 1.44269504f);
+    }
+    s = cf.q * boltz * stim;
+    eb = fabsf(yb);
   }
-  const float yg = a.L.nexp[i] * a.C.lam2[c];         // n log2(T_ref / T)
-  if (!(fabsf(yg) < 4.f)) return false;
-  const float gp = a.L.gamma[i] * a.C.P[c] * fast_exp2(yg);
+  const float yg = a.L.nexp[i] * cf.lam2;                // n log2(T_ref / T)
+  if (!(fabsf(yg) < 16.f)) return false;
+  const float gp = a.L.gamma[i] * cf.P * fast_exp2(yg);
   const float ratio = t * s * gp;
   const float g2 = gp * gp;
   const float W2 = ratio - g2;
-  const float err = 5e-6f * (ratio + g2);
+  const float coef = 2.f * (1.5e-6f + 4.3e-7f * eb + 2.5e-7f * fabsf(yg));
+  const float err = coef * (ratio + g2);
   if (!(ratio < 1e30f)) return false;
-  hi = W2 + err < 0.f ? -1.f : __builtin_sqrtf(W2 + err) * (1.f + 1e-6f);
-  lo = W2 - err < 0.f ? -1.f : __builtin_sqrtf(W2 - err) * (1.f - 1e-6f);
+  // v_sqrt_f32 (within 1 ulp; a flushed denormal stays >= 0, which is all
+  // the kept-point test uses of so small a half width)
+  hi = W2 + err < 0.f ? -1.f : __builtin_amdgcn_sqrtf(W2 + err) * (1.f + 1e-6f);
+  lo = W2 - err < 0.f ? -1.f : __builtin_amdgcn_sqrtf(W2 - err) * (1.f - 1e-6f);
   return true;
 }
 
@@ -220,18 +263,18 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 // largest lower and the largest upper bound of its cells; when the kept
 // points are the same at both ends they are those of the binary64 value
 // (the kept set grows with hw), else the entry is marked undecided and
-// listed for the binary64 pass.  A fixed grid walks the work items (run of
-// cells, 256 lines), so that the run -- and every cell quantity -- is the
-// same across a block; counts stay in registers and undecided indices are
-// gathered in LDS, leaving a few global atomics per block (same-address
-// atomics serialise in L2).
+// listed for the binary64 pass.  Block (x, y) takes lines 256 x .. 256 x +
+// 255 of the runs y, y + gridDim.y, ...: the run, and so every cell
+// quantity, is the same across a block.  Counts stay in registers and
+// undecided indices are gathered in LDS, leaving a few global atomics per
+// block (same-address atomics serialise in L2).
 constexpr int kUndBuf = 1024;
-__global__ __launch_bounds__(kAdThreads) void adaptive_window_kernel(WindowArgs a, int line_blocks,
-                                                                     int64_t items) {
+__global__ __launch_bounds__(kAdThreads) void adaptive_window_kernel(WindowArgs a) {
   __shared__ unsigned long long ubuf[kUndBuf];
   __shared__ unsigned ucount;
   __shared__ unsigned long long ubase;
   const int nl = a.L.n;
+  const int i = (int)blockIdx.x * kAdThreads + (int)threadIdx.x;
   if (threadIdx.x == 0) ucount = 0;
   __syncthreads();
   unsigned long long kept = 0;
@@ -248,20 +291,35 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_window_kernel(WindowArgs 
     }
     __syncthreads();
   };
-  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const int64_t run = item / line_blocks;
-    const int i = (int)(item - run * line_blocks) * kAdThreads + (int)threadIdx.x;
+  for (int64_t run = blockIdx.y; run < a.n_runs; run += gridDim.y) {
     const int64_t c0 = run * RT_ADAPTIVE_GROUP;
     const int members = (int)min<int64_t>(RT_ADAPTIVE_GROUP, a.n_cells - c0);
+    CellF cf[RT_ADAPTIVE_GROUP];
+#pragma unroll
+    for (int k = 0; k < RT_ADAPTIVE_GROUP; ++k) {
+      const int64_t c = c0 + (k < members ? k : 0);
+      const float4* f = reinterpret_cast<const float4*>(a.cellf + kCellF * c);
+      const float4 f0 = f[0], f1 = f[1];
+      cf[k].inv_den = f0.x;
+      cf[k].q = f0.y;
+      cf[k].beta = f0.z;
+      cf[k].theta = f0.w;
+      cf[k].lam2 = f1.x;
+      cf[k].P = f1.y;
+      cf[k].zero = f1.z != 0.f;
+    }
     if (i < nl) {
       const int64_t idx = run * nl + i;
       float wl = -1.f, wu = -1.f;
       bool ok = true;
-      for (int k = 0; k < members && ok; ++k) {
-        float l, h;
-        ok = window_bounds(a, i, c0 + k, l, h);
-        wl = fmaxf(wl, l);
-        wu = fmaxf(wu, h);
+#pragma unroll
+      for (int k = 0; k < RT_ADAPTIVE_GROUP; ++k) {
+        if (k < members) {
+          float l = -1.f, h = -1.f;
+          ok = window_bounds(a, i, cf[k], l, h) && ok;
+          wl = fmaxf(wl, l);
+          wu = fmaxf(wu, h);
+        }
       }
       const double K = (double)a.K;
       const double r = a.L.r64[i];
@@ -460,10 +518,11 @@ hipError_t launch_kappa_adaptive(rt_ctx c) {
   if (blocks > 0x7fffffffLL || wblocks > 0x7fffffffLL || sblocks > 0x7fffffffLL ||
       c->n_cells > 0x7fffffffLL)
     return hipErrorInvalidValue;
-  double* cellv = c->d_sbar;  // [3][cells]: sbar, q, 1/(pi eps sbar dnu)
+  double* cellv = c->d_sbar;  // [3][cells]: sbar, q, 1/(pi eps sbar dnu); then the FP32 records
+  float* cellf = reinterpret_cast<float*>(c->d_sbar + 3 * c->n_cells);
   hipLaunchKernelGGL(adaptive_sbar_kernel, dim3((unsigned)c->n_cells), dim3(kAdThreads), 0, c->stream,
-                     L, c->d_T, c->T_ref, c->have_E ? 1 : 0, (double)c->n_nu * c->dnu,
-                     M_PI * c->line_tol * c->dnu, c->n_cells, cellv, c->d_und);
+                     L, c->cells, c->d_T, c->T_ref, c->have_E ? 1 : 0, (double)c->n_nu * c->dnu,
+                     M_PI * c->line_tol * c->dnu, c->n_cells, cellv, cellf, c->d_und);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (pairs > 0) {
@@ -475,6 +534,7 @@ hipError_t launch_kappa_adaptive(rt_ctx c) {
     w.sbar = cellv;
     w.q = cellv + c->n_cells;
     w.inv_den = cellv + 2 * c->n_cells;
+    w.cellf = cellf;
     w.n_cells = c->n_cells;
     w.n_runs = runs;
     w.have_E = c->have_E ? 1 : 0;
@@ -487,9 +547,9 @@ hipError_t launch_kappa_adaptive(rt_ctx c) {
     w.kept = c->d_adapt_evals;
     w.und = c->d_und;
     w.und_cap = c->und_cap;
-    const int64_t sgrid = std::min<int64_t>(sblocks, 4096);
-    hipLaunchKernelGGL(adaptive_window_kernel, dim3((unsigned)sgrid), dim3(kAdThreads), 0, c->stream, w,
-                       line_blocks, sblocks);
+    const int64_t gy = std::min<int64_t>(runs, std::max<int64_t>(1, 4096 / line_blocks));
+    hipLaunchKernelGGL(adaptive_window_kernel, dim3((unsigned)line_blocks, (unsigned)gy), dim3(kAdThreads),
+                       0, c->stream, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t lblocks = std::min<int64_t>((c->und_cap + kAdThreads - 1) / kAdThreads, 4096);

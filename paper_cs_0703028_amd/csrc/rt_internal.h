@@ -50,17 +50,14 @@ struct LineSet {
   // sorted list, int2 per tile (t = 0 .. n_tiles16 - 1)
   int2* tile16 = nullptr;
   int n_tiles16 = 0;
-  // binary64 line data for the adaptive windows, decided in binary64 with
-  // the same operations as the definition: r = (nu - nu0)/dnu, S_ref,
-  // gamma_ref, n_T, a = -c2 E, exp(a / T_ref), b = -c2 nu, expm1(b / T_ref)
+  // binary64 line data for the adaptive windows: r = (nu - nu0)/dnu,
+  // S_ref, gamma_ref, n_T, a = -c2 E and 1/expm1(-c2 nu / T_ref)
   double* r64 = nullptr;
   double* S64 = nullptr;
   double* g64 = nullptr;
   double* n64 = nullptr;
   double* aE = nullptr;
-  double* eE_ref = nullptr;
-  double* bN = nullptr;
-  double* eN_ref = nullptr;
+  double* rN = nullptr;
 };
 
 // Per-cell derived parameters (device), from FP64 on the device.
@@ -132,7 +129,8 @@ struct rt_ctx_s {
   rt::ExtraGas gas[rt::kMaxGases - 1];
 
   // adaptive line windows (RT_KAPPA_ADAPTIVE): tolerance (0 = not set),
-  // per-cell sbar, partition ratio and screening factor (FP64, [3][cells]),
+  // per-cell sbar, partition ratio and screening factor (FP64, [3][cells])
+  // followed by the screening's FP32 cell records (8 floats per cell),
   // window table
   // [run of cells][line] (owned) and the device count of kept evaluations
   // since the last reset
