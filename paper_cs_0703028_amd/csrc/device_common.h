@@ -104,6 +104,10 @@ struct KappaTile {
   const int32_t* cell_list = nullptr;  // logical cell i -> cell_list[i] when set
   int compact_rows = 0;                // with a list: write row i instead of cell_list[i]
   int accumulate = 0;                  // add to the row instead of storing (a further gas)
+  // the block sums part line_part of line_parts equal shares of the lines
+  // its points need (its output is then a partial sum of the row)
+  int line_parts = 1;
+  int line_part = 0;
 };
 
 // Optional device-side gating of a launch of line-sum tiles, decided per
@@ -130,8 +134,13 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
   const int wj0 = j0 + wave * span;
 
   const int nl = a.L.n;
-  const int blk_first = first_ge(a.L.whi, nl, j0);
-  const int blk_end = first_gt(a.L.wlo, nl, j0 + kKappaTilePoints - 1);
+  int blk_first = first_ge(a.L.whi, nl, j0);
+  int blk_end = first_gt(a.L.wlo, nl, j0 + kKappaTilePoints - 1);
+  if (a.line_parts > 1) {
+    const int share = (blk_end - blk_first + a.line_parts - 1) / a.line_parts;
+    blk_first = min(blk_end, blk_first + a.line_part * share);
+    blk_end = min(blk_end, blk_first + share);
+  }
   const int w_first = first_ge(a.L.whi, nl, wj0);
   const int w_end = first_gt(a.L.wlo, nl, wj0 + span - 1);
 

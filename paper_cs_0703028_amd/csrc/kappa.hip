@@ -53,13 +53,17 @@ struct KappaArgs {
   int n_tiles;
   int tile_begin;
   TileGate gate;
+  int parts = 1;             // line shares per tile, each into its own output
+  int64_t part_stride = 0;   // floats between the shares' outputs
 };
 
 template <bool COMP>
 __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs a) {
   __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
-  const int tile = blockIdx.x % a.n_tiles;
-  const int64_t cg = blockIdx.x / a.n_tiles;
+  const int part = (int)(blockIdx.x % (unsigned)a.parts);
+  const int64_t tb = blockIdx.x / (unsigned)a.parts;
+  const int tile = (int)(tb % a.n_tiles);
+  const int64_t cg = tb / a.n_tiles;
   const int j0 = (a.tile_begin + tile) * kKappaTilePoints;
   if (a.gate.group_flag || a.gate.chunk_err) {
     bool need = a.gate.group_flag && a.gate.group_flag[cg] == a.gate.epoch;
@@ -69,6 +73,14 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs 
       for (int k = c0; k <= c1; ++k) need = need || a.gate.chunk_err[k] > a.gate.tol;
     }
     if (!need) return;
+  }
+  if (a.parts > 1) {
+    KappaTile t = a.t;
+    t.line_parts = a.parts;
+    t.line_part = part;
+    t.out += part * a.part_stride;
+    kappa_tile<COMP>(t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
+    return;
   }
   kappa_tile<COMP>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
 }
@@ -277,13 +289,15 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
 
 hipError_t launch_kappa_tiles(rt_ctx c, const KappaTile& t, int64_t n_cell_groups,
                               int tile_begin, int n_tiles, bool comp, hipStream_t s,
-                              const TileGate& gate) {
+                              const TileGate& gate, int parts, int64_t part_stride) {
   KappaArgs a;
   a.t = t;
   a.gate = gate;
   a.n_tiles = n_tiles;
   a.tile_begin = tile_begin;
-  const int64_t blocks = n_cell_groups * n_tiles;
+  a.parts = parts < 1 ? 1 : parts;
+  a.part_stride = part_stride;
+  const int64_t blocks = n_cell_groups * n_tiles * a.parts;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   if (blocks == 0) return hipSuccess;
   if (comp)

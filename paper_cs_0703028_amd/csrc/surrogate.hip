@@ -32,7 +32,8 @@ namespace rt {
 
 hipError_t launch_kappa_tiles(rt_ctx c, const dev::KappaTile& t, int64_t n_cell_groups,
                               int tile_begin, int n_tiles, bool comp, hipStream_t s,
-                              const dev::TileGate& gate = dev::TileGate());
+                              const dev::TileGate& gate = dev::TileGate(), int parts = 1,
+                              int64_t part_stride = 0);
 hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const double* x,
                                  const double* p, const CellSet& cells, hipStream_t s);
 
@@ -597,6 +598,18 @@ __global__ void normalize_kernel(float* Y, int64_t n_samples, int64_t ld_s, int 
 // cell edge l -- the quantity the absorbed and emitted power are linear in
 // for thin points and saturate in for thick ones.  Cells outside the
 // training box (recomputed exactly anyway) are left out.
+// The check's exact rows arrive as `parts` partial sums over shares of the
+// lines (parts blocks per line-sum tile keep the GPU busy on a few sampled
+// cells); they are added into the first share, in share order.
+__global__ __launch_bounds__(256) void sum_parts_kernel(float* __restrict__ x, int64_t n, int parts,
+                                                        int64_t stride) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float v = x[i];
+  for (int q = 1; q < parts; ++q) v += x[q * stride + i];
+  x[i] = v;
+}
+
 __global__ __launch_bounds__(256) void check_kernel(const float* __restrict__ kappa, int64_t ld,
                                                     const float* __restrict__ exact, int64_t ld_e,
                                                     const int32_t* __restrict__ cells, int n_check,
@@ -907,6 +920,21 @@ bool surrogate_ready(rt_ctx c) {
 //   3. the checked error per chunk (marked cells left out);
 //   4. the line sum over every tile that touches a chunk over tolerance or a
 //      marked group of cells.
+// Line shares per tile of the check's line sum: enough blocks (about 2,048)
+// that a few sampled cells do not leave most of the GPU idle, but no share
+// under about 128 lines (a tile's window meets n (512 + 2K) / n_nu lines on
+// average), and at most 32.
+int check_parts(rt_ctx c, int n_check) {
+  const int64_t tiles = (c->ld + dev::kKappaTilePoints - 1) / dev::kKappaTilePoints;
+  const int64_t blocks = (int64_t)((n_check + dev::kKappaCells - 1) / dev::kKappaCells) * tiles;
+  if (blocks <= 0) return 1;
+  const double per_tile = (double)c->lines.n * (dev::kKappaTilePoints + 2.0 * c->K) /
+                          std::max(1, c->n_nu);
+  const int64_t by_lines = (int64_t)(per_tile / 128.0);
+  const int64_t by_blocks = (2048 + blocks - 1) / blocks;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(32, std::min(by_lines, by_blocks)));
+}
+
 // The counts and timings are read back lazily by rt_surrogate_get_stats.
 // Called by rt_compute_kappa in surrogate mode.
 rt_status surrogate_kappa(rt_ctx c) {
@@ -925,7 +953,7 @@ rt_status surrogate_kappa(rt_ctx c) {
     dfree(S.d_exact);
     ok = chk(dalloc(&S.d_cell_flag, n_cells)) && chk(dalloc(&S.d_group_flag, groups_all)) &&
          chk(dalloc(&S.d_err, S.n_chunks)) && chk(dalloc(&S.d_check, std::max(1, n_check))) &&
-         chk(dalloc(&S.d_exact, std::max<int64_t>(1, (int64_t)n_check * c->ld)));
+         chk(dalloc(&S.d_exact, std::max<int64_t>(1, (int64_t)check_parts(c, n_check) * n_check * c->ld)));
     // marks start at 0, which no call uses as its epoch
     ok = ok && chk(hipMemsetAsync(S.d_cell_flag, 0, n_cells * 4, s)) &&
          chk(hipMemsetAsync(S.d_group_flag, 0, groups_all * 4, s));
@@ -983,8 +1011,13 @@ rt_status surrogate_kappa(rt_ctx c) {
     te.n_cells = n_check;
     te.out = S.d_exact;
     te.compact_rows = 1;
+    const int parts = check_parts(c, n_check);
+    const int64_t part_stride = (int64_t)n_check * c->ld;
     ok = chk(launch_kappa_tiles(c, te, (n_check + dev::kKappaCells - 1) / dev::kKappaCells, 0,
-                                tiles_all, false, s));
+                                tiles_all, false, s, dev::TileGate(), parts, part_stride));
+    if (ok && parts > 1)
+      hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)grid1(part_stride)), dim3(256), 0, s,
+                         S.d_exact, part_stride, parts, part_stride);
     if (ok)
       hipLaunchKernelGGL(check_kernel, dim3(S.n_chunks), dim3(256), 0, s, c->kappa, c->ld,
                          S.d_exact, c->ld, S.d_check, n_check, c->n_nu,
