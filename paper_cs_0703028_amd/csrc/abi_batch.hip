@@ -316,7 +316,7 @@ std::string shape_key(rt_ctx c, int n_cases, const rt_case* cases) {
     rays += (double)cases[k].n_rays;
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "v4|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
+  std::snprintf(buf, sizeof(buf), "v5|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
                 arch_name(c).c_str(), n_cases, (int)std::lround(std::log2(cells)),
                 (int)std::lround(std::log2(rays)), c->n_nu,
                 (int)std::lround(std::log2((double)std::max(1, c->lines.n))));
@@ -487,10 +487,10 @@ rt_status rt_batch_autotune(rt_ctx c, int n_cases, const rt_case* cases, int kap
   const int chunks[] = {kChunk, 2 * kChunk, 4 * kChunk};
   const int groups[] = {16, 32, 64, 128};
   const int rays[] = {16, 64, 256};
-  const int bpc[] = {2, 4, 8};
+  const int bpc[] = {2, 4, 5, 8};
   const int slots[] = {2, 4, 8};
   const int* values[5] = {chunks, groups, rays, bpc, slots};
-  const int n_values[5] = {3, 4, 3, 3, 3};
+  const int n_values[5] = {3, 4, 3, 4, 3};
   for (int pass = 0; pass < 3; ++pass) {
     bool improved = false;
     for (int param = 0; param < 5; ++param) {

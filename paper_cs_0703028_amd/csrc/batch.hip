@@ -81,7 +81,13 @@ __device__ __forceinline__ bool wait_count(const unsigned* p, unsigned target, u
 }
 
 template <bool QUAD>
-__global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
+// Five wavefronts per SIMD (at most 102 VGPRs): the march items wait on memory
+// and need the wavefronts to hide it.  Left alone the combined code paths take
+// 142 VGPRs and three wavefronts; at five, 33 VGPRs go to scratch, a few
+// accesses per march segment, which costs less than the two wavefronts gain
+// (measured: 4.57 s at three, 4.33 s at four, 4.26 s at five for the 64-case
+// launch; six spills 62 and is not used).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_kernel(BatchArgs a) {
   __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
   __shared__ long long s_item;
   __shared__ int s_ok;
