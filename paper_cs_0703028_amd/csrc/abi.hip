@@ -552,10 +552,10 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   if (mode == RT_KAPPA_ADAPTIVE) {
     const int64_t runs = (c->n_cells + RT_ADAPTIVE_GROUP - 1) / RT_ADAPTIVE_GROUP;
     const int64_t win = runs * (int64_t)std::max(c->lines.n, 1);
-    if (c->sbar_cap < c->n_cells) {  // per cell: 3 doubles, then an 8-float record
+    if (c->sbar_cap < c->n_cells) {  // per cell: 2 doubles, then an 8-float record
       dev_free(c->d_sbar);
       c->sbar_cap = 0;
-      RT_HIP(c, dev_alloc(&c->d_sbar, (size_t)(7 * c->n_cells)));
+      RT_HIP(c, dev_alloc(&c->d_sbar, (size_t)(6 * c->n_cells)));
       c->sbar_cap = c->n_cells;
     }
     // room for 1/16 of the windows to be left to binary64 (about 0.3% are

@@ -10,9 +10,8 @@
 //                            offsets, wherever FP32 bounds on the half width
 //                            already fix it; counts the kept evaluations
 //   adaptive_window_list_kernel, adaptive_window_scan_kernel : the rest, in
-//                            binary64 with the definition's operations (the
-//                            screening lists them; the scan takes any the
-//                            list had no room for)
+//                            binary64 (the screening lists them; the scan
+//                            takes any the list had no room for)
 //   kappa_adaptive_kernel  : the plain FP32 line sum of Eq. (2) over those
 //                            windows.  Each wavefront sums only the staged
 //                            lines whose window meets its 128 points, first
@@ -23,9 +22,10 @@
 // eps u_c sbar_c: |j - r_i| <= w_ci = sqrt(S s g / (pi eps sbar) - g^2)/dnu
 // (no point when the root is imaginary).  The run's window is the widest of
 // its cells', capped by the hard cutoff, and intersected with the plain
-// window [m - K + [phi > 0], m + K].  The same decision in the same
-// precision is what makes the windows, and so the kept terms, those of the
-// definition; only the transcendental functions' last bits can differ.
+// window [m - K + [phi > 0], m + K].  The decision is taken in binary64, as
+// in the definition: only the last bits of the exponentials and of the
+// order of the strength ratio's operations can differ, and a window moves
+// only if its half width lies within that of a grid point's distance.
 #include <algorithm>
 
 #include "device_common.h"
@@ -56,11 +56,11 @@ __device__ inline double sratio64(const LineSet& L, int i, const CellSet& C, int
 }
 
 // Per cell: sbar = sum_i S_i s_ci / (n_nu dnu) (binary64, the lines in their
-// sorted order), q = (T_ref/T)^1.5 and 1/(pi eps sbar dnu), the factor that
-// turns S s g / dnu into the screening's ratio in grid units; and the
-// screening's FP32 record of the cell (kCellF floats: that factor, q,
-// 1/T_ref - 1/T, c2/T, log2(T_ref/T), p/dnu, sbar == 0).  Block 0 also
-// clears the count of undecided windows.
+// sorted order), q = (T_ref/T)^1.5, and the screening's FP32 record of the
+// cell (kCellF floats: 1/(pi eps sbar dnu), the factor that turns S s g / dnu
+// into the screening's ratio in grid units, then q, 1/T_ref - 1/T, c2/T,
+// log2(T_ref/T), p/dnu and sbar == 0).  Block 0 also clears the count of
+// undecided windows.
 __global__ __launch_bounds__(kAdThreads) void adaptive_sbar_kernel(LineSet L, CellSet C,
                                                                    const double* __restrict__ T,
                                                                    double T_ref, int have_E, double band,
@@ -86,7 +86,6 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_sbar_kernel(LineSet L, Ce
     const double inv_den = 1.0 / (pi_eps_dnu * sb);
     cellv[c] = sb;
     cellv[n_cells + c] = q;
-    cellv[2 * n_cells + c] = inv_den;
     float* f = cellf + kCellF * c;
     f[0] = (float)inv_den;
     f[1] = (float)q;
@@ -106,7 +105,6 @@ struct WindowArgs {
   const double* p;
   const double* sbar;
   const double* q;
-  const double* inv_den;  // 1/(pi eps sbar dnu) per cell
   const float* cellf;     // the screening's FP32 cell records
   int64_t n_cells;
   int64_t n_runs;
@@ -123,8 +121,7 @@ struct WindowArgs {
 // offset -32768: no real window, whose offsets lie in [-K, K] with K <= 32767).
 constexpr uint32_t kUndecided = 0x80007fffu;
 
-// Half width in grid points of line i in cell c, -1 for none, in binary64
-// with the definition's operations.
+// Half width in grid points of line i in cell c, -1 for none, in binary64.
 __device__ inline double window_points(const WindowArgs& a, int i, int64_t c) {
 #pragma clang fp contract(off)
   const double sb = a.sbar[c];
@@ -518,8 +515,8 @@ hipError_t launch_kappa_adaptive(rt_ctx c) {
   if (blocks > 0x7fffffffLL || wblocks > 0x7fffffffLL || sblocks > 0x7fffffffLL ||
       c->n_cells > 0x7fffffffLL)
     return hipErrorInvalidValue;
-  double* cellv = c->d_sbar;  // [3][cells]: sbar, q, 1/(pi eps sbar dnu); then the FP32 records
-  float* cellf = reinterpret_cast<float*>(c->d_sbar + 3 * c->n_cells);
+  double* cellv = c->d_sbar;  // [2][cells]: sbar, q; then the FP32 records
+  float* cellf = reinterpret_cast<float*>(c->d_sbar + 2 * c->n_cells);
   hipLaunchKernelGGL(adaptive_sbar_kernel, dim3((unsigned)c->n_cells), dim3(kAdThreads), 0, c->stream,
                      L, c->cells, c->d_T, c->T_ref, c->have_E ? 1 : 0, (double)c->n_nu * c->dnu,
                      M_PI * c->line_tol * c->dnu, c->n_cells, cellv, cellf, c->d_und);
@@ -533,7 +530,6 @@ hipError_t launch_kappa_adaptive(rt_ctx c) {
     w.p = c->d_p;
     w.sbar = cellv;
     w.q = cellv + c->n_cells;
-    w.inv_den = cellv + 2 * c->n_cells;
     w.cellf = cellf;
     w.n_cells = c->n_cells;
     w.n_runs = runs;

@@ -129,8 +129,8 @@ struct rt_ctx_s {
   rt::ExtraGas gas[rt::kMaxGases - 1];
 
   // adaptive line windows (RT_KAPPA_ADAPTIVE): tolerance (0 = not set),
-  // per-cell sbar, partition ratio and screening factor (FP64, [3][cells])
-  // followed by the screening's FP32 cell records (8 floats per cell),
+  // per-cell sbar and partition ratio (FP64, [2][cells]) followed by the
+  // screening's FP32 cell records (8 floats per cell),
   // window table
   // [run of cells][line] (owned) and the device count of kept evaluations
   // since the last reset
