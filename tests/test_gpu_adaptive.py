@@ -154,3 +154,42 @@ def test_adaptive_error_paths(rt):
         t.compute_kappa(rt.KAPPA_ADAPTIVE)
     assert e.value.status == rt.RT_EUNSUPPORTED
     t.close()
+
+
+def test_adaptive_without_energies_and_zero_strengths(rt, O):
+    """The branches a line list without lower-state energies takes (strength
+    ratio 1), lines of zero strength (no point kept anywhere), and a list of
+    zero strengths only (sbar = 0: the plain window, and kappa 0)."""
+    w = I.small_ragged()
+    L = replace(w.lines, E_lower=None)
+    S = L.S.copy()
+    S[::7] = 0.0
+    L = replace(L, S=S)
+    for eps in (3e-4, 1e-6):
+        t = rt.Tracer(0)
+        t.setup_grid(w.grid)
+        t.setup_lines(L)
+        t.set_line_tolerance(eps)
+        t.reset_tally()
+        kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE)
+        kept = t.stats()["line_evals"]
+        r = _rel(kap.cpu().numpy().astype(np.float64)[:, :L.n_nu], O.kappa_adaptive(w.grid, L, eps))
+        want = O.adaptive_evals(w.grid, L, eps)
+        print(f"no energies, eps {eps:g}: rel err max {r.max():.3e}; kept {kept:.0f} (oracle {want})",
+              flush=True)
+        assert r.max() <= REL
+        assert kept == want
+        t.close()
+    Z = replace(L, S=np.zeros_like(L.S))
+    t = rt.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(Z)
+    t.set_line_tolerance(1e-3)
+    t.reset_tally()
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    kept = t.stats()["line_evals"]
+    assert (kap.cpu().numpy() == 0).all()
+    t.reset_tally()
+    t.compute_kappa(rt.KAPPA_PLAIN)
+    assert kept == t.stats()["line_evals"] == O.adaptive_evals(w.grid, Z, 1e-3)
+    t.close()

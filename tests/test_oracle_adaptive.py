@@ -181,3 +181,22 @@ def test_brute_force_value_criterion_counts_and_sums():
     got = O.adaptive_evals(g, L, eps)
     assert abs(got - total) <= ambiguous
     assert 0 < total < sum(int(p[1].sum()) for p in per)
+
+
+def test_zero_strengths_keep_the_plain_window():
+    # sbar = 0: no reference level, the hard window is kept (and every term is 0)
+    w = I.small_ragged()
+    Z = replace(w.lines, S=np.zeros_like(w.lines.S))
+    assert O.mean_strength(900.0, Z) == 0.0
+    assert O.adaptive_evals(w.grid, Z, 1e-3) == int(_hard_count(Z).sum()) * w.grid.n_cells
+    assert not O.kappa_adaptive(w.grid, Z, 1e-3, [0, 100]).any()
+    # a zero-strength line among others keeps no point
+    L = w.lines
+    one = replace(L, nu=L.nu[:1], S=np.zeros(1), gamma=L.gamma[:1], n_T=L.n_T[:1],
+                  E_lower=L.E_lower[:1])
+    both = replace(L, nu=L.nu[:2], S=np.array([0.0, L.S[1]]), gamma=L.gamma[:2], n_T=L.n_T[:2],
+                   E_lower=L.E_lower[:2])
+    second = replace(L, nu=L.nu[1:2], S=L.S[1:2], gamma=L.gamma[1:2], n_T=L.n_T[1:2],
+                     E_lower=L.E_lower[1:2])
+    assert O.adaptive_evals(w.grid, both, 0.05) == O.adaptive_evals(w.grid, second, 0.05)
+    assert O.adaptive_evals(w.grid, one, 0.05) == int(_hard_count(one).sum()) * w.grid.n_cells
