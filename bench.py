@@ -76,40 +76,69 @@ def line_peak_evals_per_s():
     return LANE_SLOTS_PER_S / LINE_SLOTS_PER_EVAL
 
 
-def cpu_baseline(w, n_cells_sample=32, n_rays_sample=96):
+def cpu_baseline(w, n_cells_sample=32, n_rays_sample=96, n_cells_one=4):
     """Time the FP64 oracle on a bounded sample of the same workload and
-    extrapolate linearly to the full step."""
+    extrapolate linearly to the full step, on all host threads and on one.
+    All threads: kappa and Planck rows of sampled cells (OpenMP over cells)
+    and the march of one slice of rays per thread (the oracle's march called
+    from a thread pool on disjoint rays; ctypes releases the interpreter
+    lock).  One thread: fewer rows, and one slice of rays."""
+    import concurrent.futures as cf
+
     import numpy as np
 
     from oracle import oracle as O
 
     g, L = w.grid, w.lines
+    threads = O.num_threads()
     rng = np.random.default_rng(0)
     cells = np.sort(rng.choice(g.n_cells, n_cells_sample, replace=False)).astype(np.int32)
     t0 = time.perf_counter()
     kap = O.kappa(g, L, cells)
     B = O.planck_rows(g, L, cells)
     t_kappa = time.perf_counter() - t0
-    Os, Ds, _ = O.rays(w.seed, 0, n_rays_sample, g.nx, g.ny, g.nz)
+    O.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.kappa(g, L, cells[:n_cells_one])
+        O.planck_rows(g, L, cells[:n_cells_one])
+        t_kappa_one = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(threads)
     # the march's cost does not depend on the values: every visited cell
     # reads one of the sampled rows
     row = (np.arange(g.n_cells) % n_cells_sample).astype(np.int32)
+    wgt = O.ray_weight(g, L, w.n_rays)
+    slices = [O.rays(w.seed, k * n_rays_sample, n_rays_sample, g.nx, g.ny, g.nz)[:2]
+              for k in range(threads)]
     segs = 0
-    for k in range(n_rays_sample):
-        segs += len(O.segments(g.nx, g.ny, g.nz, g.cell_m * 100.0, Os[k], Ds[k])[0])
+    for Os, Ds in slices:
+        for k in range(n_rays_sample):
+            segs += len(O.segments(g.nx, g.ny, g.nz, g.cell_m * 100.0, Os[k], Ds[k])[0])
+    seg_per_ray = segs / (threads * n_rays_sample)
     t0 = time.perf_counter()
-    O.march(g, L, Os, Ds, O.ray_weight(g, L, w.n_rays), kap, B, cell_row=row)
+    O.march(g, L, slices[0][0], slices[0][1], wgt, kap, B, cell_row=row)
+    t_march_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda sl: O.march(g, L, sl[0], sl[1], wgt, kap, B, cell_row=row), slices))
     t_march = time.perf_counter() - t0
-    total_s = t_kappa * g.n_cells / n_cells_sample + t_march * w.n_rays / n_rays_sample
-    updates_total = segs / n_rays_sample * w.n_rays * L.n_nu
+    updates_total = seg_per_ray * w.n_rays * L.n_nu
+    total_s = (t_kappa * g.n_cells / n_cells_sample
+               + t_march * w.n_rays / (threads * n_rays_sample))
+    total_one = (t_kappa_one * g.n_cells / n_cells_one
+                 + t_march_one * w.n_rays / n_rays_sample)
     return {
         "value": updates_total / total_s,
         "unit": "ray·cell·nu updates/s",
-        "cores": O.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"FP64 oracle: kappa+Planck rows of {n_cells_sample} cells x {L.n_nu} nu "
-                   f"({t_kappa:.2f} s, OpenMP over cells) and the march of rays 0..{n_rays_sample-1} "
-                   f"x {L.n_nu} nu ({t_march:.2f} s, one thread), extrapolated linearly to "
+        "value_1core": updates_total / total_one,
+        "sample": (f"FP64 oracle on {threads} threads: kappa+Planck rows of {n_cells_sample} cells "
+                   f"x {L.n_nu} nu ({t_kappa:.2f} s, OpenMP over cells) and the march of "
+                   f"{threads} x {n_rays_sample} rays x {L.n_nu} nu ({t_march:.2f} s, one slice of "
+                   f"rays per thread); on one thread: {n_cells_one} rows ({t_kappa_one:.2f} s) and "
+                   f"{n_rays_sample} rays ({t_march_one:.2f} s); both extrapolated linearly to "
                    f"{g.n_cells} cells and {w.n_rays} rays"),
     }
 

@@ -89,6 +89,8 @@ def lib():
                                 C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
                                 _f64p, _f64p, C.c_void_p, _f64p, _f64p, _f64p, C.c_void_p]
         L.orc_march.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         L.orc_boundary_area.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double]
         L.orc_boundary_area.restype = C.c_double
         for name in ("orc_const_c1", "orc_const_c2"):
@@ -100,6 +102,11 @@ def lib():
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the OpenMP loops over cells (a timing control only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def c1() -> float:

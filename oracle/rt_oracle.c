@@ -64,6 +64,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* threads of the OpenMP loops over cells (timing on one core or all) */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ======================================================================
  * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC'11), written from its published definition: ten
