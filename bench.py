@@ -292,6 +292,14 @@ def form_batched(rtlbl, I):
         "line_evals": st["batch_line_evals"],
         "updates_per_s": st["batch_updates"] / dt,
         "line_evals_per_s": st["batch_line_evals"] / dt,
+        # the line sum and the march share the launch: each phase's rate over
+        # its own VALU ceiling, and their sum (the share of the launch's VALU
+        # capacity the algorithmic work fills)
+        "frac_of_valu_ceiling": {
+            "line_sum": st["batch_line_evals"] / dt / line_peak_evals_per_s(),
+            "march": st["batch_updates"] / dt / march_peak_updates_per_s(),
+            "both": (st["batch_line_evals"] / dt / line_peak_evals_per_s()
+                     + st["batch_updates"] / dt / march_peak_updates_per_s())},
         "tuning": best.as_dict(),
         "tuning_s": tune_s,
         "energy_balance_residual_max": float(np.max(
