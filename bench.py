@@ -616,6 +616,7 @@ def main():
     del kap
     torch.cuda.empty_cache()
     peak = march_peak_updates_per_s()
+    traffic = measured_traffic()
     march_rate = updates / (march_ms * 1e-3)
     line_rate = evals / (kappa_ms * 1e-3)
     rec = {
@@ -649,8 +650,12 @@ def main():
             "peak": peak * MARCH_FLOPS_PER_UPDATE / 1e12,
             "unit": "TFLOP/s",
             "frac": march_rate / peak,
-            "traffic": measured_traffic(),
+            "traffic": traffic,
             "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+            # those bytes over the launch time: the rate past L2 (Infinity
+            # Cache and HBM), against 8 TB/s of HBM
+            "traffic_gbs": (traffic / (march_ms / launches * 1e-3) / 1e9
+                            if traffic and launches else None),
             "launches": launches,
             "avg_launch_ms": march_ms / launches if launches else None,
         },
