@@ -831,7 +831,7 @@ Surrogate& surrogate(rt_ctx c) {
   return *c->surrogate;
 }
 
-uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ULL) {
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 14695981039346656037ULL) {
   const unsigned char* b = static_cast<const unsigned char*>(p);
   for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ULL; }
   return h;

@@ -137,3 +137,59 @@ def test_save_load_roundtrip(rt, trained, tmp_path):
     with pytest.raises(rt.RtError):
         u.surrogate_load(path)
     u.close()
+
+
+def _fnv1a64(data: bytes) -> int:
+    h = 0xCBF29CE484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_corrupted_model_trips_the_check_and_falls_back(rt, trained, tmp_path):
+    """A saved model whose output normalisation is shifted on two chunks
+    (kappa there e^10 times too small, so that their absorptance nearly
+    vanishes: a kappa too large would hide in optically thick chunks, which
+    the absorptance-weighted check rightly lets pass): the sampled check must
+    trip on exactly those chunks and the fallback must give them the line
+    sum's kappa bit for bit."""
+    import struct
+    t, w = trained
+    path = str(tmp_path / "mlp.bin")
+    t.surrogate_save(path)
+    blob = bytearray(open(path, "rb").read())
+    d = rt.Tracer.MLP_DIMS
+    head = 8 + 16 + 56 + 8                       # tag, header, box and tolerance, seed
+    n_chunks = struct.unpack_from("<i", blob, 16)[0]
+    mean_off = head + 4 * sum(d[i] * d[i + 1] + d[i + 1] for i in range(4))
+    mean = np.frombuffer(bytes(blob[mean_off:mean_off + 4 * 256 * n_chunks]), np.float32).copy()
+    bad = [3, 17]
+    for k in bad:
+        mean[256 * k:256 * (k + 1)] -= 10.0      # ln kappa - 10
+    blob[mean_off:mean_off + mean.nbytes] = mean.tobytes()
+    # check tolerance 0.5 (the box's seventh double): between the clean
+    # chunks' error and the corrupted ones', so that exactly those fall back
+    struct.pack_into("<d", blob, 8 + 16 + 6 * 8, 0.5)
+    blob[-8:] = struct.pack("<Q", _fnv1a64(bytes(blob[:-8])))
+    open(path, "wb").write(bytes(blob))
+    u = rt.Tracer(0)
+    u.setup_grid(w.grid)
+    u.setup_lines(w.lines)
+    u.surrogate_load(path)
+    kap, _ = u.alloc_tables()
+    u.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
+    st = u.surrogate_stats()
+    k1 = kap.cpu().numpy()
+    u.compute_kappa(rt.KAPPA_PLAIN, kap, None)
+    k0 = kap.cpu().numpy()
+    u.close()
+    print(f"corrupted chunks {bad}: fallback {st['fallback_chunks']} of {st['n_chunks']}, "
+          f"check error max {st['check_error']:.3e}", flush=True)
+    assert st["check_error"] > 0.5
+    for k in bad:
+        assert np.array_equal(k1[:, 256 * k:256 * (k + 1)], k0[:, 256 * k:256 * (k + 1)])
+    assert st["fallback_chunks"] == len(bad)
+    # a clean chunk outside the recomputed tiles keeps the network's values
+    clean = [k for k in range(n_chunks) if k // 2 not in {b // 2 for b in bad}]
+    assert not np.array_equal(k1[:, 256 * clean[0]:256 * (clean[0] + 1)],
+                              k0[:, 256 * clean[0]:256 * (clean[0] + 1)])
