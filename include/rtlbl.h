@@ -303,6 +303,16 @@ rt_status rt_batch_launch(rt_ctx ctx);
 rt_status rt_batch_results(rt_ctx ctx, double* absorbed_W, double* emitted_W,
                            double* balance);
 
+/* The whole batched form in one call, for callers that do not keep a
+ * prepared batch: the workspace is allocated here (rt_batch_workspace_size
+ * bytes of device memory, freed before returning), then rt_batch_prepare,
+ * one rt_batch_launch and rt_batch_results as above.  tuning NULL: the
+ * default.  Synchronises; leaves no batch prepared.  RT_ENOMEM when the
+ * workspace cannot be allocated. */
+rt_status rt_batch_run(rt_ctx ctx, int n_cases, const rt_case* cases, int kappa_mode,
+                       const rt_batch_tuning* tuning, double* absorbed_W, double* emitted_W,
+                       double* balance);
+
 /* Picks chunk_points, kappa_groups, march_rays, blocks_per_cu and slots by timing
  * launches restricted to the first spectral chunks of every case (a sweep
  * one parameter at a time from the default), and remembers the winner in a

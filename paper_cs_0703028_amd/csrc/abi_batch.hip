@@ -455,6 +455,27 @@ rt_status rt_batch_results(rt_ctx c, double* absorbed, double* emitted, double* 
   return RT_OK;
 }
 
+rt_status rt_batch_run(rt_ctx c, int n_cases, const rt_case* cases, int kappa_mode,
+                       const rt_batch_tuning* tuning, double* absorbed, double* emitted,
+                       double* balance) {
+  if (!c) return RT_EINVAL;
+  int64_t bytes = 0;
+  if (rt_status s = rt_batch_workspace_size(c, n_cases, cases, tuning, &bytes)) return s;
+  RT_BHIP(c, hipSetDevice(c->device));
+  void* ws = nullptr;
+  hipError_t e = hipMalloc(&ws, (size_t)bytes);
+  if (e != hipSuccess)
+    return bfail(c, RT_ENOMEM, std::string("rt_batch_run: workspace of ") + std::to_string(bytes) +
+                                   " bytes: " + hipGetErrorString(e));
+  rt_status s = rt_batch_prepare(c, n_cases, cases, kappa_mode, tuning, ws, bytes);
+  if (s == RT_OK) s = rt_batch_launch(c);
+  if (s == RT_OK) s = rt_batch_results(c, absorbed, emitted, balance);
+  (void)hipStreamSynchronize(c->stream);  // nothing may still read the workspace
+  release_plan(c);
+  (void)hipFree(ws);
+  return s;
+}
+
 rt_status rt_batch_autotune(rt_ctx c, int n_cases, const rt_case* cases, int kappa_mode, void* ws,
                             int64_t bytes, const char* cache_path, rt_batch_tuning* best) {
   if (!c || !best) return RT_EINVAL;

@@ -118,6 +118,7 @@ def _load():
                                    C.POINTER(BatchTuning), vp, C.c_int64]
     L.rt_batch_launch.argtypes = [vp]
     L.rt_batch_results.argtypes = [vp, vp, vp, vp]
+    L.rt_batch_run.argtypes = [vp, C.c_int, C.POINTER(RtCase), C.c_int, vp, vp, vp, vp]
     L.rt_batch_autotune.argtypes = [vp, C.c_int, C.POINTER(RtCase), C.c_int, vp, C.c_int64,
                                     C.c_char_p, C.POINTER(BatchTuning)]
     L.rt_surrogate_train.argtypes = [vp, C.POINTER(SurrogateCfg), C.POINTER(C.c_double)]
@@ -382,6 +383,23 @@ class Tracer:
         e = np.zeros(tot, np.float64)
         b = np.zeros((len(sizes), 4), np.float64)
         self._check(lib.rt_batch_results(self._h, _ptr(a), _ptr(e), _ptr(b)))
+        out, off = [], 0
+        for k, n in enumerate(sizes):
+            out.append((a[off:off + n], e[off:off + n], b[k]))
+            off += n
+        return out
+
+    def batch_run(self, workloads, kappa_mode=KAPPA_PLAIN, tuning=None):
+        """The batched form in one call (the library allocates and frees the
+        workspace).  Per case: (absorbed [cells], emitted [cells], balance [4])."""
+        sizes = [w.grid.n_cells for w in workloads]
+        tot = int(sum(sizes))
+        a = np.zeros(tot, np.float64)
+        e = np.zeros(tot, np.float64)
+        b = np.zeros((len(sizes), 4), np.float64)
+        arr, keep = self._cases(workloads)
+        self._check(lib.rt_batch_run(self._h, len(workloads), arr, kappa_mode,
+                                     C.byref(tuning) if tuning else None, _ptr(a), _ptr(e), _ptr(b)))
         out, off = [], 0
         for k, n in enumerate(sizes):
             out.append((a[off:off + n], e[off:off + n], b[k]))

@@ -113,6 +113,25 @@ def test_batch_graph_replays(rt):
     del ws
 
 
+def test_batch_run_one_call(rt):
+    # the one-call form (workspace allocated and freed by the library) gives
+    # the prepared batch's results, and leaves no batch prepared
+    cases = _cases()[:3]
+    t = rt.Tracer(0)
+    t.setup_lines(cases[0].lines)
+    ws = t.batch_prepare(cases)
+    t.batch_launch()
+    ref = t.batch_results()
+    del ws
+    got = t.batch_run(cases)
+    for (a0, e0, b0), (a1, e1, b1) in zip(ref, got):
+        np.testing.assert_allclose(a1, a0, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(e1, e0, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(b1, b0, rtol=1e-12, atol=0)
+    assert t.raw_status("rt_batch_launch") == rt.RT_ESTATE
+    t.close()
+
+
 def test_batch_autotune_and_cache(rt, tmp_path):
     import torch
     cases = _cases()
