@@ -21,7 +21,10 @@ rt_status fail(rt_ctx c, rt_status s, const std::string& msg) {
   return s;
 }
 
+// Reports a HIP failure and clears it from the runtime's last error, so that
+// the next call's launch checks do not report it again.
 rt_status hip_fail(rt_ctx c, hipError_t e, const char* what) {
+  (void)hipGetLastError();
   return fail(c, (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? RT_ENOMEM : RT_EDEVICE,
               std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -32,11 +35,16 @@ rt_status hip_fail(rt_ctx c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);  \
   } while (0)
 
+// A failed hipMalloc also leaves its error as the runtime's last error, which
+// the next launch check (hipGetLastError) would report; it is cleared here and
+// returned once.
 template <class T>
 hipError_t dev_alloc(T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
 }
 
 template <class T>
@@ -184,6 +192,7 @@ rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream) {
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_adapt_evals), sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->d_adapt_evals, 0, sizeof(unsigned long long));
   if (e != hipSuccess) {
+    (void)hipGetLastError();  // not left for the next launch check
     rt_destroy(c);
     return fail(nullptr, RT_ENOMEM, std::string("rt_create: ") + hipGetErrorString(e));
   }

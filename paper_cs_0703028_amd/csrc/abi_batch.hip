@@ -27,7 +27,8 @@ rt_status bfail(rt_ctx c, rt_status s, const std::string& m) {
   do {                                                                                  \
     hipError_t e_ = (call);                                                             \
     if (e_ != hipSuccess)                                                               \
-      return bfail(ctx, (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE,           \
+      return (void)hipGetLastError(), /* not left for the next launch check */          \
+             bfail(ctx, (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE,           \
                    std::string(#call) + ": " + hipGetErrorString(e_));                  \
   } while (0)
 
@@ -464,9 +465,11 @@ rt_status rt_batch_run(rt_ctx c, int n_cases, const rt_case* cases, int kappa_mo
   RT_BHIP(c, hipSetDevice(c->device));
   void* ws = nullptr;
   hipError_t e = hipMalloc(&ws, (size_t)bytes);
-  if (e != hipSuccess)
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // not left for the next launch check
     return bfail(c, RT_ENOMEM, std::string("rt_batch_run: workspace of ") + std::to_string(bytes) +
                                    " bytes: " + hipGetErrorString(e));
+  }
   rt_status s = rt_batch_prepare(c, n_cases, cases, kappa_mode, tuning, ws, bytes);
   if (s == RT_OK) s = rt_batch_launch(c);
   if (s == RT_OK) s = rt_batch_results(c, absorbed, emitted, balance);

@@ -672,14 +672,17 @@ rt_status sfail(rt_ctx c, rt_status s, const std::string& m) {
   do {                                                                                  \
     hipError_t e_ = (call);                                                             \
     if (e_ != hipSuccess)                                                               \
-      return sfail(ctx, (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE,           \
+      return (void)hipGetLastError(), /* not left for the next launch check */          \
+             sfail(ctx, (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE,           \
                    std::string(#call) + ": " + hipGetErrorString(e_));                  \
   } while (0)
 
 template <class T>
 hipError_t dalloc(T** p, int64_t n) {
   *p = nullptr;
-  return hipMalloc(reinterpret_cast<void**>(p), (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) (void)hipGetLastError();  // not left for the next launch check
+  return e;
 }
 template <class T>
 void dfree(T*& p) {

@@ -132,6 +132,23 @@ def test_batch_run_one_call(rt):
     t.close()
 
 
+def test_batch_run_out_of_memory_is_reported(rt):
+    # a 2048 x 1 x 1 case with 2^31 rays asks for about 35 TB of segment
+    # workspace: the device allocation fails, the call returns RT_ENOMEM,
+    # and the handle stays usable
+    from dataclasses import replace
+    cases = _cases()[:1]
+    t = rt.Tracer(0)
+    t.setup_lines(cases[0].lines)
+    huge = replace(cases[0], grid=I.linear_T_grid(2048, 0.001, ny=1, nz=1), n_rays=1 << 31)
+    with pytest.raises(rt.RtError) as e:
+        t.batch_run([huge])
+    assert e.value.status == rt.RT_ENOMEM
+    print("huge batch:", t.last_error(), flush=True)
+    assert len(t.batch_run(cases)) == 1
+    t.close()
+
+
 def test_batch_autotune_and_cache(rt, tmp_path):
     import torch
     cases = _cases()
