@@ -92,6 +92,39 @@ def test_batch_matches_single_runs_and_oracle(rt):
     del ws
 
 
+def test_full_64_case_batch_sampled_cases(rt):
+    """The 64-case workload (16^3-48^3 cells, 2^14-2^18 rays, 5,000 lines,
+    20,000 points) in the launch configuration bench times (the committed
+    tuning): the smallest, the largest and one more case against the
+    single-case path, which is itself checked against the oracle."""
+    import json
+    import torch
+    cases = I.batched_cases(64)
+    t = rt.Tracer(0)
+    t.setup_lines(cases[0].lines)
+    here = os.path.dirname(os.path.abspath(__file__))
+    cache = os.path.join(os.path.dirname(here), "paper_cs_0703028_amd", "tuning", "batch_tune.json")
+    vals = list(json.load(open(cache)).values())[0]
+    tun = rt.Tracer.default_tuning()
+    (tun.chunk_points, tun.kappa_groups, tun.march_rays, tun.blocks_per_cu, tun.slots) = vals
+    print("64-case batch, tuning", vals, flush=True)
+    ws = t.batch_prepare(cases, rt.KAPPA_PLAIN, tun)
+    t.batch_launch()
+    out = t.batch_results()
+    t.close()
+    del ws
+    torch.cuda.empty_cache()
+    sizes = [c.grid.n_cells * c.n_rays for c in cases]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17})
+    for k in pick:
+        w = cases[k]
+        print(f"  case {k}: {w.grid.nx}^3 cells, {w.n_rays} rays", flush=True)
+        sa, se, sb = _single(rt, w)
+        a, e, b = out[k]
+        assert _rel(a, sa).max() <= 1e-9 and _rel(e, se).max() <= 1e-9
+        assert _rel(b, sb).max() <= 1e-9      # balance; entering is 0 with cold walls
+
+
 def test_batch_graph_replays(rt):
     cases = _cases()[:3]
     t = rt.Tracer(0)
