@@ -40,7 +40,7 @@ static_assert(kLineTile <= 256, "staged line indices are kept in bytes");
 
 constexpr int kAdThreads = 256;
 constexpr int kCellF = 8;  // floats per cell in the screening's cell record
-constexpr int kAdRec = 4 + 2 * kKappaCells;  // floats per staged line
+constexpr int kAdRec = kLineRec;  // floats per staged line
 
 // Eq. (1) strength ratio in binary64: q exp(-c2 E/T) / exp(-c2 E/T_ref)
 // * expm1(-c2 nu/T) / expm1(-c2 nu/T_ref), taken as
@@ -379,9 +379,8 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_window_scan_kernel(Window
 }
 
 // One block: points [j0, j0 + 512) of the run of 8 cells `run`, as the plain
-// line-sum tile (dev::kappa_tile) with a window per (run, line).  Staged
-// record per line: m, phi, lo, hi (offsets from m) and, per cell, the
-// Lorentz amplitude and squared half width in grid units.
+// line-sum tile (dev::kappa_tile) with a window per (run, line): the staged
+// line records (dev::kLineRec) carry the run's window offsets lo, hi.
 __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile a,
                                                                        const uint32_t* __restrict__ win,
                                                                        int n_tiles) {
@@ -412,33 +411,6 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[p][c] = 0.f;
 
-  auto add_line = [&](auto full_tag, int l) {
-    constexpr bool FULL = decltype(full_tag)::value;
-    const float* rec = lds + l * kAdRec;
-    const float4 h = *reinterpret_cast<const float4*>(rec);
-    float dv[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const float t = jf[p] - h.x;
-      const float d = t - h.y;
-      if (FULL) {
-        dv[p] = d;
-      } else {
-        const bool in = (t >= h.z) & (t <= h.w);
-        dv[p] = in ? d : __builtin_inff();
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < C; c += 2) {
-      const float4 ag = *reinterpret_cast<const float4*>(rec + 4 + 2 * c);
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        acc[p][c] = fmaf(ag.x, fast_rcp(fmaf(dv[p], dv[p], ag.y)), acc[p][c]);
-        acc[p][c + 1] = fmaf(ag.z, fast_rcp(fmaf(dv[p], dv[p], ag.w)), acc[p][c + 1]);
-      }
-    }
-  };
-
   for (int base = blk_first; base < blk_end; base += kLineTile) {
     const int nt = min(kLineTile, blk_end - base);
     __syncthreads();
@@ -455,14 +427,7 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile
         rec[2] = (float)(int16_t)(uint16_t)(w & 0xffffu);
         rec[3] = (float)(int16_t)(uint16_t)(w >> 16);
       }
-      const float gp = a.L.gamma[i] * a.C.P[cell] * fast_exp2(a.L.nexp[i] * a.C.lam2[cell]);
-      float amp = a.C.G[cell] * a.L.S[i] * gp;
-      if (a.have_E) {
-        amp *= exp_split(a.L.E2[i] * a.C.beta[cell]);
-        amp *= one_minus_exp_neg_d(a.L.nu[i] * a.C.theta[cell]);
-      }
-      rec[4 + 2 * cc] = amp;
-      rec[5 + 2 * cc] = gp * gp;
+      line_cell_params(a.L, a.C, i, cell, a.have_E, rec[4 + 2 * cc], rec[5 + 2 * cc]);
     }
     __syncthreads();
     // this wavefront's lines: those whose window meets [wj0, wj0 + span);
@@ -485,8 +450,9 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile
       np += __popcll(bp);
     }
     __syncthreads();
-    for (int e = 0; e < nf; ++e) add_line(std::true_type(), lists[wave][e]);
-    for (int e = 0; e < np; ++e) add_line(std::false_type(), lists[wave][kLineTile - 1 - e]);
+    for (int e = 0; e < nf; ++e) add_line_terms<true, P>(lds + lists[wave][e] * kAdRec, jf, acc);
+    for (int e = 0; e < np; ++e)
+      add_line_terms<false, P>(lds + lists[wave][kLineTile - 1 - e] * kAdRec, jf, acc);
   }
 
 #pragma unroll

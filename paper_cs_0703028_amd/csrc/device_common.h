@@ -74,13 +74,65 @@ __device__ __forceinline__ void two_sum_acc(float& s, float& comp, float x) {
   comp += err;
 }
 
+// ------------------------------------------------------------ line records
+// A staged line: (m, phi, lo, hi) -- the integer centre, the fraction, and
+// the first and last offsets from m of the points the line contributes to
+// -- then, per cell, (A, g2): the Lorentz amplitude u S s gamma / (pi dnu^2)
+// and the squared half width (gamma/dnu)^2 in grid units, so that the line
+// adds A / ((j - m - phi)^2 + g2) at point j.
+constexpr int kLineRec = 4 + 2 * kKappaCells;  // floats per staged line
+
+// The per-cell part of a record for line i and cell `cell` (Eqs. (1)-(2)).
+__device__ __forceinline__ void line_cell_params(const LineSet& L, const CellSet& C, int i,
+                                                 int64_t cell, int have_E, float& amp, float& g2) {
+  const float gp = L.gamma[i] * C.P[cell] * fast_exp2(L.nexp[i] * C.lam2[cell]);
+  float a = C.G[cell] * L.S[i] * gp;
+  if (have_E) {
+    a *= exp_split(L.E2[i] * C.beta[cell]);
+    a *= one_minus_exp_neg_d(L.nu[i] * C.theta[cell]);
+  }
+  amp = a;
+  g2 = gp * gp;
+}
+
+// Adds one staged line to P points x kKappaCells cells of a lane: jf are the
+// lane's points as floats.  FULL: every point is inside [m + lo, m + hi];
+// otherwise a point outside gets an infinite offset, whose term is 0.
+template <bool FULL, int P>
+__device__ __forceinline__ void add_line_terms(const float* rec, const float (&jf)[P],
+                                               float (&part)[P][kKappaCells]) {
+  const float4 h = *reinterpret_cast<const float4*>(rec);
+  float dv[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const float t = jf[p] - h.x;
+    const float d = t - h.y;
+    if (FULL) {
+      dv[p] = d;
+    } else {
+      const bool in = (t >= h.z) & (t <= h.w);
+      dv[p] = in ? d : __builtin_inff();
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kKappaCells; c += 2) {
+    const float4 ag = *reinterpret_cast<const float4*>(rec + 4 + 2 * c);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      part[p][c] = fmaf(ag.x, fast_rcp(fmaf(dv[p], dv[p], ag.y)), part[p][c]);
+      part[p][c + 1] = fmaf(ag.z, fast_rcp(fmaf(dv[p], dv[p], ag.w)), part[p][c + 1]);
+    }
+  }
+}
+
 // ------------------------------------------------------------ line sum tile
 // Eq. (2) with the Eq. (1) strength ratio for one block: nu points
 // [j0, j0 + 512) x kKappaCells cells starting at cell0.  Wave w owns the
 // points j0 + 128 w + 64 p + lane (p < 2).  Lines whose window meets the
-// block's points are staged kLineTile at a time: per line (m, phi, window
-// start) and, per cell, the Lorentz amplitude A = u S s gamma / (pi dnu^2)
-// and the squared half width g2 = (gamma/dnu)^2, so that a line adds
+// block's points are staged kLineTile at a time as line records (m, phi,
+// the window's offsets -K + [phi > 0] and K, and per cell the Lorentz
+// amplitude A = u S s gamma / (pi dnu^2) and the squared half width
+// g2 = (gamma/dnu)^2), so that a line adds
 //   A / ((j - r_i)^2 + g2)
 // to kappa at point j.  Grid units: line i sits at r_i = (nu_i - nu0)/dnu =
 // m_i + phi_i with integer m_i; the offset j - r_i is the exact float
@@ -89,7 +141,7 @@ __device__ __forceinline__ void two_sum_acc(float& s, float& comp, float x) {
 // [m_i - K + [phi_i > 0], m_i + K], the exact form of |j - r_i| <= K.
 // Output: out[(cell - 0) * ld_out + (j - col0)] for col0 <= j < col_end;
 // points at or beyond n_nu are written as 0.  Must be called by all 256
-// threads of the block; `lds` holds kLineTile * (4 + 2 kKappaCells) floats.
+// threads of the block; `lds` holds kLineTile * kLineRec floats.
 struct KappaTile {
   LineSet L;
   CellSet C;          // per-cell factors of this grid (row 0 = its first cell)
@@ -126,7 +178,7 @@ struct TileGate {
 template <bool COMP>
 __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds) {
   constexpr int C = kKappaCells, P = kKappaPoints;
-  constexpr int REC = 4 + 2 * C;
+  constexpr int REC = kLineRec;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -147,7 +199,6 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
   float jf[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) jf[p] = (float)(wj0 + 64 * p + lane);
-  const float Kf = (float)a.K;
 
   // windows are non-decreasing along the sorted list, so the lines whose
   // window covers [wj0, wj0 + span) are the contiguous range [f_first, f_end)
@@ -174,31 +225,7 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
       for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int c = 0; c < C; ++c) part[p][c] = COMP ? 0.f : acc[p][c];
-      for (int l = s0; l < s1; ++l) {
-        const float* rec = lds + (l - base) * REC;
-        const float4 h = *reinterpret_cast<const float4*>(rec);
-        float dv[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          const float t = jf[p] - h.x;
-          const float d = t - h.y;
-          if (FULL) {
-            dv[p] = d;
-          } else {
-            const bool in = (t >= h.z) & (t <= Kf);
-            dv[p] = in ? d : __builtin_inff();
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < C; c += 2) {
-          const float4 ag = *reinterpret_cast<const float4*>(rec + 4 + 2 * c);
-#pragma unroll
-          for (int p = 0; p < P; ++p) {
-            part[p][c] = fmaf(ag.x, fast_rcp(fmaf(dv[p], dv[p], ag.y)), part[p][c]);
-            part[p][c + 1] = fmaf(ag.z, fast_rcp(fmaf(dv[p], dv[p], ag.w)), part[p][c + 1]);
-          }
-        }
-      }
+      for (int l = s0; l < s1; ++l) add_line_terms<FULL, P>(lds + (l - base) * REC, jf, part);
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
@@ -224,16 +251,9 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
         rec[0] = (float)a.L.m[i];
         rec[1] = a.L.phi[i];
         rec[2] = (float)(a.L.wlo[i] - a.L.m[i]);  // -K + [phi > 0]
-        rec[3] = 0.f;
+        rec[3] = (float)a.K;
       }
-      const float gp = a.L.gamma[i] * a.C.P[cell] * fast_exp2(a.L.nexp[i] * a.C.lam2[cell]);
-      float amp = a.C.G[cell] * a.L.S[i] * gp;
-      if (a.have_E) {
-        amp *= exp_split(a.L.E2[i] * a.C.beta[cell]);
-        amp *= one_minus_exp_neg_d(a.L.nu[i] * a.C.theta[cell]);
-      }
-      rec[4 + 2 * cc] = amp;
-      rec[5 + 2 * cc] = gp * gp;
+      line_cell_params(a.L, a.C, i, cell, a.have_E, rec[4 + 2 * cc], rec[5 + 2 * cc]);
     }
     __syncthreads();
 
