@@ -76,6 +76,8 @@ def lib():
                                          C.c_double, C.c_double, C.c_double, C.c_int,
                                          C.c_double, C.c_int, _f64p]
         L.orc_kappa_adaptive.restype = C.c_int
+        L.orc_wing_return.argtypes = L.orc_kappa_adaptive.argtypes
+        L.orc_wing_return.restype = C.c_int
         L.orc_adaptive_evals.argtypes = [C.c_int, _f64p, _f64p, C.c_int, _f64p, _f64p, _f64p,
                                          _f64p, C.c_void_p, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_int, C.c_double, C.c_int]
@@ -208,21 +210,46 @@ def mean_strength(T, lines) -> float:
                                    lines.T_ref, lines.cutoff, lines.nu0, lines.dnu, lines.n_nu)
 
 
-def kappa_adaptive(grid, lines, eps, cell_list=None, group=ADAPTIVE_GROUP) -> np.ndarray:
-    """kappa rows of the adaptive-window form (rt_oracle.c)."""
+def kappa_adaptive(grid, lines, eps, cell_list=None, group=ADAPTIVE_GROUP,
+                   wings=False) -> np.ndarray:
+    """kappa rows of the adaptive-window form (rt_oracle.c); with wings, each
+    row also carries its cell's wing-return constant (wing_return)."""
     if cell_list is None:
         cell_list = np.arange(grid.n_cells, dtype=np.int32)
     cell_list = np.ascontiguousarray(cell_list, np.int32)
     out = np.zeros((len(cell_list), lines.n_nu), np.float64)
-    E = None if lines.E_lower is None else np.ascontiguousarray(lines.E_lower, np.float64)
-    Ep = None if E is None else E.ctypes.data_as(C.c_void_p)
-    rc = lib().orc_kappa_adaptive(len(cell_list), cell_list, grid.n_cells, _f(grid.T), _f(grid.x),
-                                  _f(grid.p), len(lines.nu), _f(lines.nu), _f(lines.S),
-                                  _f(lines.gamma), _f(lines.n_T), Ep, lines.T_ref, lines.cutoff,
-                                  lines.nu0, lines.dnu, lines.n_nu, float(eps), int(group), out)
+    args, keep = _adaptive_args(grid, lines, eps, cell_list, group)
+    rc = lib().orc_kappa_adaptive(*args, out)
     if rc != 0:
         raise ValueError(f"orc_kappa_adaptive: bad arguments ({rc})")
+    if wings:
+        out += wing_return(grid, lines, eps, cell_list, group)[:, None]
     return out
+
+
+def wing_return(grid, lines, eps, cell_list=None, group=ADAPTIVE_GROUP) -> np.ndarray:
+    """Per listed cell, the band-uniform constant that returns the Lorentz
+    mass of the points the adaptive windows drop (rt_oracle.c)."""
+    if cell_list is None:
+        cell_list = np.arange(grid.n_cells, dtype=np.int32)
+    cell_list = np.ascontiguousarray(cell_list, np.int32)
+    out = np.zeros(len(cell_list), np.float64)
+    args, keep = _adaptive_args(grid, lines, eps, cell_list, group)
+    rc = lib().orc_wing_return(*args, out)
+    if rc != 0:
+        raise ValueError(f"orc_wing_return: bad arguments ({rc})")
+    return out
+
+
+def _adaptive_args(grid, lines, eps, cell_list, group):
+    # the arguments, and the energies array that the raw pointer in them
+    # refers to (the caller keeps it alive over the call)
+    E = None if lines.E_lower is None else np.ascontiguousarray(lines.E_lower, np.float64)
+    Ep = None if E is None else E.ctypes.data_as(C.c_void_p)
+    return (len(cell_list), cell_list, grid.n_cells, _f(grid.T), _f(grid.x), _f(grid.p),
+            len(lines.nu), _f(lines.nu), _f(lines.S), _f(lines.gamma), _f(lines.n_T), Ep,
+            lines.T_ref, lines.cutoff, lines.nu0, lines.dnu, lines.n_nu, float(eps),
+            int(group)), E
 
 
 def adaptive_evals(grid, lines, eps, group=ADAPTIVE_GROUP) -> int:

@@ -29,6 +29,10 @@
  *              keeps exactly the points where its plain value reaches the
  *              threshold; nesting in the tolerance; the dropped remainder
  *              within its bound; brute-force value-criterion counts
+ *   wing return  nothing to return at vanishing tolerance; one isolated
+ *              line dropped whole returns its Poisson-comb band mean; the
+ *              band integral of the plain sum within the midpoint rule's
+ *              bound; a symmetric line's two wings in closed form
  */
 #include <math.h>
 #include <stdint.h>
@@ -604,6 +608,76 @@ double orc_adaptive_evals(int n_cells, const double* T, const double* p, int n_l
     total += kept * (double)members;
   }
   return total;
+}
+
+/* ======================================================================
+ * Wing return: an extension of the adaptive form (not in the paper).  The
+ * points a line drops in cell c -- inside its hard window and on the grid,
+ * outside the run's kept interval -- carry a Lorentz mass that the plain sum
+ * would have added.  Each maximal run of consecutive dropped points a..b is
+ * priced by the midpoint rule, the integral of the profile over
+ * [a - 1/2, b + 1/2] in grid units:
+ *   sum_{j=a..b} g / (pi ((j - r)^2 dnu^2 + g^2))
+ *     ~ (atan((b + 1/2 - r) dnu / g) - atan((a - 1/2 - r) dnu / g)) / (pi dnu)
+ * and the cell's total over all lines is returned as a constant over the
+ * band:
+ *   wing_c = u_c / (n_nu pi dnu) sum_i S_i s_ci (sum over its dropped runs
+ *            of the atan differences),
+ * which kappa_c(nu_j) of the adaptive form then carries at every j.
+ * Returns -1 on a non-integer cutoff/dnu, -2 on bad eps or group. */
+int orc_wing_return(int n_cells_listed, const int32_t* cell_list, int n_cells, const double* T,
+                    const double* x, const double* p, int n_lines, const double* nu_line,
+                    const double* S_ref, const double* gamma_ref, const double* n_T,
+                    const double* E_lower, double T_ref, double cutoff_cm, double nu0,
+                    double dnu, int n_nu, double eps, int group, double* out) {
+  double Kd = cutoff_cm / dnu;
+  double K = floor(Kd + 0.5);
+  if (fabs(Kd - K) > 1e-9 * (K > 1.0 ? K : 1.0)) return -1;
+  if (!(eps > 0.0) || group < 1 || group > 64) return -2;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int row = 0; row < n_cells_listed; ++row) {
+    int c = cell_list[row];
+    int grp = c / group;
+    double sbar[64];
+    for (int k = 0; k < group; ++k) {
+      int cc = grp * group + k;
+      sbar[k] = cc < n_cells ? orc_mean_strength(T[cc], n_lines, nu_line, S_ref, E_lower,
+                                                 T_ref, cutoff_cm, nu0, dnu, n_nu)
+                             : 0.0;
+    }
+    double total = 0.0;
+    for (int i = 0; i < n_lines; ++i) {
+      double r = (nu_line[i] - nu0) / dnu;
+      if (!orc_meets_grid(r, K, n_nu)) continue;
+      double hw = orc_group_window(grp, group, n_cells, T, p, sbar, i, nu_line, S_ref,
+                                   gamma_ref, n_T, E_lower, T_ref, dnu, eps, K);
+      double s = orc_strength_ratio(T[c], T_ref, nu_line[i],
+                                    E_lower ? E_lower[i] : 0.0, E_lower != NULL);
+      double g = orc_half_width(gamma_ref[i], n_T[i], T[c], T_ref, p[c]);
+      double jlo_d = ceil(r - K) - 1.0, jhi_d = floor(r + K) + 1.0;
+      long jlo = jlo_d < 0.0 ? 0 : (long)jlo_d;
+      long jhi = jhi_d > (double)(n_nu - 1) ? n_nu - 1 : (long)jhi_d;
+      double mass = 0.0;
+      long a = -1;  /* first point of the open run of dropped points */
+      for (long j = jlo; j <= jhi + 1; ++j) {
+        int dropped = 0;
+        if (j <= jhi) {
+          double jd = (double)j;
+          int hard = jd - K <= r && r <= jd + K;
+          dropped = hard && !orc_kept(jd, r, K, hw);
+        }
+        if (dropped && a < 0) a = j;
+        if (!dropped && a >= 0) {
+          double b = (double)(j - 1);
+          mass += atan((b + 0.5 - r) * dnu / g) - atan(((double)a - 0.5 - r) * dnu / g);
+          a = -1;
+        }
+      }
+      total += S_ref[i] * s * mass;
+    }
+    out[row] = orc_density(T[c], x[c], p[c]) * total / ((double)n_nu * M_PI * dnu);
+  }
+  return 0;
 }
 
 /* Eq. (4) in its wavenumber form: B(nu, T) = c1 nu^3 / (exp(c2 nu/T) - 1)
