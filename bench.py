@@ -441,13 +441,16 @@ def form_table16(rtlbl, I, reps=3):
     return out
 
 
-def form_adaptive(rtlbl, I, eps_list=(1e-3, 1e-4, 3e-5, 1e-5, 1e-6), reps=3):
+def form_adaptive(rtlbl, I, eps_list=(1e-3, 1e-4, 3e-5, 1e-5, 1e-6),
+                  wing_eps_list=(1e-2, 3e-3, 1e-3, 1e-4), reps=3):
     """Adaptive line windows (the paper's announced next version: points per
     line set by the local temperature and the line's intensity) on the 32^3
     workload beside the plain line sum: for each tolerance eps, the
     compute_kappa time (band means, windows and windowed sum), the fraction
     of line evaluations kept, and how far the per-cell absorbed power of the
-    same 2^20 rays moves from the plain sum's."""
+    same 2^20 rays moves from the plain sum's.  The same for the windows with
+    their wing return (the dropped points' Lorentz mass spread over the
+    band, an extension), at the tolerances listed for it."""
     import numpy as np
     import torch
     w = I.plain_32cube()
@@ -472,24 +475,31 @@ def form_adaptive(rtlbl, I, eps_list=(1e-3, 1e-4, 3e-5, 1e-5, 1e-6), reps=3):
     ms0, ev0 = timed(rtlbl.KAPPA_PLAIN)
     a0 = absorbed()
     m = a0 > 0
-    rows = []
-    for eps in eps_list:
-        t.set_line_tolerance(eps)
-        ms, ev = timed(rtlbl.KAPPA_ADAPTIVE)
-        a1 = absorbed()
-        rel = np.abs(a1[m] - a0[m]) / a0[m]
-        rows.append({
-            "eps": eps,
-            "kappa_ms": ms,
-            "evals_kept": ev / ev0,
-            "speedup_over_plain_line_sum": ms0 / ms,
-            "absorbed_rel_diff_vs_plain": {"max": float(rel.max()), "median": float(np.median(rel))},
-            "total_absorbed_rel_diff": float(abs(a1.sum() - a0.sum()) / a0.sum()),
-        })
+    def rows(mode, tolerances):
+        out = []
+        for eps in tolerances:
+            t.set_line_tolerance(eps)
+            ms, ev = timed(mode)
+            a1 = absorbed()
+            rel = np.abs(a1[m] - a0[m]) / a0[m]
+            out.append({
+                "eps": eps,
+                "kappa_ms": ms,
+                "evals_kept": ev / ev0,
+                "speedup_over_plain_line_sum": ms0 / ms,
+                "absorbed_rel_diff_vs_plain": {"max": float(rel.max()),
+                                               "median": float(np.median(rel))},
+                "total_absorbed_rel_diff": float(abs(a1.sum() - a0.sum()) / a0.sum()),
+            })
+        return out
+
+    res = {"workload": w.name, "kappa_ms_plain": ms0, "line_evals_plain": ev0,
+           "tolerances": rows(rtlbl.KAPPA_ADAPTIVE, eps_list),
+           "wing_return": rows(rtlbl.KAPPA_ADAPTIVE_WINGS, wing_eps_list)}
     t.close()
     del kap
     torch.cuda.empty_cache()
-    return {"workload": w.name, "kappa_ms_plain": ms0, "line_evals_plain": ev0, "tolerances": rows}
+    return res
 
 
 def form_arith(rtlbl, I):

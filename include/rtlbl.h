@@ -60,12 +60,26 @@ typedef enum {
                                 the density and the Eq. (1) strength ratio;
                                 multiply-adds only, no per-cell half width.  An
                                 approximation of the plain sum, every gas. */
-  RT_KAPPA_ADAPTIVE = 4      /* the paper's announced next version (its
+  RT_KAPPA_ADAPTIVE = 4,     /* the paper's announced next version (its
                                 conclusion): the points evaluated per line
                                 follow the local temperature and the line's
                                 intensity.  The FP32 line sum of the plain
                                 mode over adaptive windows: see
                                 rt_set_line_tolerance.  Gas 0 only. */
+  RT_KAPPA_ADAPTIVE_WINGS = 5 /* an extension of RT_KAPPA_ADAPTIVE, not in
+                                the paper: the same windows and line sum,
+                                plus per cell the Lorentz mass of the points
+                                the windows drop, returned as one constant
+                                over the band.  Each dropped range a..b of
+                                line i (in its plain window, on the grid)
+                                counts its midpoint-rule integral, u S_i s_ci
+                                (atan((b + 1/2 - r_i) dnu / g) - atan((a -
+                                1/2 - r_i) dnu / g)) / (pi dnu), and cell c
+                                adds the sum over its lines, divided by n_nu,
+                                at every point: the band integral of the plain
+                                sum is kept to within the midpoint rule's
+                                error on the wings (Eq. (2) with the cutoff).
+                                Gas 0 only; needs rt_set_line_tolerance. */
 } rt_kappa_mode;
 
 /* Cells sharing one line window in RT_KAPPA_ADAPTIVE: cell c belongs to the

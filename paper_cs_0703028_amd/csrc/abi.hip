@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "adaptive.h"
 #include "rt_internal.h"
 
 namespace {
@@ -528,9 +529,10 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   if (!c->have_grid || !c->have_lines)
     return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_setup_grid and rt_setup_lines first");
   if (mode != RT_KAPPA_PLAIN && mode != RT_KAPPA_COMPENSATED && mode != RT_KAPPA_SURROGATE &&
-      mode != RT_KAPPA_TABLE16 && mode != RT_KAPPA_ADAPTIVE)
+      mode != RT_KAPPA_TABLE16 && mode != RT_KAPPA_ADAPTIVE && mode != RT_KAPPA_ADAPTIVE_WINGS)
     return fail(c, RT_EINVAL, "rt_compute_kappa: unknown mode");
-  if (mode == RT_KAPPA_ADAPTIVE) {
+  const bool adaptive = mode == RT_KAPPA_ADAPTIVE || mode == RT_KAPPA_ADAPTIVE_WINGS;
+  if (adaptive) {
     if (!(c->line_tol > 0))
       return fail(c, RT_ESTATE, "rt_compute_kappa: call rt_set_line_tolerance before the adaptive mode");
     if (n_gases(c) > 1)
@@ -558,13 +560,13 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     RT_HIP(c, dev_alloc(&c->d_bwall, (size_t)ld));
     c->bwall_len = ld;
   }
-  if (mode == RT_KAPPA_ADAPTIVE) {
+  if (adaptive) {
     const int64_t runs = (c->n_cells + RT_ADAPTIVE_GROUP - 1) / RT_ADAPTIVE_GROUP;
     const int64_t win = runs * (int64_t)std::max(c->lines.n, 1);
-    if (c->sbar_cap < c->n_cells) {  // per cell: 2 doubles, then an 8-float record
+    if (c->sbar_cap < c->n_cells) {  // per cell: 2 doubles, an 8-float record, the wing constant
       dev_free(c->d_sbar);
       c->sbar_cap = 0;
-      RT_HIP(c, dev_alloc(&c->d_sbar, (size_t)(6 * c->n_cells)));
+      RT_HIP(c, dev_alloc(&c->d_sbar, (size_t)(rt::kAdaptiveCellDoubles * c->n_cells)));
       c->sbar_cap = c->n_cells;
     }
     // room for 1/16 of the windows to be left to binary64 (about 0.3% are
@@ -599,6 +601,8 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     RT_HIP(c, rt::launch_kappa_table16(c));
   } else if (mode == RT_KAPPA_ADAPTIVE) {
     RT_HIP(c, rt::launch_kappa_adaptive(c));
+  } else if (mode == RT_KAPPA_ADAPTIVE_WINGS) {
+    RT_HIP(c, rt::launch_kappa_adaptive_wings(c));
   } else {
     RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
   }
@@ -609,7 +613,7 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     for (const auto& g : c->gas)
       if (g.active) lines += g.lines.n;
     c->stats.line_evals += 16.0 * lines * (double)c->n_cells;
-  } else if (mode != RT_KAPPA_SURROGATE && mode != RT_KAPPA_ADAPTIVE) {
+  } else if (mode != RT_KAPPA_SURROGATE && !adaptive) {
     // (the adaptive windows count their kept evaluations on the device)
     double per_cell = c->line_evals_per_cell;
     for (const auto& g : c->gas)

@@ -17,6 +17,11 @@
 //                            lines whose window meets its 128 points, first
 //                            those covering all of them (no membership
 //                            test), then the rest
+//   adaptive_wing_kernel   : (wing-return form, an extension) per cell, the
+//                            Lorentz mass of the points its run's windows
+//                            drop, priced by the midpoint rule and spread
+//                            over the band as one constant that the line sum
+//                            adds to every point
 //
 // A line keeps point j of cell c while its Lorentz value there is at least
 // eps u_c sbar_c: |j - r_i| <= w_ci = sqrt(S s g / (pi eps sbar) - g^2)/dnu
@@ -28,6 +33,7 @@
 // only if its half width lies within that of a grid point's distance.
 #include <algorithm>
 
+#include "adaptive.h"
 #include "device_common.h"
 
 namespace rt {
@@ -383,7 +389,8 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_window_scan_kernel(Window
 // line records (dev::kLineRec) carry the run's window offsets lo, hi.
 __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile a,
                                                                        const uint32_t* __restrict__ win,
-                                                                       int n_tiles) {
+                                                                       int n_tiles,
+                                                                       const double* __restrict__ wing) {
   constexpr int C = kKappaCells, P = kKappaPoints;
   __shared__ float4 lds4[kLineTile * kAdRec / 4];
   __shared__ uint8_t lists[kKappaThreads / 64][kLineTile];
@@ -459,17 +466,94 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile
   for (int c = 0; c < C; ++c) {
     const int64_t cell = cell0 + c;
     if (cell >= a.n_cells) break;
+    const float add = wing ? (float)wing[cell] : 0.f;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int64_t j = wj0 + 64 * p + lane;
-      if (j < a.ld_out) a.out[cell * a.ld_out + j] = (j < a.n_nu) ? acc[p][c] : 0.f;
+      if (j < a.ld_out) a.out[cell * a.ld_out + j] = (j < a.n_nu) ? acc[p][c] + add : 0.f;
     }
   }
 }
 
+
+// atan(x1 + d) - atan(x1), d > 0: when both ends have one sign, as
+// atan(d / (1 + x1 (x1 + d))), which keeps the relative accuracy of a narrow
+// span far out in a wing (two arctangents near +-pi/2 would cancel); across
+// the centre the two arctangents have opposite signs and simply add.
+__device__ inline float atan_span(float x1, float d) {
+  const float x2 = x1 + d;
+  if (x1 >= 0.f || x2 <= 0.f) return atanf(d / fmaf(x1, x2, 1.f));
+  return atanf(x2) - atanf(x1);
+}
+
+// Wing return, one block per run of cells.  The points line i drops in the
+// run are those of its plain window on the grid, [max(wlo, 0), min(whi,
+// n_nu - 1)], outside the run's kept interval: at most two ranges, the same
+// for the run's cells.  Range [a, b] of cell c carries, by the midpoint rule
+// in grid units, amp_ci / g_ci (atan((b + 1/2 - r)/g) - atan((a - 1/2 -
+// r)/g)), with amp_ci and g_ci (half width in grid points) those of the line
+// sum.  Terms in FP32, sums in binary64; wing[c] = sum / n_nu.
+__global__ __launch_bounds__(kAdThreads) void adaptive_wing_kernel(LineSet L, CellSet C,
+                                                                  const uint32_t* __restrict__ win,
+                                                                  int64_t n_cells, int n_nu,
+                                                                  int have_E,
+                                                                  double* __restrict__ wing) {
+  constexpr int G = RT_ADAPTIVE_GROUP;
+  __shared__ double red[G][kAdThreads];
+  const int64_t run = blockIdx.x;
+  const int64_t cell0 = run * G;
+  const uint32_t* wrow = win + run * (int64_t)L.n;
+  double acc[G];
+#pragma unroll
+  for (int c = 0; c < G; ++c) acc[c] = 0.0;
+  for (int i = threadIdx.x; i < L.n; i += kAdThreads) {
+    const int m = L.m[i];
+    const uint32_t w = wrow[i];
+    const int lo_off = (int16_t)(uint16_t)(w & 0xffffu), hi_off = (int16_t)(uint16_t)(w >> 16);
+    const int h0 = max(L.wlo[i], 0), h1 = min(L.whi[i], n_nu - 1);
+    const int k0 = max(m + lo_off, 0), k1 = min(m + hi_off, n_nu - 1);
+    // dropped ranges (empty when a > b): the whole in-grid window when the
+    // run keeps none of it, else what lies below and above the kept points
+    int a0 = h0, b0 = h1, a1 = 1, b1 = 0;
+    if (lo_off <= hi_off && k0 <= k1) {
+      b0 = k0 - 1;
+      a1 = k1 + 1;
+      b1 = h1;
+    }
+    const bool r0 = a0 <= b0, r1 = a1 <= b1;
+    if (!r0 && !r1) continue;
+    const float phi = L.phi[i];
+    // range ends' offsets from the centre r = m + phi, and the widths
+    const float e0 = (float)(a0 - m) - 0.5f - phi, n0 = (float)(b0 - a0 + 1);
+    const float e1 = (float)(a1 - m) - 0.5f - phi, n1 = (float)(b1 - a1 + 1);
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      const int64_t cell = cell0 + c < n_cells ? cell0 + c : n_cells - 1;
+      float amp, g2;
+      line_cell_params(L, C, i, cell, have_E, amp, g2);
+      const float ig = 1.0f / sqrtf(g2);
+      float span = 0.f;
+      if (r0) span += atan_span(e0 * ig, n0 * ig);
+      if (r1) span += atan_span(e1 * ig, n1 * ig);
+      acc[c] += (double)(amp * ig * span);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < G; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int h = kAdThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int c = 0; c < G; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < G && cell0 + threadIdx.x < n_cells)
+    wing[cell0 + threadIdx.x] = red[threadIdx.x][0] / (double)n_nu;
+}
+
 }  // namespace
 
-hipError_t launch_kappa_adaptive(rt_ctx c) {
+static hipError_t launch_adaptive(rt_ctx c, bool wings) {
   const LineSet& L = c->lines;
   const int64_t runs = (c->n_cells + RT_ADAPTIVE_GROUP - 1) / RT_ADAPTIVE_GROUP;
   const int n_tiles = (int)((c->ld + kKappaTilePoints - 1) / kKappaTilePoints);
@@ -524,6 +608,14 @@ hipError_t launch_kappa_adaptive(rt_ctx c) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  double* wing = nullptr;
+  if (wings) {
+    wing = adaptive_wing_constants(c);
+    hipLaunchKernelGGL(adaptive_wing_kernel, dim3((unsigned)runs), dim3(kAdThreads), 0, c->stream, L,
+                       c->cells, c->d_win, c->n_cells, c->n_nu, c->have_E ? 1 : 0, wing);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   KappaTile t;
   t.L = L;
   t.C = c->cells;
@@ -536,8 +628,12 @@ hipError_t launch_kappa_adaptive(rt_ctx c) {
   t.col0 = 0;
   t.col_end = c->ld;
   hipLaunchKernelGGL(kappa_adaptive_kernel, dim3((unsigned)blocks), dim3(kKappaThreads), 0, c->stream, t,
-                     c->d_win, n_tiles);
+                     c->d_win, n_tiles, wing);
   return hipGetLastError();
 }
+
+hipError_t launch_kappa_adaptive(rt_ctx c) { return launch_adaptive(c, false); }
+
+hipError_t launch_kappa_adaptive_wings(rt_ctx c) { return launch_adaptive(c, true); }
 
 }  // namespace rt

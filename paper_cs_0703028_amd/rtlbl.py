@@ -21,7 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtlbl.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE, KAPPA_TABLE16, KAPPA_ADAPTIVE = 0, 1, 2, 3, 4
+(KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE, KAPPA_TABLE16, KAPPA_ADAPTIVE,
+ KAPPA_ADAPTIVE_WINGS) = 0, 1, 2, 3, 4, 5
 ADAPTIVE_GROUP = 8   # RT_ADAPTIVE_GROUP: cells sharing one line window
 TALLY_F32, TALLY_F64 = 0, 1
 # rt_arith_op: name -> (code, operands read)

@@ -1,9 +1,10 @@
-"""Adaptive line windows (RT_KAPPA_ADAPTIVE) through the C ABI against the
-FP64 oracle: kappa within 1e-5 relative with exact zeros where the oracle is
-zero (window membership is integer work, decided in binary64 on both
-sides), the kept-evaluation count equal to the oracle's, the march over the
-adaptive table, the full 32^3 workload on sampled runs of cells, and the
-error paths."""
+"""Adaptive line windows (RT_KAPPA_ADAPTIVE) and their wing return
+(RT_KAPPA_ADAPTIVE_WINGS) through the C ABI against the FP64 oracle: kappa
+within 1e-5 relative with exact zeros where the oracle is zero (window
+membership is integer work, decided in binary64 on both sides), the
+kept-evaluation count equal to the oracle's, the march over the adaptive
+tables, the full 32^3 workload on sampled runs of cells, and the error
+paths."""
 from dataclasses import replace
 
 import numpy as np
@@ -82,22 +83,23 @@ def test_vanishing_tolerance_gives_the_plain_sum(rt, O):
     t.close()
 
 
-def test_adaptive_tallies_match_oracle_march(rt, O):
+@pytest.mark.parametrize("wings", [False, True])
+def test_adaptive_tallies_match_oracle_march(rt, O, wings):
     w = I.plain_8cube()
     eps = 1e-4
     t = rt.Tracer(0)
     t.setup_workload(w)
     t.set_line_tolerance(eps)
-    t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    t.compute_kappa(rt.KAPPA_ADAPTIVE_WINGS if wings else rt.KAPPA_ADAPTIVE)
     t.trace_rays(w.seed, w.n_rays, 0, w.n_rays, 0)
     ag, eg, _ = t.tally()
     g = w.grid
     Or, Dr, _ = O.rays(w.seed, 0, w.n_rays, g.nx, g.ny, g.nz)
-    kap = O.kappa_adaptive(g, w.lines, eps)
+    kap = O.kappa_adaptive(g, w.lines, eps, wings=wings)
     a, e, _, _ = O.march(g, w.lines, Or, Dr, O.ray_weight(g, w.lines, w.n_rays), kap,
                          O.planck_rows(g, w.lines))
     ra, re = _rel(ag, a), _rel(eg, e)
-    print(f"adaptive tallies: absorbed max {ra.max():.3e}, emitted max {re.max():.3e}", flush=True)
+    print(f"adaptive tallies (wings {wings}): absorbed max {ra.max():.3e}, emitted max {re.max():.3e}", flush=True)
     assert ra.max() <= REL and re.max() <= REL
     t.close()
 
@@ -138,9 +140,13 @@ def test_adaptive_error_paths(rt):
     w = I.small_ragged()
     t = rt.Tracer(0)
     t.setup_workload(w)
+    for mode in (rt.KAPPA_ADAPTIVE, rt.KAPPA_ADAPTIVE_WINGS):
+        with pytest.raises(rt.RtError) as e:
+            t.compute_kappa(mode)
+        assert e.value.status == rt.RT_ESTATE
     with pytest.raises(rt.RtError) as e:
-        t.compute_kappa(rt.KAPPA_ADAPTIVE)
-    assert e.value.status == rt.RT_ESTATE
+        t.compute_kappa(6)
+    assert e.value.status == rt.RT_EINVAL
     for bad in (0.0, -1e-3, 1.0, float("nan"), float("inf")):
         with pytest.raises(rt.RtError) as e:
             t.set_line_tolerance(bad)
@@ -150,9 +156,10 @@ def test_adaptive_error_paths(rt):
     t = rt.Tracer(0)
     t.setup_workload(w2)
     t.set_line_tolerance(1e-4)
-    with pytest.raises(rt.RtError) as e:
-        t.compute_kappa(rt.KAPPA_ADAPTIVE)
-    assert e.value.status == rt.RT_EUNSUPPORTED
+    for mode in (rt.KAPPA_ADAPTIVE, rt.KAPPA_ADAPTIVE_WINGS):
+        with pytest.raises(rt.RtError) as e:
+            t.compute_kappa(mode)
+        assert e.value.status == rt.RT_EUNSUPPORTED
     t.close()
 
 
@@ -192,4 +199,59 @@ def test_adaptive_without_energies_and_zero_strengths(rt, O):
     t.reset_tally()
     t.compute_kappa(rt.KAPPA_PLAIN)
     assert kept == t.stats()["line_evals"] == O.adaptive_evals(w.grid, Z, 1e-3)
+    t.close()
+
+
+@pytest.mark.parametrize("wl", ["small_ragged", "plain_8cube"])
+@pytest.mark.parametrize("eps", [1e-2, 1e-3, 1e-5])
+def test_wing_return_matches_oracle(rt, O, wl, eps):
+    w = getattr(I, wl)()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    t.set_line_tolerance(eps)
+    print(f"wing return {wl} eps {eps:g}", flush=True)
+    t.reset_tally()
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE_WINGS)
+    n_nu = w.lines.n_nu
+    kg = kap.cpu().numpy().astype(np.float64)
+    assert (kg[:, n_nu:] == 0).all()
+    r = _rel(kg[:, :n_nu], O.kappa_adaptive(w.grid, w.lines, eps, wings=True))
+    kept = t.stats()["line_evals"]
+    print(f"  rel err max {r.max():.3e} median {np.median(r):.3e}", flush=True)
+    assert r.max() <= REL
+    # the same windows and kept evaluations as the adaptive mode
+    assert kept == O.adaptive_evals(w.grid, w.lines, eps)
+    t.close()
+
+
+def test_wing_return_vanishing_tolerance_is_the_plain_sum(rt, O):
+    w = I.small_ragged()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    t.set_line_tolerance(1e-300)
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE_WINGS)
+    kg = kap.cpu().numpy().astype(np.float64)[:, :w.lines.n_nu]
+    assert _rel(kg, O.kappa(w.grid, w.lines)).max() <= REL
+    t.close()
+
+
+def test_wing_return_full_size_32cube_sampled_runs(rt, O):
+    """The 32^3 workload (20,000 lines, 50,000 points) with the wing return
+    at eps = 1e-3, in the launch configuration the benchmark times: three
+    runs of 8 cells (the coldest, the hottest and one more) against the
+    oracle row by row."""
+    w = I.plain_32cube()
+    eps = 1e-3
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    t.set_line_tolerance(eps)
+    print("wing return 32^3 kappa", flush=True)
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE_WINGS)
+    g = w.grid
+    runs = sorted({int(np.argmin(g.T)) // 8, int(np.argmax(g.T)) // 8, 2901})
+    cells = np.array([8 * r + k for r in runs for k in range(8)], np.int32)
+    kg = kap[cells.tolist()].cpu().numpy().astype(np.float64)[:, :w.lines.n_nu]
+    r = _rel(kg, O.kappa_adaptive(g, w.lines, eps, cells, wings=True))
+    print(f"  sampled rows: rel err max {r.max():.3e}", flush=True)
+    assert r.max() <= REL
     t.close()
