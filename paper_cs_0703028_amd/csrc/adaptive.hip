@@ -47,6 +47,9 @@ static_assert(kLineTile <= 256, "staged line indices are kept in bytes");
 constexpr int kAdThreads = 256;
 constexpr int kCellF = 8;  // floats per cell in the screening's cell record
 constexpr int kAdRec = kLineRec;  // floats per staged line
+// passes per wavefront of the windowed sum: two of 64 points (32^3 workload:
+// 20.3 against 22.5 ms at eps = 1e-3, 71.0 against 70.1 ms at 1e-6)
+constexpr int kAdPasses = 2;
 
 // Eq. (1) strength ratio in binary64: q exp(-c2 E/T) / exp(-c2 E/T_ref)
 // * expm1(-c2 nu/T) / expm1(-c2 nu/T_ref), taken as
@@ -386,14 +389,22 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_window_scan_kernel(Window
 
 // One block: points [j0, j0 + 512) of the run of 8 cells `run`, as the plain
 // line-sum tile (dev::kappa_tile) with a window per (run, line): the staged
-// line records (dev::kLineRec) carry the run's window offsets lo, hi.
-__global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile a,
+// line records (dev::kLineRec) carry the run's window offsets lo, hi.  Each
+// wavefront owns 128 points and sums them in NQ passes of 128 / NQ: a pass
+// lists only the staged lines whose window meets its points, so a narrow
+// window costs the points of the passes it meets rather than all 128.
+template <int NQ>
+__global__ __launch_bounds__(kKappaThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void kappa_adaptive_kernel(KappaTile a,
                                                                        const uint32_t* __restrict__ win,
                                                                        int n_tiles,
                                                                        const double* __restrict__ wing) {
-  constexpr int C = kKappaCells, P = kKappaPoints;
+  constexpr int C = kKappaCells, P = kKappaPoints / NQ;
+  static_assert(P * NQ == kKappaPoints, "passes split the lane's points evenly");
   __shared__ float4 lds4[kLineTile * kAdRec / 4];
   __shared__ uint8_t lists[kKappaThreads / 64][kLineTile];
+  __shared__ int sel[kLineTile];
+  __shared__ int wkeep[kKappaThreads / 64];
+  static_assert(kLineTile == kKappaThreads, "one candidate line per thread");
   float* lds = reinterpret_cast<float*>(lds4);
   const int tile = blockIdx.x % n_tiles;
   const int64_t run = blockIdx.x / n_tiles;
@@ -402,28 +413,55 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
-  const int span = 64 * P;
-  const int wj0 = j0 + wave * span;
+  const int span = 64 * P;  // points of one pass
+  const int wj0 = j0 + wave * 64 * kKappaPoints;
   const int nl = a.L.n;
   const int blk_first = first_ge(a.L.whi, nl, j0);
   const int blk_end = first_gt(a.L.wlo, nl, j0 + kKappaTilePoints - 1);
   const uint32_t* wrow = win + run * (int64_t)nl;
 
-  float jf[P];
+  float jf[NQ][P];
 #pragma unroll
-  for (int p = 0; p < P; ++p) jf[p] = (float)(wj0 + 64 * p + lane);
-  float acc[P][C];
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
-  for (int p = 0; p < P; ++p)
+    for (int p = 0; p < P; ++p) jf[q][p] = (float)(wj0 + q * span + 64 * p + lane);
+  float acc[NQ][P][C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[p][c] = 0.f;
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[q][p][c] = 0.f;
 
   for (int base = blk_first; base < blk_end; base += kLineTile) {
-    const int nt = min(kLineTile, blk_end - base);
+    // the candidates base .. base + 255 (hard window meets the block) whose
+    // kept window meets the block's points, compacted in order: only they
+    // are staged, so a narrow window costs no amplitude evaluations in the
+    // blocks it misses
+    const int nc = min(kLineTile, blk_end - base);
+    bool keep = false;
+    if (tid < nc) {
+      const uint32_t w = wrow[base + tid];
+      const int lo = (int16_t)(uint16_t)(w & 0xffffu), hi = (int16_t)(uint16_t)(w >> 16);
+      const int m = a.L.m[base + tid];
+      keep = lo <= hi && m + lo <= j0 + kKappaTilePoints - 1 && m + hi >= j0;
+    }
+    const uint64_t bk = __ballot(keep);
+    __syncthreads();  // the previous tile's records, lists and selection read
+    if (lane == 0) wkeep[wave] = __popcll(bk);
     __syncthreads();
+    int off = 0, nt = 0;
+#pragma unroll
+    for (int v = 0; v < kKappaThreads / 64; ++v) {
+      off += v < wave ? wkeep[v] : 0;
+      nt += wkeep[v];
+    }
+    if (keep) sel[off + lanes_below(bk)] = base + tid;
+    __syncthreads();
+    if (nt == 0) continue;
     for (int q = tid; q < nt * C; q += kKappaThreads) {
       const int li = q / C, cc = q % C;
-      const int i = base + li;
+      const int i = sel[li];
       int64_t cell = cell0 + cc;
       if (cell >= a.n_cells) cell = a.n_cells - 1;
       float* rec = lds + li * kAdRec;
@@ -436,30 +474,35 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile
       }
       line_cell_params(a.L, a.C, i, cell, a.have_E, rec[4 + 2 * cc], rec[5 + 2 * cc]);
     }
-    __syncthreads();
-    // this wavefront's lines: those whose window meets [wj0, wj0 + span);
-    // indices of lines covering all of it from the front of the list, the
-    // others from the back
-    int nf = 0, np = 0;
-    for (int l0 = 0; l0 < nt; l0 += 64) {
-      const int l = l0 + lane;
-      bool meet = false, full = false;
-      if (l < nt) {
-        const float4 h = *reinterpret_cast<const float4*>(lds + l * kAdRec);
-        const int m = (int)h.x, w0 = m + (int)h.z, w1 = m + (int)h.w;
-        meet = w0 <= w1 && w0 <= wj0 + span - 1 && w1 >= wj0;
-        full = meet && w0 <= wj0 && w1 >= wj0 + span - 1;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int s0 = wj0 + q * span;
+      __syncthreads();  // records staged; the previous pass's list read
+      // this pass's lines: those whose window meets [s0, s0 + span); indices
+      // of lines covering all of it from the front of the list, the others
+      // from the back
+      int nf = 0, np = 0;
+      for (int l0 = 0; l0 < nt; l0 += 64) {
+        const int l = l0 + lane;
+        bool meet = false, full = false;
+        if (l < nt) {
+          const float4 h = *reinterpret_cast<const float4*>(lds + l * kAdRec);
+          const int m = (int)h.x, w0 = m + (int)h.z, w1 = m + (int)h.w;
+          meet = w0 <= w1 && w0 <= s0 + span - 1 && w1 >= s0;
+          full = meet && w0 <= s0 && w1 >= s0 + span - 1;
+        }
+        const uint64_t bf = __ballot(full), bp = __ballot(meet && !full);
+        if (full) lists[wave][nf + lanes_below(bf)] = (uint8_t)l;
+        if (meet && !full) lists[wave][kLineTile - 1 - (np + lanes_below(bp))] = (uint8_t)l;
+        nf += __popcll(bf);
+        np += __popcll(bp);
       }
-      const uint64_t bf = __ballot(full), bp = __ballot(meet && !full);
-      if (full) lists[wave][nf + lanes_below(bf)] = (uint8_t)l;
-      if (meet && !full) lists[wave][kLineTile - 1 - (np + lanes_below(bp))] = (uint8_t)l;
-      nf += __popcll(bf);
-      np += __popcll(bp);
+      __syncthreads();
+      for (int e = 0; e < nf; ++e)
+        add_line_terms<true, P>(lds + lists[wave][e] * kAdRec, jf[q], acc[q]);
+      for (int e = 0; e < np; ++e)
+        add_line_terms<false, P>(lds + lists[wave][kLineTile - 1 - e] * kAdRec, jf[q], acc[q]);
     }
-    __syncthreads();
-    for (int e = 0; e < nf; ++e) add_line_terms<true, P>(lds + lists[wave][e] * kAdRec, jf, acc);
-    for (int e = 0; e < np; ++e)
-      add_line_terms<false, P>(lds + lists[wave][kLineTile - 1 - e] * kAdRec, jf, acc);
   }
 
 #pragma unroll
@@ -468,13 +511,14 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_adaptive_kernel(KappaTile
     if (cell >= a.n_cells) break;
     const float add = wing ? (float)wing[cell] : 0.f;
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int64_t j = wj0 + 64 * p + lane;
-      if (j < a.ld_out) a.out[cell * a.ld_out + j] = (j < a.n_nu) ? acc[p][c] + add : 0.f;
-    }
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int64_t j = wj0 + q * span + 64 * p + lane;
+        if (j < a.ld_out) a.out[cell * a.ld_out + j] = (j < a.n_nu) ? acc[q][p][c] + add : 0.f;
+      }
   }
 }
-
 
 // atan(x1 + d) - atan(x1), d > 0: when both ends have one sign, as
 // atan(d / (1 + x1 (x1 + d))), which keeps the relative accuracy of a narrow
@@ -627,8 +671,8 @@ static hipError_t launch_adaptive(rt_ctx c, bool wings) {
   t.ld_out = c->ld;
   t.col0 = 0;
   t.col_end = c->ld;
-  hipLaunchKernelGGL(kappa_adaptive_kernel, dim3((unsigned)blocks), dim3(kKappaThreads), 0, c->stream, t,
-                     c->d_win, n_tiles, wing);
+  hipLaunchKernelGGL(kappa_adaptive_kernel<kAdPasses>, dim3((unsigned)blocks), dim3(kKappaThreads), 0,
+                     c->stream, t, c->d_win, n_tiles, wing);
   return hipGetLastError();
 }
 
