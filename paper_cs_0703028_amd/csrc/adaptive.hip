@@ -523,10 +523,11 @@ __global__ __launch_bounds__(kKappaThreads) __attribute__((amdgpu_waves_per_eu(6
 // atan(x1 + d) - atan(x1), d > 0: when both ends have one sign, as
 // atan(d / (1 + x1 (x1 + d))), which keeps the relative accuracy of a narrow
 // span far out in a wing (two arctangents near +-pi/2 would cancel); across
-// the centre the two arctangents have opposite signs and simply add.
+// the centre the two arctangents have opposite signs and simply add.  The
+// quotient takes the hardware reciprocal (within 1 ulp).
 __device__ inline float atan_span(float x1, float d) {
   const float x2 = x1 + d;
-  if (x1 >= 0.f || x2 <= 0.f) return atanf(d / fmaf(x1, x2, 1.f));
+  if (x1 >= 0.f || x2 <= 0.f) return atanf(d * __builtin_amdgcn_rcpf(fmaf(x1, x2, 1.f)));
   return atanf(x2) - atanf(x1);
 }
 
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_wing_kernel(LineSet L, Ce
       const int64_t cell = cell0 + c < n_cells ? cell0 + c : n_cells - 1;
       float amp, g2;
       line_cell_params(L, C, i, cell, have_E, amp, g2);
-      const float ig = 1.0f / sqrtf(g2);
+      const float ig = __builtin_amdgcn_rsqf(g2);  // 1 / g, within 1 ulp
       float span = 0.f;
       if (r0) span += atan_span(e0 * ig, n0 * ig);
       if (r1) span += atan_span(e1 * ig, n1 * ig);
