@@ -76,7 +76,7 @@ def line_peak_evals_per_s():
     return LANE_SLOTS_PER_S / LINE_SLOTS_PER_EVAL
 
 
-def cpu_baseline(w, n_cells_sample=32, n_rays_sample=96, n_cells_one=4):
+def cpu_baseline(w, n_cells_sample=256, n_rays_sample=768, n_cells_one=16):
     """Time the FP64 oracle on a bounded sample of the same workload and
     extrapolate linearly to the full step, on all host threads and on one.
     All threads: kappa and Planck rows of sampled cells (OpenMP over cells)
