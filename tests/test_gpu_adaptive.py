@@ -163,10 +163,13 @@ def test_adaptive_error_paths(rt):
     t.close()
 
 
-def test_adaptive_without_energies_and_zero_strengths(rt, O):
+@pytest.mark.parametrize("wings", [False, True])
+def test_adaptive_without_energies_and_zero_strengths(rt, O, wings):
     """The branches a line list without lower-state energies takes (strength
     ratio 1), lines of zero strength (no point kept anywhere), and a list of
-    zero strengths only (sbar = 0: the plain window, and kappa 0)."""
+    zero strengths only (sbar = 0: the plain window, and kappa 0), in both
+    adaptive modes."""
+    mode = rt.KAPPA_ADAPTIVE_WINGS if wings else rt.KAPPA_ADAPTIVE
     w = I.small_ragged()
     L = replace(w.lines, E_lower=None)
     S = L.S.copy()
@@ -178,11 +181,12 @@ def test_adaptive_without_energies_and_zero_strengths(rt, O):
         t.setup_lines(L)
         t.set_line_tolerance(eps)
         t.reset_tally()
-        kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE)
+        kap, _ = t.compute_kappa(mode)
         kept = t.stats()["line_evals"]
-        r = _rel(kap.cpu().numpy().astype(np.float64)[:, :L.n_nu], O.kappa_adaptive(w.grid, L, eps))
+        r = _rel(kap.cpu().numpy().astype(np.float64)[:, :L.n_nu],
+                 O.kappa_adaptive(w.grid, L, eps, wings=wings))
         want = O.adaptive_evals(w.grid, L, eps)
-        print(f"no energies, eps {eps:g}: rel err max {r.max():.3e}; kept {kept:.0f} (oracle {want})",
+        print(f"no energies (wings {wings}), eps {eps:g}: rel err max {r.max():.3e}; kept {kept:.0f} (oracle {want})",
               flush=True)
         assert r.max() <= REL
         assert kept == want
@@ -193,7 +197,7 @@ def test_adaptive_without_energies_and_zero_strengths(rt, O):
     t.setup_lines(Z)
     t.set_line_tolerance(1e-3)
     t.reset_tally()
-    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE)
+    kap, _ = t.compute_kappa(mode)
     kept = t.stats()["line_evals"]
     assert (kap.cpu().numpy() == 0).all()
     t.reset_tally()
@@ -221,6 +225,10 @@ def test_wing_return_matches_oracle(rt, O, wl, eps):
     assert r.max() <= REL
     # the same windows and kept evaluations as the adaptive mode
     assert kept == O.adaptive_evals(w.grid, w.lines, eps)
+    # a second call gives the same table bit for bit (the constants are
+    # reduced in a fixed order)
+    kap2, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE_WINGS, kappa=kap)
+    assert np.array_equal(kap2.cpu().numpy(), kg.astype(np.float32))
     t.close()
 
 
