@@ -168,19 +168,42 @@ struct CellF {
   bool zero;
 };
 
-__device__ inline bool window_bounds(const WindowArgs& a, int i, const CellF& cf, float& lo, float& hi) {
+// One line's data for the screening, loaded once per thread and kept in
+// registers over the runs it screens.
+struct LineF {
+  float S, E2, nu, nexp, gamma;
+  double r;
+  int wlo, whi, m;
+};
+
+__device__ inline LineF load_line(const WindowArgs& a, int i) {
+  LineF ln;
+  ln.S = a.L.S[i];
+  ln.E2 = a.have_E ? (float)a.L.E2[i] : 0.f;
+  ln.nu = a.have_E ? (float)a.L.nu[i] : 0.f;
+  ln.nexp = a.L.nexp[i];
+  ln.gamma = a.L.gamma[i];
+  ln.r = a.L.r64[i];
+  ln.wlo = a.L.wlo[i];
+  ln.whi = a.L.whi[i];
+  ln.m = a.L.m[i];
+  return ln;
+}
+
+__device__ inline bool window_bounds(const WindowArgs& a, const LineF& ln, const CellF& cf, float& lo,
+                                     float& hi) {
   if (cf.zero) {
     lo = hi = (float)a.K;
     return true;
   }
-  const float S = a.L.S[i];
+  const float S = ln.S;
   if (!(S == 0.f || S >= 1.2e-38f)) return false;       // normal or zero
   const float t = S * cf.inv_den;
   if (!(t < 1e30f)) return false;
   float s = 1.f, eb = 0.f;
   if (a.have_E) {
-    const float yb = (float)a.L.E2[i] * cf.beta;        // c2 E (1/T_ref - 1/T)
-    const float ys = (float)a.L.nu[i] * cf.theta;       // c2 nu / T
+    const float yb = ln.E2 * cf.beta;                   // c2 E (1/T_ref - 1/T)
+    const float ys = ln.nu * cf.theta;                  // c2 nu / T
     if (!(fabsf(yb) < 80.f) || !(ys < 80.f)) return false;
     const float boltz = fast_exp2(yb * 1.44269504f);
     float stim;
@@ -197,9 +220,9 @@ __device__ inline bool window_bounds(const WindowArgs& a, int i, const CellF& cf
     s = cf.q * boltz * stim;
     eb = fabsf(yb);
   }
-  const float yg = a.L.nexp[i] * cf.lam2;                // n log2(T_ref / T)
+  const float yg = ln.nexp * cf.lam2;                    // n log2(T_ref / T)
   if (!(fabsf(yg) < 16.f)) return false;
-  const float gp = a.L.gamma[i] * cf.P * fast_exp2(yg);
+  const float gp = ln.gamma * cf.P * fast_exp2(yg);
   const float ratio = t * s * gp;
   const float g2 = gp * gp;
   const float W2 = ratio - g2;
@@ -233,9 +256,8 @@ __device__ inline bool kept_interval(double r, double hw, int wlo, int whi, int&
 }
 
 // Packs the window and returns the kept in-grid evaluations of the run.
-__device__ inline unsigned long long store_window(const WindowArgs& a, int64_t idx, int i,
+__device__ inline unsigned long long store_window(const WindowArgs& a, int64_t idx, int m,
                                                   bool any, int lo, int hi, int members) {
-  const int m = a.L.m[i];
   int lo_off = 1, hi_off = 0;  // empty
   unsigned long long kept = 0;
   if (any) {
@@ -284,6 +306,8 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_window_kernel(WindowArgs 
   if (threadIdx.x == 0) ucount = 0;
   __syncthreads();
   unsigned long long kept = 0;
+  LineF ln{};
+  if (i < nl) ln = load_line(a, i);
   auto flush = [&]() {
     __syncthreads();
     const unsigned n = ucount;
@@ -322,19 +346,17 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_window_kernel(WindowArgs 
       for (int k = 0; k < RT_ADAPTIVE_GROUP; ++k) {
         if (k < members) {
           float l = -1.f, h = -1.f;
-          ok = window_bounds(a, i, cf[k], l, h) && ok;
+          ok = window_bounds(a, ln, cf[k], l, h) && ok;
           wl = fmaxf(wl, l);
           wu = fmaxf(wu, h);
         }
       }
       const double K = (double)a.K;
-      const double r = a.L.r64[i];
-      const int wlo = a.L.wlo[i], whi = a.L.whi[i];
       int l0 = 0, h0 = 0, l1 = 0, h1 = 0;
-      const bool e0 = ok && kept_interval(r, fmin((double)wl, K), wlo, whi, l0, h0);
-      const bool e1 = ok && kept_interval(r, fmin((double)wu, K), wlo, whi, l1, h1);
+      const bool e0 = ok && kept_interval(ln.r, fmin((double)wl, K), ln.wlo, ln.whi, l0, h0);
+      const bool e1 = ok && kept_interval(ln.r, fmin((double)wu, K), ln.wlo, ln.whi, l1, h1);
       if (ok && e0 == e1 && (!e0 || (l0 == l1 && h0 == h1))) {
-        kept += store_window(a, idx, i, e0, l0, h0, members);
+        kept += store_window(a, idx, ln.m, e0, l0, h0, members);
       } else {
         a.win[idx] = kUndecided;
         ubuf[atomicAdd(&ucount, 1u)] = (unsigned long long)idx;  // < kUndBuf: flushed below
@@ -363,7 +385,7 @@ __device__ inline unsigned long long decide_exact(const WindowArgs& a, int64_t i
   const double hw = w < (double)a.K ? w : (double)a.K;
   int lo = 0, hi = 0;
   const bool any = kept_interval(a.L.r64[i], hw, a.L.wlo[i], a.L.whi[i], lo, hi);
-  return store_window(a, idx, i, any, lo, hi, members);
+  return store_window(a, idx, a.L.m[i], any, lo, hi, members);
 }
 
 // Binary64 pass over the listed undecided entries (grid-stride).
