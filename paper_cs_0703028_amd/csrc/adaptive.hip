@@ -50,6 +50,11 @@ constexpr int kAdRec = kLineRec;  // floats per staged line
 // passes per wavefront of the windowed sum: two of 64 points (32^3 workload:
 // 20.3 against 22.5 ms at eps = 1e-3, 71.0 against 70.1 ms at 1e-6)
 constexpr int kAdPasses = 2;
+// From this tolerance on, the windowed sum takes four passes of 32 points
+// with 4 cells per lane: windows of a few tens of points (32^3 workload:
+// 16.1 against 17.3 ms at eps = 1e-3, 11.7 against 12.7 at 1e-2 with the
+// wing return; equal at 1e-4; 51.8 against 49.2 at 1e-5).
+constexpr double kAdNarrowTol = 3e-4;
 
 // Eq. (1) strength ratio in binary64: q exp(-c2 E/T) / exp(-c2 E/T_ref)
 // * expm1(-c2 nu/T) / expm1(-c2 nu/T_ref), taken as
@@ -409,19 +414,55 @@ __global__ __launch_bounds__(kAdThreads) void adaptive_window_scan_kernel(Window
   add_block_count(kept, a.kept);
 }
 
+// Adds one staged line to P points x CPL cells of a lane: the cells
+// cg CPL .. cg CPL + CPL - 1 of the run (their amplitudes and squared half
+// widths sit at rec + 4 + 2 CPL cg).  As dev::add_line_terms otherwise.
+template <bool FULL, int P, int CPL>
+__device__ __forceinline__ void add_line_terms_cells(const float* rec, const float (&jf)[P], int cg,
+                                                     float (&part)[P][CPL]) {
+  const float4 h = *reinterpret_cast<const float4*>(rec);
+  float dv[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const float t = jf[p] - h.x;
+    const float d = t - h.y;
+    if (FULL) {
+      dv[p] = d;
+    } else {
+      const bool in = (t >= h.z) & (t <= h.w);
+      dv[p] = in ? d : __builtin_inff();
+    }
+  }
+  const float* ag = rec + 4 + 2 * CPL * cg;
+#pragma unroll
+  for (int c = 0; c < CPL; c += 2) {
+    const float4 v = *reinterpret_cast<const float4*>(ag + 2 * c);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      part[p][c] = fmaf(v.x, fast_rcp(fmaf(dv[p], dv[p], v.y)), part[p][c]);
+      part[p][c + 1] = fmaf(v.z, fast_rcp(fmaf(dv[p], dv[p], v.w)), part[p][c + 1]);
+    }
+  }
+}
+
 // One block: points [j0, j0 + 512) of the run of 8 cells `run`, as the plain
 // line-sum tile (dev::kappa_tile) with a window per (run, line): the staged
 // line records (dev::kLineRec) carry the run's window offsets lo, hi.  Each
-// wavefront owns 128 points and sums them in NQ passes of 128 / NQ: a pass
-// lists only the staged lines whose window meets its points, so a narrow
-// window costs the points of the passes it meets rather than all 128.
-template <int NQ>
+// wavefront owns 128 points and sums them in NQ passes: a pass lists only
+// the staged lines whose window meets its points, so a narrow window costs
+// the points of the passes it meets rather than all 128.  CPL = 8: a lane
+// takes one point of a 64-point row for all 8 cells; CPL = 4: a half
+// wavefront takes 32 points for 4 cells, which halves a pass's span for
+// windows of a few tens of points.
+template <int NQ, int CPL>
 __global__ __launch_bounds__(kKappaThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void kappa_adaptive_kernel(KappaTile a,
                                                                        const uint32_t* __restrict__ win,
                                                                        int n_tiles,
                                                                        const double* __restrict__ wing) {
-  constexpr int C = kKappaCells, P = kKappaPoints / NQ;
-  static_assert(P * NQ == kKappaPoints, "passes split the lane's points evenly");
+  constexpr int C = kKappaCells;
+  constexpr int ROW = 64 * CPL / C;                 // points of a row of lanes
+  constexpr int P = 64 * kKappaPoints / (ROW * NQ); // points per lane per pass
+  static_assert(C % CPL == 0 && P * ROW * NQ == 64 * kKappaPoints, "passes split the wave's points evenly");
   __shared__ float4 lds4[kLineTile * kAdRec / 4];
   __shared__ uint8_t lists[kKappaThreads / 64][kLineTile];
   __shared__ int sel[kLineTile];
@@ -435,7 +476,8 @@ __global__ __launch_bounds__(kKappaThreads) __attribute__((amdgpu_waves_per_eu(6
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
-  const int span = 64 * P;  // points of one pass
+  const int pt = lane % ROW, cg = lane / ROW;       // point in the row, cell group
+  const int span = ROW * P;                         // points of one pass
   const int wj0 = j0 + wave * 64 * kKappaPoints;
   const int nl = a.L.n;
   const int blk_first = first_ge(a.L.whi, nl, j0);
@@ -446,14 +488,14 @@ __global__ __launch_bounds__(kKappaThreads) __attribute__((amdgpu_waves_per_eu(6
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int p = 0; p < P; ++p) jf[q][p] = (float)(wj0 + q * span + 64 * p + lane);
-  float acc[NQ][P][C];
+    for (int p = 0; p < P; ++p) jf[q][p] = (float)(wj0 + q * span + ROW * p + pt);
+  float acc[NQ][P][CPL];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc[q][p][c] = 0.f;
+      for (int c = 0; c < CPL; ++c) acc[q][p][c] = 0.f;
 
   for (int base = blk_first; base < blk_end; base += kLineTile) {
     // the candidates base .. base + 255 (hard window meets the block) whose
@@ -520,23 +562,30 @@ __global__ __launch_bounds__(kKappaThreads) __attribute__((amdgpu_waves_per_eu(6
         np += __popcll(bp);
       }
       __syncthreads();
-      for (int e = 0; e < nf; ++e)
-        add_line_terms<true, P>(lds + lists[wave][e] * kAdRec, jf[q], acc[q]);
-      for (int e = 0; e < np; ++e)
-        add_line_terms<false, P>(lds + lists[wave][kLineTile - 1 - e] * kAdRec, jf[q], acc[q]);
+      if constexpr (CPL == C) {
+        for (int e = 0; e < nf; ++e) add_line_terms<true, P>(lds + lists[wave][e] * kAdRec, jf[q], acc[q]);
+        for (int e = 0; e < np; ++e)
+          add_line_terms<false, P>(lds + lists[wave][kLineTile - 1 - e] * kAdRec, jf[q], acc[q]);
+      } else {
+        for (int e = 0; e < nf; ++e)
+          add_line_terms_cells<true, P, CPL>(lds + lists[wave][e] * kAdRec, jf[q], cg, acc[q]);
+        for (int e = 0; e < np; ++e)
+          add_line_terms_cells<false, P, CPL>(lds + lists[wave][kLineTile - 1 - e] * kAdRec, jf[q], cg,
+                                              acc[q]);
+      }
     }
   }
 
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int64_t cell = cell0 + c;
+  for (int c = 0; c < CPL; ++c) {
+    const int64_t cell = cell0 + cg * CPL + c;
     if (cell >= a.n_cells) break;
     const float add = wing ? (float)wing[cell] : 0.f;
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const int64_t j = wj0 + q * span + 64 * p + lane;
+        const int64_t j = wj0 + q * span + ROW * p + pt;
         if (j < a.ld_out) a.out[cell * a.ld_out + j] = (j < a.n_nu) ? acc[q][p][c] + add : 0.f;
       }
   }
@@ -694,8 +743,12 @@ static hipError_t launch_adaptive(rt_ctx c, bool wings) {
   t.ld_out = c->ld;
   t.col0 = 0;
   t.col_end = c->ld;
-  hipLaunchKernelGGL(kappa_adaptive_kernel<kAdPasses>, dim3((unsigned)blocks), dim3(kKappaThreads), 0,
-                     c->stream, t, c->d_win, n_tiles, wing);
+  if (c->line_tol >= kAdNarrowTol)
+    hipLaunchKernelGGL((kappa_adaptive_kernel<4, 4>), dim3((unsigned)blocks), dim3(kKappaThreads), 0,
+                       c->stream, t, c->d_win, n_tiles, wing);
+  else
+    hipLaunchKernelGGL((kappa_adaptive_kernel<kAdPasses, kKappaCells>), dim3((unsigned)blocks),
+                       dim3(kKappaThreads), 0, c->stream, t, c->d_win, n_tiles, wing);
   return hipGetLastError();
 }
 
