@@ -13,10 +13,13 @@
 //                            binary64 (the screening lists them; the scan
 //                            takes any the list had no room for)
 //   kappa_adaptive_kernel  : the plain FP32 line sum of Eq. (2) over those
-//                            windows.  Each wavefront sums only the staged
-//                            lines whose window meets its 128 points, first
-//                            those covering all of them (no membership
-//                            test), then the rest
+//                            windows.  A block stages only the lines whose
+//                            kept window meets its 512 points; a wavefront
+//                            sums its 128 points in passes (two of 64, or
+//                            from eps = 3e-4 four of 32 with 4 cells per
+//                            lane), each over the staged lines whose window
+//                            meets it: first those covering all of its
+//                            points (no membership test), then the rest
 //   adaptive_wing_kernel   : (wing-return form, an extension) per cell, the
 //                            Lorentz mass of the points its run's windows
 //                            drop, priced by the midpoint rule and spread
