@@ -263,3 +263,21 @@ def test_wing_return_full_size_32cube_sampled_runs(rt, O):
     print(f"  sampled rows: rel err max {r.max():.3e}", flush=True)
     assert r.max() <= REL
     t.close()
+
+
+@pytest.mark.parametrize("wings", [False, True])
+def test_adaptive_empty_line_list(rt, wings):
+    # no lines at all: no windows to decide, nothing kept, nothing dropped,
+    # and a zero table in both modes
+    w = I.small_ragged()
+    L = replace(w.lines, nu=np.zeros(0), S=np.zeros(0), gamma=np.zeros(0), n_T=np.zeros(0),
+                E_lower=None)
+    t = rt.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(L)
+    t.set_line_tolerance(1e-3)
+    t.reset_tally()
+    kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE_WINGS if wings else rt.KAPPA_ADAPTIVE)
+    assert (kap.cpu().numpy() == 0).all()
+    assert t.stats()["line_evals"] == 0
+    t.close()
