@@ -10,8 +10,11 @@ namespace rt {
 // screening's 8-float cell record (4), then the wing-return constant (1).
 constexpr int kAdaptiveCellDoubles = 7;
 
-// The wing-return constants, one per cell, FP64, in cm^-1.
-inline double* adaptive_wing_constants(rt_ctx c) { return c->d_sbar + 6 * c->n_cells; }
+// The wing-return constants, one per cell, FP64, in cm^-1: the last of the
+// per-cell segments.
+inline double* adaptive_wing_constants(rt_ctx c) {
+  return c->d_sbar + (kAdaptiveCellDoubles - 1) * c->n_cells;
+}
 
 // RT_KAPPA_ADAPTIVE_WINGS: the adaptive windows, then per cell the
 // midpoint-rule mass of the dropped points spread over the band, added to
