@@ -243,17 +243,18 @@ def test_wing_return_vanishing_tolerance_is_the_plain_sum(rt, O):
     t.close()
 
 
-def test_wing_return_full_size_32cube_sampled_runs(rt, O):
+@pytest.mark.parametrize("eps", [1e-3, 1e-4])
+def test_wing_return_full_size_32cube_sampled_runs(rt, O, eps):
     """The 32^3 workload (20,000 lines, 50,000 points) with the wing return
-    at eps = 1e-3, in the launch configuration the benchmark times: three
-    runs of 8 cells (the coldest, the hottest and one more) against the
-    oracle row by row."""
+    in the launch configurations the benchmark times (eps = 1e-3: 32-point
+    passes with 4 cells per lane; 1e-4: 64-point passes with 8): three runs
+    of 8 cells (the coldest, the hottest and one more) against the oracle
+    row by row."""
     w = I.plain_32cube()
-    eps = 1e-3
     t = rt.Tracer(0)
     t.setup_workload(w)
     t.set_line_tolerance(eps)
-    print("wing return 32^3 kappa", flush=True)
+    print(f"wing return 32^3 kappa, eps {eps:g}", flush=True)
     kap, _ = t.compute_kappa(rt.KAPPA_ADAPTIVE_WINGS)
     g = w.grid
     runs = sorted({int(np.argmin(g.T)) // 8, int(np.argmax(g.T)) // 8, 2901})
