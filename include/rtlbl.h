@@ -86,13 +86,18 @@ typedef enum {
  * run c / RT_ADAPTIVE_GROUP of consecutive cells (x fastest). */
 #define RT_ADAPTIVE_GROUP 8
 
-/* Form of the march (Eq. (3)); per-cell accumulators are FP64 in both.
+/* Form of the march (Eq. (3)).  In both, the per-segment sums over a
+ * wavefront are formed in a fixed order and added to per-cell accumulators
+ * that are exact fixed-point integers (digits of 2^-112 W up to 2^80 W), so
+ * the tallies do not depend on the order in which the GPU delivers them: the
+ * same rays give the same tallies bit for bit, however they are split over
+ * calls.  Each added value is rounded to 29 significant bits first.
  *   RT_TALLY_F32: plain form.  Planck values evaluated in registers (FP32),
  *     1 - exp(-tau) from the hardware exponential with a degree-4 series
  *     below tau = 1/16, per-wavefront partial sums in FP32.
- *   RT_TALLY_F64: precision form.  Planck values read from the FP64-derived
- *     table of rt_compute_kappa (required), degree-5 series below tau = 1/4,
- *     partial sums in FP64. */
+ *   RT_TALLY_F64: precision form.  Planck values read from the table of
+ *     rt_compute_kappa (required), degree-5 series below tau = 1/4, partial
+ *     sums in FP64. */
 typedef enum {
   RT_TALLY_F32 = 0,
   RT_TALLY_F64 = 1
@@ -229,16 +234,22 @@ rt_status rt_trace_rays(rt_ctx ctx, uint64_t seed, uint64_t n_rays_total,
 /* Rays given explicitly in the fixed-point frame (one cell edge = 2^21
  * units): origin O[3*r..] on the boundary, inward integer direction
  * D[3*r..] (|D_k| <= 2^21), host arrays, n_rays >= 1, with the given
- * weight.  For closed-form checks (slabs, axis-normal rays).  If exit_I is
- * not NULL it is a host array of n_rays*n_nu doubles receiving the
- * radiance at exit.  Synchronises when exit_I is given. */
+ * weight (0 <= weight <= 2^40).  For closed-form checks (slabs, axis-normal
+ * rays).  If exit_I is not NULL it is a host array of n_rays*n_nu doubles
+ * receiving the radiance at exit.  Synchronises when exit_I is given. */
 rt_status rt_trace_explicit(rt_ctx ctx, int n_rays, const int64_t* O,
                             const int64_t* D, double weight, int tally_prec,
                             double* exit_I);
 
-/* Copies the tallies to the host (synchronises): absorbed_W[c] and
- * emitted_W[c] (host arrays of nx*ny*nz doubles, each may be NULL) and
- * balance[4] = {entering, emitted, absorbed, escaped} in W (may be NULL). */
+/* The power exchanged with each volume, summed over rays and wavenumbers
+ * (Section 3: the host receives the sum of I_in - I_out over the volumes, as
+ * absorbed minus emitted; both are returned).  Copies the tallies to the host
+ * (synchronises): absorbed_W[c] and emitted_W[c] (host arrays of nx*ny*nz
+ * doubles, each may be NULL) and balance[4] = {entering, emitted, absorbed,
+ * escaped} in W (may be NULL); emitted and absorbed in the balance are exact
+ * sums of the per-cell accumulators, converted once.  RT_EDEVICE if a traced
+ * power fell outside the accumulators' range (negative, not finite or not
+ * below 2^80 W). */
 rt_status rt_tally(rt_ctx ctx, double* absorbed_W, double* emitted_W,
                    double* balance);
 

@@ -187,7 +187,6 @@ rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream) {
   c->device = hip_device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   e = hipSetDevice(hip_device);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_slots), 2 * rt::kSlots * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_balance), 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_segcount), sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_adapt_evals), sizeof(unsigned long long));
@@ -210,7 +209,7 @@ rt_status rt_destroy(rt_ctx c) {
   free_cells(c);
   dev_free(c->d_T); dev_free(c->d_x); dev_free(c->d_p);
   dev_free(c->d_bwall);
-  dev_free(c->d_abs); dev_free(c->d_emi); dev_free(c->d_slots); dev_free(c->d_balance);
+  dev_free(c->d_abs); dev_free(c->d_emi); dev_free(c->d_acc); dev_free(c->d_balance);
   dev_free(c->d_segcount);
   dev_free(c->d_sbar); dev_free(c->d_win); dev_free(c->d_adapt_evals); dev_free(c->d_und);
   dev_free(c->d_segs); dev_free(c->d_counts); dev_free(c->d_rays_explicit); dev_free(c->d_exit);
@@ -247,7 +246,8 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   if (rt_status s = set_device(c)) return s;
   RT_HIP(c, hipStreamSynchronize(c->stream));
   dev_free(c->d_T); dev_free(c->d_x); dev_free(c->d_p);
-  dev_free(c->d_abs); dev_free(c->d_emi);
+  dev_free(c->d_abs); dev_free(c->d_emi); dev_free(c->d_acc);
+  c->d_ovf = nullptr;
   free_cells(c);
   free_gases(c);
   c->have_grid = false;
@@ -258,6 +258,9 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   RT_HIP(c, dev_alloc(&c->d_p, n));
   RT_HIP(c, dev_alloc(&c->d_abs, n));
   RT_HIP(c, dev_alloc(&c->d_emi, n));
+  // accumulator rows of the cells and the balance, then the overflow flag
+  RT_HIP(c, dev_alloc(&c->d_acc, (size_t)((n + rt::kBalRows) * rt::kAccRow + 1)));
+  c->d_ovf = reinterpret_cast<unsigned*>(c->d_acc + (n + rt::kBalRows) * rt::kAccRow);
   RT_HIP(c, dev_alloc(&c->cells.G, n));
   RT_HIP(c, dev_alloc(&c->cells.beta, n));
   RT_HIP(c, dev_alloc(&c->cells.theta, n));
@@ -628,8 +631,13 @@ static rt_status trace_batches(rt_ctx c, uint64_t seed, uint64_t begin, uint64_t
                                double weight, bool f64, bool explicit_rays, float* exit_dev) {
   if (rt_status s = ensure_batch(c, (int64_t)count)) return s;
   if (rt_status s = record_begin(c, c->trace_events)) return s;
-  for (uint64_t off = 0; off < count; off += (uint64_t)c->batch_rays) {
-    const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)c->batch_rays, count - off);
+  // A launch adds at most (rays x chunks) terms to one accumulator word
+  // (a ray crosses a cell once); the words are normalised after every launch.
+  const int64_t n_chunks = std::max<int64_t>(1, c->ld / rt::kChunk);
+  const int64_t per_launch =
+      std::max<int64_t>(1, std::min<int64_t>(c->batch_rays, rt::kAccMaxTerms / n_chunks));
+  for (uint64_t off = 0; off < count; off += (uint64_t)per_launch) {
+    const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)per_launch, count - off);
     if (explicit_rays && off > 0) return fail(c, RT_EINVAL, "explicit rays exceed one batch");
     const bool order = !explicit_rays && n >= rt::kOrderMinRays;
     if (order) RT_HIP(c, rt::launch_order(c, seed, begin + off, n));
@@ -668,7 +676,8 @@ rt_status rt_trace_explicit(rt_ctx c, int n_rays, const int64_t* O, const int64_
   if (!c) return fail(c, RT_EINVAL, "rt_trace_explicit: NULL handle");
   if (!c->have_kappa) return fail(c, RT_ESTATE, "rt_trace_explicit: call rt_compute_kappa first");
   if (n_rays < 1 || !O || !D) return fail(c, RT_EINVAL, "rt_trace_explicit: bad ray arrays");
-  if (!std::isfinite(weight)) return fail(c, RT_EINVAL, "rt_trace_explicit: weight not finite");
+  if (!(weight >= 0 && weight <= 0x1p40))
+    return fail(c, RT_EINVAL, "rt_trace_explicit: weight must be in [0, 2^40]");
   if (tally_prec != RT_TALLY_F32 && tally_prec != RT_TALLY_F64)
     return fail(c, RT_EINVAL, "rt_trace_explicit: unknown tally precision");
   if (tally_prec == RT_TALLY_F64 && !c->planck)
@@ -741,8 +750,12 @@ rt_status rt_tally(rt_ctx c, double* absorbed, double* emitted, double* balance)
   if (emitted)
     RT_HIP(c, hipMemcpyAsync(emitted, c->d_emi, c->n_cells * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   double bal[4];
+  unsigned ovf = 0;
   RT_HIP(c, hipMemcpyAsync(bal, c->d_balance, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  RT_HIP(c, hipMemcpyAsync(&ovf, c->d_ovf, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
   RT_HIP(c, hipStreamSynchronize(c->stream));
+  if (ovf)
+    return fail(c, RT_EDEVICE, "rt_tally: a tallied power was negative, not finite or not below 2^80 W");
   if (balance) std::memcpy(balance, bal, sizeof(bal));
   return RT_OK;
 }

@@ -107,6 +107,10 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
     b.n_cells = (int64_t)q.nx * q.ny * q.nz;
     b.cell_off = cell_off;
     b.n_rays = (int64_t)q.n_rays;
+    // one launch adds up to rays x spectral chunks terms to a case's
+    // accumulator words, which hold kAccMaxTerms until normalised
+    if ((double)q.n_rays * (double)((c->n_nu + kChunk - 1) / kChunk) > (double)kAccMaxTerms)
+      return bfail(c, RT_EINVAL, "rt_batch: n_rays x spectral chunks of a case must be <= 2^35");
     b.seg_off = seg_off;
     b.ray_off = ray_off;
     b.seed = q.seed;
@@ -187,7 +191,7 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   int64_t o_G = take(nc * 4), o_beta = take(nc * 8), o_theta = take(nc * 8), o_lam2 = take(nc * 4),
           o_P = take(nc * 4);
   int64_t o_abs = take(nc * 8), o_emi = take(nc * 8);
-  int64_t o_cs = take((int64_t)n_cases * 2 * kCaseSlots * 8), o_bal = take((int64_t)n_cases * 4 * 8);
+  int64_t o_acc = take(((nc + (int64_t)n_cases * kCaseBalRows) * kAccRow + 1) * 8), o_bal = take((int64_t)n_cases * 4 * 8);
   int64_t o_bw = take((int64_t)n_cases * pl.bwall_ld * 4);
   int64_t o_segs = take(seg_off * 8), o_cnt = take(ray_off * 4);
   int64_t o_keys = take(ray_off * 4), o_perm = take(ray_off * 4);
@@ -209,7 +213,7 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   pl.cells.P = reinterpret_cast<float*>(o_P);
   pl.d_abs = reinterpret_cast<double*>(o_abs);
   pl.d_emi = reinterpret_cast<double*>(o_emi);
-  pl.d_case_slots = reinterpret_cast<double*>(o_cs);
+  pl.d_acc = reinterpret_cast<unsigned long long*>(o_acc);
   pl.d_balance = reinterpret_cast<double*>(o_bal);
   pl.d_bwall = reinterpret_cast<float*>(o_bw);
   pl.d_segs = reinterpret_cast<int2*>(o_segs);
@@ -232,7 +236,7 @@ void carve(BatchPlan& pl, void* ws) {
   rebase(pl.d_T, b); rebase(pl.d_x, b); rebase(pl.d_p, b); rebase(pl.d_T_wall, b);
   rebase(pl.cells.G, b); rebase(pl.cells.beta, b); rebase(pl.cells.theta, b);
   rebase(pl.cells.lam2, b); rebase(pl.cells.P, b);
-  rebase(pl.d_abs, b); rebase(pl.d_emi, b); rebase(pl.d_case_slots, b); rebase(pl.d_balance, b);
+  rebase(pl.d_abs, b); rebase(pl.d_emi, b); rebase(pl.d_acc, b); rebase(pl.d_balance, b);
   rebase(pl.d_bwall, b); rebase(pl.d_segs, b); rebase(pl.d_counts, b); rebase(pl.d_slabs, b);
   rebase(pl.d_keys, b); rebase(pl.d_perm, b); rebase(pl.d_hist, b);
   rebase(pl.d_counters, b); rebase(pl.d_stages, b); rebase(pl.d_cases, b);
@@ -426,8 +430,12 @@ rt_status rt_batch_results(rt_ctx c, double* absorbed, double* emitted, double* 
   BatchPlan& pl = *c->batch;
   RT_BHIP(c, hipSetDevice(c->device));
   RT_BHIP(c, hipStreamSynchronize(c->stream));
-  unsigned err = 0;
+  unsigned err = 0, ovf = 0;
   RT_BHIP(c, hipMemcpy(&err, pl.d_counters + 2, sizeof(unsigned), hipMemcpyDeviceToHost));
+  RT_BHIP(c, hipMemcpy(&ovf, pl.d_acc + (pl.total_cells + (int64_t)pl.n_cases * kCaseBalRows) * kAccRow, sizeof(unsigned),
+                       hipMemcpyDeviceToHost));
+  if (ovf)
+    return bfail(c, RT_EDEVICE, "rt_batch_results: a tallied power was negative, not finite or not below 2^80 W");
   if (absorbed)
     RT_BHIP(c, hipMemcpy(absorbed, pl.d_abs, pl.total_cells * 8, hipMemcpyDeviceToHost));
   if (emitted)

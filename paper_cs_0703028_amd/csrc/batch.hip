@@ -49,9 +49,8 @@ struct BatchArgs {
   const uint32_t* perm;  // per case: slot -> ray index (coherent order)
   const float* bwall;  // [case][bwall_ld]
   int64_t bwall_ld;
-  double* acc_abs;
-  double* acc_emi;
-  double* case_slots;  // [case][2][kCaseSlots]
+  unsigned long long* acc;  // accumulator rows (see BatchPlan::d_acc)
+  unsigned* ovf;
   double nu0, dnu, c1;
   unsigned long long* queue;
   unsigned* rg_done;
@@ -88,7 +87,11 @@ template <bool QUAD>
 // (measured: 4.57 s at three, 4.33 s at four, 4.26 s at five for the 64-case
 // launch; six spills 62 and is not used).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_kernel(BatchArgs a) {
-  __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
+  // line-sum tiles stage line records here; march items stage their
+  // per-segment partial sums (4 wavefronts) in the same memory
+  constexpr int kLdsFloats = kLineTile * (4 + 2 * kKappaCells);
+  static_assert(kLdsFloats >= 4 * TallyStage<false>::kEntries, "march staging fits");
+  __shared__ float4 lds4[kLdsFloats / 4];
   __shared__ long long s_item;
   __shared__ int s_ok;
   float* lds = reinterpret_cast<float*>(lds4);
@@ -198,23 +201,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     w.dnu = a.dnu;
     w.c1 = a.c1;
     w.weight = cs.weight;
-    w.acc_abs = a.acc_abs + cs.cell_off;
-    w.acc_emi = a.acc_emi + cs.cell_off;
+    w.acc = a.acc;
+    w.row0 = cs.cell_off + (int64_t)st.cas * kCaseBalRows;
+    w.bal_row0 = w.row0 + cs.n_cells;
+    w.bal_mask = kCaseBalRows - 1;
+    w.ovf = a.ovf;
+    float* stage = lds + wave * TallyStage<false>::kEntries;
     const int64_t r0 = local * a.march_rays;
     const int64_t r1 = min(r0 + a.march_rays, cs.n_rays);
-    double* cslots = a.case_slots + (int64_t)st.cas * 2 * kCaseSlots;
     for (int64_t r = r0 + wave; r < r1; r += 4) {
       const int2* sg = a.segs + cs.seg_off + r * cs.max_segs;
       const int ns = a.counts[cs.ray_off + r];
       for (int sub = 0; sub < a.chunk_points / kChunk; ++sub) {
         const int64_t j = w.col0 + (int64_t)sub * kChunk + lane * kQ;
-        float te, tx;
-        march_wave<false, false, QUAD>(w, sg, ns, j, lane, nullptr, te, tx);
-        if (lane == 0) {
-          const int s = (int)(r % kCaseSlots);
-          unsafeAtomicAdd(cslots + s, w.weight * (double)te);
-          unsafeAtomicAdd(cslots + kCaseSlots + s, w.weight * (double)tx);
-        }
+        march_wave<false, false, QUAD>(w, sg, ns, j, lane, nullptr, stage, r);
       }
     }
     __syncthreads();
@@ -222,31 +222,68 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   }
 }
 
-// balance per case = {entering, sum emitted, sum absorbed, escaped}, FP64,
-// fixed order.
-__global__ __launch_bounds__(256) void case_tally_kernel(const BatchCase* cases,
-                                                         const double* __restrict__ abs_,
-                                                         const double* __restrict__ emi,
-                                                         const double* __restrict__ cslots,
-                                                         double* balance) {
-  __shared__ double red[4][256];
-  const BatchCase cs = cases[blockIdx.x];
+// Carries of every accumulator row (rows x 2 digit groups).
+__global__ void batch_acc_normalize_kernel(unsigned long long* acc, int64_t groups) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < groups) acc_normalize(acc + i * kAccDigits);
+}
+
+// The exact sum of accumulator rows [first, first + n): each digit is summed
+// over the rows as an integer (normalised digits are below 2^28 and there are
+// fewer than 2^31 rows), in a fixed-order tree over the block's 256 threads;
+// thread 0 gets the normalised digits in d.
+__device__ void case_rows_sum(const unsigned long long* __restrict__ acc, int64_t first,
+                              int64_t n, unsigned long long (*red)[256], unsigned long long* d) {
   const int t = threadIdx.x;
-  double sa = 0, se = 0, en = 0, ex = 0;
-  for (int64_t c = t; c < cs.n_cells; c += 256) {
-    sa += abs_[cs.cell_off + c];
-    se += emi[cs.cell_off + c];
-  }
-  const double* sl = cslots + (int64_t)blockIdx.x * 2 * kCaseSlots;
-  for (int s = t; s < kCaseSlots; s += 256) { en += sl[s]; ex += sl[kCaseSlots + s]; }
-  red[0][t] = en; red[1][t] = se; red[2][t] = sa; red[3][t] = ex;
+  unsigned long long s[kAccRow];
+#pragma unroll
+  for (int k = 0; k < kAccRow; ++k) s[k] = 0;
+  for (int64_t r = first + t; r < first + n; r += 256)
+#pragma unroll
+    for (int k = 0; k < kAccRow; ++k) s[k] += acc[r * kAccRow + k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kAccRow; ++k) red[k][t] = s[k];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (t < off)
-      for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + off];
+#pragma unroll
+      for (int k = 0; k < kAccRow; ++k) red[k][t] += red[k][t + off];
     __syncthreads();
   }
-  if (t < 4) balance[4 * blockIdx.x + t] = red[t][0];
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < kAccRow; ++k) d[k] = red[k][0];
+    acc_normalize(d);
+    acc_normalize(d + kAccDigits);
+  }
+}
+
+// Per-cell powers of every case from its accumulator rows; one block per
+// case then forms its balance = {entering, sum emitted, sum absorbed,
+// escaped} from exact integer sums of its rows.
+__global__ __launch_bounds__(256) void case_tally_kernel(const BatchCase* cases,
+                                                         const unsigned long long* __restrict__ acc,
+                                                         double* abs_, double* emi,
+                                                         double* balance) {
+  __shared__ unsigned long long red[kAccRow][256];
+  const BatchCase cs = cases[blockIdx.x];
+  const int64_t row0 = cs.cell_off + (int64_t)blockIdx.x * kCaseBalRows;
+  for (int64_t c = threadIdx.x; c < cs.n_cells; c += 256) {
+    const unsigned long long* r = acc + (row0 + c) * kAccRow;
+    abs_[cs.cell_off + c] = acc_value(r);
+    emi[cs.cell_off + c] = acc_value(r + kAccDigits);
+  }
+  unsigned long long cells[kAccRow], bal[kAccRow];
+  case_rows_sum(acc, row0, cs.n_cells, red, cells);
+  case_rows_sum(acc, row0 + cs.n_cells, kCaseBalRows, red, bal);
+  if (threadIdx.x == 0) {
+    double* b = balance + 4 * blockIdx.x;
+    b[0] = acc_value(bal);
+    b[1] = acc_value(cells + kAccDigits);
+    b[2] = acc_value(cells);
+    b[3] = acc_value(bal + kAccDigits);
+  }
 }
 
 // Coherent ray order per case (see order_key): counting sort of every
@@ -360,9 +397,8 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
                      pl.d_hist);
   hipLaunchKernelGGL(batch_order_scatter_kernel, dim3(ray_blocks), dim3(256), 0, s, pl.d_cases,
                      pl.n_cases, pl.total_rays, pl.d_keys, pl.d_hist, pl.d_perm);
-  fill_d(pl.d_abs, pl.total_cells);
-  fill_d(pl.d_emi, pl.total_cells);
-  fill_d(pl.d_case_slots, (int64_t)pl.n_cases * 2 * kCaseSlots);
+  const int64_t acc_words = (pl.total_cells + (int64_t)pl.n_cases * kCaseBalRows) * kAccRow;
+  fill_d(reinterpret_cast<double*>(pl.d_acc), acc_words + 1);  // + overflow flag
   BatchArgs a;
   a.stages = pl.d_stages;
   a.n_stages = pl.n_stages;
@@ -386,9 +422,8 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
   a.perm = pl.d_perm;
   a.bwall = pl.d_bwall;
   a.bwall_ld = pl.bwall_ld;
-  a.acc_abs = pl.d_abs;
-  a.acc_emi = pl.d_emi;
-  a.case_slots = pl.d_case_slots;
+  a.acc = pl.d_acc;
+  a.ovf = reinterpret_cast<unsigned*>(pl.d_acc + acc_words);
   a.nu0 = c->nu0;
   a.dnu = c->dnu;
   a.c1 = first_radiation_wavenumber();
@@ -402,8 +437,11 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
     hipLaunchKernelGGL(batch_kernel<true>, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(batch_kernel<false>, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
+  const int64_t groups = acc_words / kAccDigits;
+  hipLaunchKernelGGL(batch_acc_normalize_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256),
+                     0, s, pl.d_acc, groups);
   hipLaunchKernelGGL(case_tally_kernel, dim3((unsigned)pl.n_cases), dim3(256), 0, s, pl.d_cases,
-                     pl.d_abs, pl.d_emi, pl.d_case_slots, pl.d_balance);
+                     pl.d_acc, pl.d_abs, pl.d_emi, pl.d_balance);
   return hipGetLastError();
 }
 

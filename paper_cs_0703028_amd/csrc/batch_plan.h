@@ -6,7 +6,8 @@
 namespace rt {
 
 constexpr int kStageRaygen = 0, kStageKappa = 1, kStageMarch = 2;
-constexpr int kCaseSlots = 64;  // entering/escaped partial-sum slots per case
+// balance rows (entering, escaped) per case; a case's rays spread over them
+constexpr int kCaseBalRows = 64;
 
 // One contiguous range of queue items of one kind.
 struct BatchStage {
@@ -44,7 +45,11 @@ struct BatchPlan {
   // device pointers into the caller's workspace
   double *d_T = nullptr, *d_x = nullptr, *d_p = nullptr, *d_T_wall = nullptr;
   CellSet cells;
-  double *d_abs = nullptr, *d_emi = nullptr, *d_case_slots = nullptr, *d_balance = nullptr;
+  // fixed-point accumulator rows: case k's cells from cell_off + k kCaseBalRows,
+  // then its kCaseBalRows balance rows (entering, escaped); the overflow flag
+  // after the last row
+  unsigned long long* d_acc = nullptr;
+  double *d_abs = nullptr, *d_emi = nullptr, *d_balance = nullptr;
   float* d_bwall = nullptr;
   int2* d_segs = nullptr;
   int32_t* d_counts = nullptr;

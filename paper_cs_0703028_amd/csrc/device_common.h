@@ -457,36 +457,6 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return *reinterpret_cast<double*>(&r);
 }
 
-// Sum over the 64 lanes: butterflies inside each row of 16 (quad
-// permutations, half-row and row mirrors) leave every lane of row k with the
-// row total r_k.  Row broadcasts then combine the rows, with all rows
-// enabled so that each step is a single DPP add: after row_bcast:15 row 1
-// holds r0 + r1 and row 3 holds r2 + r3 (row 0 takes no source lane and
-// receives 0); after row_bcast:31 row 3 holds r0 + r1 + r2 + r3.  Only
-// lane 63 is read, so what rows 0-2 end with does not matter.
-__device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f32<0x141>(v);  // row_half_mirror
-  v += dpp_f32<0x140>(v);  // row_mirror
-  v += dpp_f32<0x142>(v);  // row_bcast:15
-  v += dpp_f32<0x143>(v);  // row_bcast:31
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64<0xB1>(v);
-  v += dpp_f64<0x4E>(v);
-  v += dpp_f64<0x141>(v);
-  v += dpp_f64<0x140>(v);
-  v += dpp_f64<0x142>(v);
-  v += dpp_f64<0x143>(v);
-  int2 h = *reinterpret_cast<int2*>(&v);
-  int2 r;
-  r.x = __builtin_amdgcn_readlane(h.x, 63);
-  r.y = __builtin_amdgcn_readlane(h.y, 63);
-  return *reinterpret_cast<double*>(&r);
-}
-
 // a = 1 - e^{-tau} for tau >= 0, two accuracy levels.
 //   precision form: degree-5 Taylor polynomial of (1 - e^{-tau})/tau below
 //     tau = 1/4 (truncation < 5e-8), 1 - 2^{-tau log2 e} above (<= 5e-7);
@@ -511,21 +481,91 @@ struct Partial { using T = float; };
 template <>
 struct Partial<true> { using T = double; };
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_pt(float v) { return dpp_f32<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double dpp_pt(double v) { return dpp_f64<CTRL>(v); }
+
+// ------------------------------------------------------ fixed-point tallies
+// The absorbed and emitted power of every cell, and the entering and escaped
+// power of the balance, are kept as exact integers: kAccDigits digits of
+// kAccBits bits, digit k worth 2^(kAccBits k + kAccLsb) W, each held in a
+// 64-bit word whose upper bits take the carries of up to 2^35 additions
+// until the words are normalised (after every launch).  A value is rounded to
+// kAccSig significant bits (relative error below 2^-kAccSig), which then
+// span at most two digits, and added with integer atomics; integer additions
+// commute, so every tally comes out the same bit for bit whatever order the
+// wavefronts deliver their sums in.  Values below 2^kAccLsb W are dropped
+// (truncation, the same in every order); a value that is NaN, negative or
+// not below 2^80 W sets the overflow flag instead.
+constexpr int kAccSig = kAccBits + 1;
+static_assert(kAccSig + kAccBits - 1 <= 2 * kAccBits, "a rounded value spans two digits");
+static_assert((80 - kAccSig - kAccLsb) / kAccBits + 1 <= kAccDigits - 1, "values below 2^80 W fit");
+constexpr unsigned long long kAccMask = (1ull << kAccBits) - 1;
+
+__device__ __forceinline__ void acc_add(unsigned long long* d, double v, unsigned* ovf) {
+  if (!(v >= 0.0 && v < 0x1p80)) {
+    atomicOr(ovf, 1u);
+    return;
+  }
+  if (v == 0.0) return;
+  int e;
+  const double mant = frexp(v, &e);  // v = mant 2^e, 1/2 <= mant < 1, e <= 80
+  unsigned long long m = (unsigned long long)rint(ldexp(mant, kAccSig));
+  if (m >> kAccSig) {                // rounded up to 2^kAccSig
+    m >>= 1;
+    ++e;
+  }
+  int p = e - kAccSig - kAccLsb;     // accumulator bit of m's lowest bit
+  if (p < 0) {
+    if (p <= -kAccSig) return;       // wholly below the lowest digit
+    m >>= -p;
+    p = 0;
+  }
+  const int k = p / kAccBits, s = p % kAccBits;
+  const unsigned long long w = m << s;  // below 2^(2 kAccBits): digits k, k + 1
+  atomicAdd(d + k, w & kAccMask);
+  const unsigned long long hi = w >> kAccBits;
+  if (hi) atomicAdd(d + k + 1, hi);
+}
+
+// Carries every digit's upper bits into the next digit.
+__device__ __forceinline__ void acc_normalize(unsigned long long* d) {
+  unsigned long long carry = 0;
+#pragma unroll
+  for (int k = 0; k < kAccDigits - 1; ++k) {
+    const unsigned long long s = d[k] + carry;
+    d[k] = s & kAccMask;
+    carry = s >> kAccBits;
+  }
+  d[kAccDigits - 1] += carry;
+}
+
+// The value of normalised digits, summed from the top digit down.
+__device__ __forceinline__ double acc_value(const unsigned long long* d) {
+  double v = 0.0;
+#pragma unroll
+  for (int k = kAccDigits - 1; k >= 0; --k) v += ldexp((double)d[k], kAccBits * k + kAccLsb);
+  return v;
+}
+
 // --------------------------------------------------------------- the march
 // One wavefront, one ray, one chunk of kChunk points: Eq. (3) cell after cell
 // for every point, I <- I - (I - B) a with a = 1 - e^{-tau}.  Each lane owns
-// kQ contiguous points starting at the absolute index j.  Per segment the
-// chunk's absorbed (sum I a) and emitted (sum B a) power are reduced across
-// the wavefront and lane 0 adds weight * sum to the cell's FP64
-// accumulators.  PREC selects the precision form: Planck values from the
-// FP64-derived table, the degree-5 branch and FP64 partial sums.  Otherwise
-// the Planck values of a lane's points come from one exact value at its
-// first point nu_a and the second-order expansion of ln B:
+// kQ contiguous points starting at the absolute index j.  Per segment every
+// lane's partial sums of the chunk's absorbed (sum I a) and emitted (sum B a)
+// radiance are staged in LDS; TallyStage<PREC>::kSegs segments at a time they
+// are summed across the wavefront in a fixed order, weighted and added to the
+// cells' fixed-point accumulators (tally_flush).  The ray's entering and
+// escaped radiance over the chunk go the same way to the balance row.  PREC
+// selects the precision form: Planck values from the table, the degree-5
+// branch and FP64 partial sums.  Otherwise the Planck values of a lane's
+// points come from one exact value at its first point nu_a and the
+// second-order expansion of ln B:
 //   B(nu_a + d) = B_a (1 + g1 d + (g1^2 + g2) d^2 / 2),
 //   g1 = 3/nu - theta (1 + r),  g2 = -3/nu^2 + theta^2 r (1 + r),
 //   theta = c2 / T,  r = 1 / (exp(theta nu) - 1);
 // for d <= (kQ - 1) dnu the neglected terms are below 1e-9 relative.
-// Returns the wavefront's entering and escaped radiance sums (unweighted).
 struct MarchWave {
   const float* kappa;   // row c at kappa + c * ld, column j - col0
   const float* planck;  // same layout (precision form)
@@ -534,19 +574,69 @@ struct MarchWave {
   const double* theta;  // c2 / T per cell (plain form)
   const float* bwall;   // B(nu_j, T_wall), indexed by absolute j
   double nu0, dnu, c1, weight;
-  double* acc_abs;
-  double* acc_emi;
+  unsigned long long* acc;  // accumulator rows, kAccRow words each
+  int64_t row0;             // row of cell 0
+  int64_t bal_row0;         // first of the balance rows (entering, escaped)
+  int bal_mask;             // balance rows - 1 (a power of two): a ray adds to
+                            // row bal_row0 + (its slot & bal_mask)
+  unsigned* ovf;            // set by acc_add for a value out of range
 };
+
+// Per-wavefront LDS staging of the per-segment partial sums: [kSegs][2][64].
+template <bool PREC>
+struct TallyStage {
+  static constexpr int kSegs = PREC ? 4 : 8;
+  static constexpr int kEntries = kSegs * 2 * 64;
+};
+
+// Adds np staged entries to the accumulators.  Entry s is segment k0 + s of
+// the ray, or the ray's balance row bal_row once k0 + s reaches ns.  Value v = 2 s + q
+// (q = 0 absorbed or entering, 1 emitted or escaped) is summed by
+// 64 / (2 kSegs) lanes, each over a fixed run of the 64 partials, then across
+// those lanes with DPP: the same order every time.
+template <bool PREC>
+__device__ __forceinline__ void tally_flush(const MarchWave& a,
+                                            const typename Partial<PREC>::T* stage,
+                                            const int2* sg, int ns, int k0, int np, int lane,
+                                            int64_t bal_row) {
+  using PT = typename Partial<PREC>::T;
+  constexpr int V = 2 * TallyStage<PREC>::kSegs;
+  constexpr int LPV = 64 / V;  // lanes per value
+  constexpr int E = 64 / LPV;  // partials per lane
+  static_assert(LPV == 4 || LPV == 8, "flush layout");
+  __builtin_amdgcn_wave_barrier();
+  // a flush runs once per kSegs segments: its lane-derived addresses are
+  // formed here rather than hoisted and kept live across the march loop
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
+  const int v = ln / LPV, part = ln % LPV;
+  const PT* src = stage + v * 64 + part * E;
+  PT s = src[0];
+#pragma unroll
+  for (int i = 1; i < E; ++i) s += src[i];
+  s += dpp_pt<0xB1>(s);  // quad_perm [1,0,3,2]
+  s += dpp_pt<0x4E>(s);  // quad_perm [2,3,0,1]
+  if (LPV == 8) s += dpp_pt<0x141>(s);  // row_half_mirror: the two quads of 8 lanes
+  __builtin_amdgcn_wave_barrier();
+  const int seg = v >> 1;
+  if (part == 0 && seg < np) {
+    const int k = k0 + seg;
+    const int64_t row = k < ns ? a.row0 + sg[k].x : bal_row;
+    acc_add(a.acc + row * kAccRow + (v & 1) * kAccDigits, (double)s * a.weight, a.ovf);
+  }
+}
 
 // QUAD: keep the second-order term of the per-lane Planck expansion (plain
 // form); the host drops it when its relative size over a lane's span is
 // below FP32 unit roundoff for every cell temperature and wavenumber.
+// stage: this wavefront's TallyStage<PREC>::kEntries LDS entries; slot: the
+// ray's index in its launch, which picks its balance row.
 template <bool PREC, bool EXIT, bool QUAD = true>
 __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, int ns, int64_t j,
                                            int lane, float* exit_row,
-                                           typename Partial<PREC>::T& enter_sum,
-                                           typename Partial<PREC>::T& escape_sum) {
+                                           typename Partial<PREC>::T* stage, int64_t slot) {
   using PT = typename Partial<PREC>::T;
+  constexpr int kSegs = TallyStage<PREC>::kSegs;
   const int64_t col = j - a.col0;
   float I[kQ];
 #pragma unroll
@@ -563,10 +653,11 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
     three_nu = (float)(3.0 / nu_a);
     three_nu2 = (float)(3.0 / (nu_a * nu_a));
   }
-  float enter = 0.f;
+  PT enter = 0;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) enter += I[q];
+  for (int q = 0; q < kQ; ++q) enter += (PT)I[q];
   const float nlog2e = -1.4426950408889634f;
+  int np = 0, k0 = 0;  // staged entries, and the segment of the first
   for (int k = 0; k < ns; ++k) {
     const int2 s = sg[k];
     const int64_t c = s.x;
@@ -617,6 +708,7 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
         for (int q = 0; q < kQ; ++q) bv[q] = fmaf(K1, (float)q, B0);
       }
     }
+    // a = 1 - e^{-tau} per point
     float av[kQ];
     if (PREC) {
 #pragma unroll
@@ -633,9 +725,9 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
         kmin = fminf(kmin, kv[q]);
       }
       if (__ballot(kmin * l < 0.0625f)) {
-        // tau < 1/16: a = tau - tau^2/2 + tau^3/6 - tau^4/24 written in
-        // x = -tau log2(e), i.e. a = -sum_k (x ln 2)^k / k!, k = 1..4
-        // (truncation below 1.3e-7 relative)
+        // some lane has tau < 1/16: there a = tau - tau^2/2 + tau^3/6 -
+        // tau^4/24 written in x = -tau log2(e), i.e. a = -sum_k (x ln 2)^k / k!,
+        // k = 1..4 (truncation below 1.3e-7 relative)
         constexpr float L1 = -0.69314718055994531f, L2 = -0.24022650695910071f,
                         L3 = -0.055504108664821576f, L4 = -0.0096181291076284772f;
         constexpr float xlim = -0.0625f * 1.4426950408889634f;
@@ -654,24 +746,34 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
       em += (PT)(bv[q] * av[q]);
       I[q] = fmaf(-(I[q] - bv[q]), av[q], I[q]);
     }
-    const PT tab = wave_sum(ab);
-    const PT tem = wave_sum(em);
-    if (lane == 0) {
-      unsafeAtomicAdd(a.acc_abs + c, a.weight * (double)tab);
-      unsafeAtomicAdd(a.acc_emi + c, a.weight * (double)tem);
+    // the update of I is complete here, so a[] dies before the staging and
+    // the flush below (the scheduler would otherwise sink the updates past
+    // them and keep a[] and B[] live across the flush)
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) asm volatile("" : "+v"(I[q]));
+    PT* st = stage + np * 128;
+    st[lane] = ab;
+    st[64 + lane] = em;
+    if (++np == kSegs) {
+      tally_flush<PREC>(a, stage, sg, ns, k0, np, lane, 0);
+      k0 += np;
+      np = 0;
     }
   }
-  float esc = 0.f;
+  PT esc = 0;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) esc += I[q];
+  for (int q = 0; q < kQ; ++q) esc += (PT)I[q];
   if (EXIT) {
 #pragma unroll
     for (int h = 0; h < kQ / 4; ++h)
       *reinterpret_cast<float4*>(exit_row + col + 4 * h) =
           make_float4(I[4 * h], I[4 * h + 1], I[4 * h + 2], I[4 * h + 3]);
   }
-  enter_sum = wave_sum((PT)enter);
-  escape_sum = wave_sum((PT)esc);
+  // np < kSegs here: one more entry, the balance row's (entering, escaped)
+  PT* st = stage + np * 128;
+  st[lane] = enter;
+  st[64 + lane] = esc;
+  tally_flush<PREC>(a, stage, sg, ns, k0, np + 1, lane, a.bal_row0 + (slot & a.bal_mask));
 }
 
 }  // namespace dev

@@ -7,10 +7,11 @@
 //                traversal -> per-ray list of (cell, length) segments
 //   march      : Eq. (3) applied cell after cell for every nu point; each
 //                wavefront owns one ray and a kChunk-point spectral chunk
-//                (dev::march_wave); per segment the absorbed and emitted
-//                power of the chunk is combined across the wavefront with DPP
-//                reductions and added to the cell's FP64 accumulator
-//   tally      : deterministic FP64 reductions for the energy balance
+//                (dev::march_wave); the absorbed and emitted power of the
+//                chunk per segment is summed across the wavefront in a fixed
+//                order and added to the cell's fixed-point accumulator
+//   tally      : the accumulators as FP64 powers per cell, and the energy
+//                balance from exact sums of the accumulators
 #include "device_common.h"
 
 namespace rt {
@@ -106,7 +107,6 @@ struct MarchArgs {
   const int32_t* counts;
   int max_segs;
   int64_t n_rays;
-  double* slots;
   float* exit_I;
 };
 
@@ -116,8 +116,8 @@ struct MarchArgs {
 // chunk-major, so the waves in flight on it march neighbouring rays of the
 // coherent order through one chunk and share kappa rows in its L2.
 template <bool PREC, bool EXIT, bool QUAD>
-__global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
-  using PT = typename Partial<PREC>::T;
+__device__ __forceinline__ void march_block(const MarchArgs& a,
+                                            typename Partial<PREC>::T (*stage)[TallyStage<PREC>::kEntries]) {
   const int64_t b = blockIdx.x;
   const int64_t xcd = b & 7, local = b >> 3;
   const int chunk = (int)(local / a.ray_blocks_x);
@@ -127,38 +127,86 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs a) {
   const int64_t ray = rb * 4 + wave;
   if (ray >= a.n_rays) return;
   const int64_t j = (int64_t)chunk * kChunk + lane * kQ;
-  PT te, tx;
   march_wave<PREC, EXIT, QUAD>(a.w, a.segs + ray * a.max_segs, a.counts[ray], j, lane,
-                         EXIT ? a.exit_I + ray * a.w.ld : nullptr, te, tx);
-  if (lane == 0) {
-    const int slot = (int)(b % kSlots);
-    unsafeAtomicAdd(a.slots + slot, a.w.weight * (double)te);
-    unsafeAtomicAdd(a.slots + kSlots + slot, a.w.weight * (double)tx);
+                               EXIT ? a.exit_I + ray * a.w.ld : nullptr, stage[wave], ray);
+}
+
+// Plain form.  Five wavefronts per SIMD (at most 96 VGPRs): the kappa rows
+// of the next segments are in flight while other wavefronts compute.
+template <bool EXIT, bool QUAD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void march_kernel(
+    MarchArgs a) {
+  __shared__ float stage[4][TallyStage<false>::kEntries];
+  march_block<false, EXIT, QUAD>(a, stage);
+}
+
+// Precision form (Planck table, FP64 partial sums).
+template <bool EXIT>
+__global__ __launch_bounds__(256) void march_prec_kernel(MarchArgs a) {
+  __shared__ double stage[4][TallyStage<true>::kEntries];
+  march_block<true, EXIT, true>(a, stage);
+}
+
+// Carries of every accumulator row (rows x 2 digit groups).
+__global__ void acc_normalize_kernel(unsigned long long* acc, int64_t groups) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < groups) acc_normalize(acc + i * kAccDigits);
+}
+
+// Per-cell powers from the normalised accumulators.
+__global__ void acc_cells_kernel(const unsigned long long* __restrict__ acc, int64_t n_cells,
+                                 double* abs_, double* emi) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  abs_[c] = acc_value(acc + c * kAccRow);
+  emi[c] = acc_value(acc + c * kAccRow + kAccDigits);
+}
+
+// The exact sum of accumulator rows [first, first + n): each digit is summed
+// over the rows as an integer (normalised digits are below 2^28 and there are
+// fewer than 2^31 rows), in a fixed-order tree over the block's 256 threads;
+// thread 0 gets the normalised digits in d.
+__device__ void acc_rows_sum(const unsigned long long* __restrict__ acc, int64_t first, int64_t n,
+                             unsigned long long (*red)[256], unsigned long long* d) {
+  const int t = threadIdx.x;
+  unsigned long long s[kAccRow];
+#pragma unroll
+  for (int k = 0; k < kAccRow; ++k) s[k] = 0;
+  for (int64_t r = first + t; r < first + n; r += 256)
+#pragma unroll
+    for (int k = 0; k < kAccRow; ++k) s[k] += acc[r * kAccRow + k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kAccRow; ++k) red[k][t] = s[k];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off)
+#pragma unroll
+      for (int k = 0; k < kAccRow; ++k) red[k][t] += red[k][t + off];
+    __syncthreads();
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < kAccRow; ++k) d[k] = red[k][0];
+    acc_normalize(d);
+    acc_normalize(d + kAccDigits);
   }
 }
 
-// Deterministic FP64 sums: balance = {entering, sum emitted, sum absorbed,
-// escaped}; fixed strided partial sums then a fixed tree.
-__global__ __launch_bounds__(1024) void tally_kernel(const double* __restrict__ abs_,
-                                                     const double* __restrict__ emi,
-                                                     int64_t n_cells,
-                                                     const double* __restrict__ slots,
-                                                     double* balance) {
-  __shared__ double red[4][1024];
-  const int t = threadIdx.x;
-  double s_abs = 0, s_emi = 0;
-  for (int64_t c = t; c < n_cells; c += 1024) { s_abs += abs_[c]; s_emi += emi[c]; }
-  red[0][t] = slots[t];
-  red[1][t] = s_emi;
-  red[2][t] = s_abs;
-  red[3][t] = slots[kSlots + t];
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off)
-      for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + off];
-    __syncthreads();
+// balance = {entering, sum emitted, sum absorbed, escaped}, each from the
+// exact sum of its accumulators (cells, or the balance rows), converted once.
+__global__ __launch_bounds__(256) void tally_kernel(const unsigned long long* __restrict__ acc,
+                                                    int64_t n_cells, double* balance) {
+  __shared__ unsigned long long red[kAccRow][256];
+  unsigned long long cells[kAccRow], bal[kAccRow];
+  acc_rows_sum(acc, 0, n_cells, red, cells);
+  acc_rows_sum(acc, n_cells, kBalRows, red, bal);
+  if (threadIdx.x == 0) {
+    balance[0] = acc_value(bal);
+    balance[1] = acc_value(cells + kAccDigits);
+    balance[2] = acc_value(cells);
+    balance[3] = acc_value(bal + kAccDigits);
   }
-  if (t < 4) balance[t] = red[t][0];
 }
 
 __global__ void zero_f64_kernel(double* p, int64_t n) {
@@ -167,8 +215,6 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
 }
 
 }  // namespace
-
-static_assert(kSlots == 1024, "tally kernel assumes 1024 slots");
 
 hipError_t launch_order(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count) {
   const int threads = 256;
@@ -233,35 +279,42 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float
   a.w.dnu = c->dnu;
   a.w.c1 = first_radiation_wavenumber();
   a.w.weight = weight;
-  a.w.acc_abs = c->d_abs;
-  a.w.acc_emi = c->d_emi;
+  a.w.acc = c->d_acc;
+  a.w.row0 = 0;
+  a.w.bal_row0 = c->n_cells;
+  a.w.bal_mask = kBalRows - 1;
+  a.w.ovf = c->d_ovf;
   a.n_chunks = (int)(c->ld / kChunk);
   a.ray_blocks_x = ((count + 3) / 4 + 7) / 8;
   a.segs = c->d_segs;
   a.counts = c->d_counts;
   a.max_segs = c->max_segs;
   a.n_rays = count;
-  a.slots = c->d_slots;
   a.exit_I = exit_dev;
   const int64_t blocks = 8 * a.ray_blocks_x * a.n_chunks;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)blocks), t(256);
   if (prec) {
-    if (exit_dev) hipLaunchKernelGGL((march_kernel<true, true, true>), g, t, 0, c->stream, a);
-    else hipLaunchKernelGGL((march_kernel<true, false, true>), g, t, 0, c->stream, a);
+    if (exit_dev) hipLaunchKernelGGL((march_prec_kernel<true>), g, t, 0, c->stream, a);
+    else hipLaunchKernelGGL((march_prec_kernel<false>), g, t, 0, c->stream, a);
   } else if (planck_needs_quadratic(c->T_min, c->T_max, c->nu0, c->dnu, c->n_nu)) {
-    if (exit_dev) hipLaunchKernelGGL((march_kernel<false, true, true>), g, t, 0, c->stream, a);
-    else hipLaunchKernelGGL((march_kernel<false, false, true>), g, t, 0, c->stream, a);
+    if (exit_dev) hipLaunchKernelGGL((march_kernel<true, true>), g, t, 0, c->stream, a);
+    else hipLaunchKernelGGL((march_kernel<false, true>), g, t, 0, c->stream, a);
   } else {
-    if (exit_dev) hipLaunchKernelGGL((march_kernel<false, true, false>), g, t, 0, c->stream, a);
-    else hipLaunchKernelGGL((march_kernel<false, false, false>), g, t, 0, c->stream, a);
+    if (exit_dev) hipLaunchKernelGGL((march_kernel<true, false>), g, t, 0, c->stream, a);
+    else hipLaunchKernelGGL((march_kernel<false, false>), g, t, 0, c->stream, a);
   }
+  const int64_t groups = 2 * (c->n_cells + kBalRows);
+  hipLaunchKernelGGL(acc_normalize_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0,
+                     c->stream, c->d_acc, groups);
   return hipGetLastError();
 }
 
 hipError_t launch_tally(rt_ctx c) {
-  hipLaunchKernelGGL(tally_kernel, dim3(1), dim3(1024), 0, c->stream, c->d_abs, c->d_emi,
-                     c->n_cells, c->d_slots, c->d_balance);
+  hipLaunchKernelGGL(acc_cells_kernel, dim3((unsigned)((c->n_cells + 255) / 256)), dim3(256), 0,
+                     c->stream, c->d_acc, c->n_cells, c->d_abs, c->d_emi);
+  hipLaunchKernelGGL(tally_kernel, dim3(1), dim3(256), 0, c->stream, c->d_acc, c->n_cells,
+                     c->d_balance);
   return hipGetLastError();
 }
 
@@ -272,7 +325,7 @@ hipError_t launch_zero(rt_ctx c) {
   };
   z(c->d_abs, c->n_cells);
   z(c->d_emi, c->n_cells);
-  z(c->d_slots, 2 * kSlots);
+  z(reinterpret_cast<double*>(c->d_acc), (c->n_cells + kBalRows) * kAccRow + 1);  // + overflow flag
   z(c->d_balance, 4);
   z(reinterpret_cast<double*>(c->d_segcount), 1);
   return hipGetLastError();

@@ -154,10 +154,13 @@ struct rt_ctx_s {
   float* d_bwall = nullptr; // B(nu_j, T_wall), ld floats (owned)
   int64_t bwall_len = 0;
 
-  // tallies (owned)
+  // tallies (owned): fixed-point accumulator rows [n_cells + kBalRows][2][kAccDigits]
+  // (rows from n_cells: entering, escaped) followed by the overflow flag; the
+  // per-cell powers and the balance converted from them by rt_tally
+  unsigned long long* d_acc = nullptr;
+  unsigned* d_ovf = nullptr;
   double* d_abs = nullptr;
   double* d_emi = nullptr;
-  double* d_slots = nullptr;  // [2][kSlots]: entering, escaped partials
   double* d_balance = nullptr;
   unsigned long long* d_segcount = nullptr;
 
@@ -183,7 +186,19 @@ struct rt_ctx_s {
 };
 
 namespace rt {
-constexpr int kSlots = 1024;
+// Fixed-point tally accumulators: kAccDigits digits of kAccBits bits, digit k
+// worth 2^(kAccBits k + kAccLsb) W, each in a 64-bit word with room for the
+// carries of 2^36 additions; a row holds the digits of the absorbed (or
+// entering) and emitted (or escaped) power.
+constexpr int kAccBits = 28;
+constexpr int kAccDigits = 7;
+constexpr int kAccLsb = -112;
+constexpr int kAccRow = 2 * kAccDigits;
+// terms one launch may add to one accumulator word (rays x spectral chunks)
+constexpr int64_t kAccMaxTerms = int64_t(1) << 35;
+// Balance rows (entering, escaped) per grid: rays spread over them so that
+// their additions do not all meet in one accumulator.
+constexpr int kBalRows = 1024;
 // Coherent ray order: 6 dominant directions x 3 x 3 transverse direction
 // bins x 64 x 64 positions on the mid-plane; used for batches of at least
 // kOrderMinRays rays.
