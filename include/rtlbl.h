@@ -231,6 +231,23 @@ rt_status rt_trace_rays(rt_ctx ctx, uint64_t seed, uint64_t n_rays_total,
                         uint64_t ray_begin, uint64_t ray_count,
                         int tally_prec);
 
+/* rt_trace_rays for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same rays, kernels and tallies as rt_trace_rays -- bit for bit the same
+ * tallies -- but the call allocates nothing.  Its ray segments, order keys,
+ * permutation and histogram live in a static 64 MiB device array that the
+ * library holds on every GPU it runs on until the process ends; the tallies
+ * are the handle's own (allocated by rt_setup_grid).  Rays are traced in
+ * batches of as many as fit: 12 + 8 (nx+ny+nz) bytes per ray, at most 2^21
+ * rays per batch.  RT_EINVAL when not even 256 rays of the grid fit
+ * (nx+ny+nz above about 32,000).  Records no timing for rt_get_stats.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (other handles, other streams, other
+ * host threads) race and must be serialised by the caller.  Other arguments,
+ * errors and requirements as rt_trace_rays. */
+rt_status rt_trace_rays_noalloc(rt_ctx ctx, uint64_t seed, uint64_t n_rays_total,
+                                uint64_t ray_begin, uint64_t ray_count, int tally_prec);
+
 /* Rays given explicitly in the fixed-point frame (one cell edge = 2^21
  * units): origin O[3*r..] on the boundary, inward integer direction
  * D[3*r..] (|D_k| <= 2^21), host arrays, n_rays >= 1, with the given

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -16,6 +17,32 @@
 namespace {
 
 thread_local std::string g_create_error;
+
+// Device scratch of rt_trace_rays_noalloc: one batch of rays' segments,
+// counts, coherent-order keys and permutation, and the order's histogram.
+// Each GPU the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: rt_create looks up
+// the device address once per device (hipGetSymbolAddress, device current)
+// and every launch takes that address.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device index, nullptr until looked up
+
+// The device address of `scratch` on `device` (which must be current).
+hipError_t scratch_address(int device, int n_devices, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() < n_devices) g_scratch_ptr.resize(n_devices, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 rt_status fail(rt_ctx c, rt_status s, const std::string& msg) {
   if (c) c->err = msg; else g_create_error = msg;
@@ -187,6 +214,7 @@ rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream) {
   c->device = hip_device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   e = hipSetDevice(hip_device);
+  if (e == hipSuccess) e = scratch_address(hip_device, n, &c->noalloc_scratch);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_balance), 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_segcount), sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_adapt_evals), sizeof(unsigned long long));
@@ -627,48 +655,113 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   return RT_OK;
 }
 
-static rt_status trace_batches(rt_ctx c, uint64_t seed, uint64_t begin, uint64_t count,
-                               double weight, bool f64, bool explicit_rays, float* exit_dev) {
-  if (rt_status s = ensure_batch(c, (int64_t)count)) return s;
-  if (rt_status s = record_begin(c, c->trace_events)) return s;
+// Traces rays [begin, begin + count) batch by batch through the ray scratch
+// rs.  timed: record the HIP events rt_get_stats reads (the entry point that
+// allocates nothing records none).
+static rt_status trace_with(rt_ctx c, const rt::RayScratch& rs, uint64_t seed, uint64_t begin,
+                            uint64_t count, double weight, bool f64, bool explicit_rays,
+                            float* exit_dev, bool timed) {
+  if (timed)
+    if (rt_status s = record_begin(c, c->trace_events)) return s;
   // A launch adds at most (rays x chunks) terms to one accumulator word
   // (a ray crosses a cell once); the words are normalised after every launch.
   const int64_t n_chunks = std::max<int64_t>(1, c->ld / rt::kChunk);
   const int64_t per_launch =
-      std::max<int64_t>(1, std::min<int64_t>(c->batch_rays, rt::kAccMaxTerms / n_chunks));
+      std::max<int64_t>(1, std::min<int64_t>(rs.cap, rt::kAccMaxTerms / n_chunks));
   for (uint64_t off = 0; off < count; off += (uint64_t)per_launch) {
     const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)per_launch, count - off);
     if (explicit_rays && off > 0) return fail(c, RT_EINVAL, "explicit rays exceed one batch");
     const bool order = !explicit_rays && n >= rt::kOrderMinRays;
-    if (order) RT_HIP(c, rt::launch_order(c, seed, begin + off, n));
-    RT_HIP(c, rt::launch_raygen(c, seed, begin + off, n, explicit_rays, nullptr, true,
-                                order ? c->d_perm : nullptr));
-    if (rt_status s = record_begin(c, c->march_events)) return s;
-    RT_HIP(c, rt::launch_march(c, n, weight, f64, exit_dev));
-    if (rt_status s = record_end(c, c->march_events)) return s;
+    if (order) RT_HIP(c, rt::launch_order(c, rs, seed, begin + off, n));
+    RT_HIP(c, rt::launch_raygen(c, rs, seed, begin + off, n, explicit_rays, nullptr, true,
+                                order ? rs.perm : nullptr));
+    if (timed)
+      if (rt_status s = record_begin(c, c->march_events)) return s;
+    RT_HIP(c, rt::launch_march(c, rs, n, weight, f64, exit_dev));
+    if (timed)
+      if (rt_status s = record_end(c, c->march_events)) return s;
     c->stats.march_launches += 1;
   }
-  if (rt_status s = record_end(c, c->trace_events)) return s;
+  if (timed)
+    if (rt_status s = record_end(c, c->trace_events)) return s;
   c->stats.rays += (double)count;
+  return RT_OK;
+}
+
+static rt_status trace_batches(rt_ctx c, uint64_t seed, uint64_t begin, uint64_t count,
+                               double weight, bool f64, bool explicit_rays, float* exit_dev) {
+  if (rt_status s = ensure_batch(c, (int64_t)count)) return s;
+  return trace_with(c, rt::owned_rays(c), seed, begin, count, weight, f64, explicit_rays,
+                    exit_dev, true);
+}
+
+// Checks shared by rt_trace_rays and rt_trace_rays_noalloc.
+static rt_status check_trace(rt_ctx c, const char* who, uint64_t n_rays_total,
+                             uint64_t ray_begin, uint64_t ray_count, int tally_prec) {
+  const std::string w(who);
+  if (!c->have_kappa) return fail(c, RT_ESTATE, w + ": call rt_compute_kappa first");
+  if (n_rays_total == 0) return fail(c, RT_EINVAL, w + ": n_rays_total must be >= 1");
+  if (ray_begin > n_rays_total || ray_count > n_rays_total - ray_begin)
+    return fail(c, RT_EINVAL, w + ": ray range outside [0, n_rays_total)");
+  if (tally_prec != RT_TALLY_F32 && tally_prec != RT_TALLY_F64)
+    return fail(c, RT_EINVAL, w + ": unknown tally precision");
+  if (tally_prec == RT_TALLY_F64 && !c->planck)
+    return fail(c, RT_ESTATE, w + ": the precision form needs the Planck table "
+                                  "(pass planck_dev to rt_compute_kappa)");
   return RT_OK;
 }
 
 rt_status rt_trace_rays(rt_ctx c, uint64_t seed, uint64_t n_rays_total, uint64_t ray_begin,
                         uint64_t ray_count, int tally_prec) {
   if (!c) return fail(c, RT_EINVAL, "rt_trace_rays: NULL handle");
-  if (!c->have_kappa) return fail(c, RT_ESTATE, "rt_trace_rays: call rt_compute_kappa first");
-  if (n_rays_total == 0) return fail(c, RT_EINVAL, "rt_trace_rays: n_rays_total must be >= 1");
-  if (ray_begin > n_rays_total || ray_count > n_rays_total - ray_begin)
-    return fail(c, RT_EINVAL, "rt_trace_rays: ray range outside [0, n_rays_total)");
-  if (tally_prec != RT_TALLY_F32 && tally_prec != RT_TALLY_F64)
-    return fail(c, RT_EINVAL, "rt_trace_rays: unknown tally precision");
-  if (tally_prec == RT_TALLY_F64 && !c->planck)
-    return fail(c, RT_ESTATE, "rt_trace_rays: the precision form needs the Planck table "
-                              "(pass planck_dev to rt_compute_kappa)");
+  if (rt_status s = check_trace(c, "rt_trace_rays", n_rays_total, ray_begin, ray_count, tally_prec))
+    return s;
   if (ray_count == 0) return RT_OK;
   if (rt_status s = set_device(c)) return s;
   return trace_batches(c, seed, ray_begin, ray_count, ray_weight(c, (double)n_rays_total),
                        tally_prec == RT_TALLY_F64, false, nullptr);
+}
+
+rt_status rt_trace_rays_noalloc(rt_ctx c, uint64_t seed, uint64_t n_rays_total,
+                                uint64_t ray_begin, uint64_t ray_count, int tally_prec) {
+  if (!c) return fail(c, RT_EINVAL, "rt_trace_rays_noalloc: NULL handle");
+  if (rt_status s = check_trace(c, "rt_trace_rays_noalloc", n_rays_total, ray_begin, ray_count,
+                                tally_prec))
+    return s;
+  if (!c->noalloc_scratch)
+    return fail(c, RT_ESTATE, "rt_trace_rays_noalloc: no device scratch for this handle");
+  // carve the static scratch: histogram, then per ray count, key and
+  // permutation words, then the segments
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  const int max_segs = c->nx + c->ny + c->nz;
+  const size_t hist_bytes = up((size_t)rt::kOrderBuckets * 4);
+  const size_t per_ray = 12 + 8 * (size_t)max_segs;
+  const size_t room = kNoAllocBytes - hist_bytes - 3 * 256;  // 3 alignment gaps
+  const int64_t cap = std::min<int64_t>((int64_t)(room / per_ray), int64_t(1) << 21) / 256 * 256;
+  if (cap < 256)
+    return fail(c, RT_EINVAL, "rt_trace_rays_noalloc: the grid's traversals (nx+ny+nz = " +
+                                  std::to_string(max_segs) + " segments per ray) do not fit 256 rays "
+                                  "in the 64 MiB device scratch");
+  if (ray_count == 0) return RT_OK;
+  if (rt_status s = set_device(c)) return s;
+  char* base = static_cast<char*>(c->noalloc_scratch);
+  rt::RayScratch rs;
+  size_t off = 0;
+  rs.hist = reinterpret_cast<uint32_t*>(base + off);
+  off += hist_bytes;
+  rs.counts = reinterpret_cast<int32_t*>(base + off);
+  off += up((size_t)cap * 4);
+  rs.keys = reinterpret_cast<uint32_t*>(base + off);
+  off += up((size_t)cap * 4);
+  rs.perm = reinterpret_cast<uint32_t*>(base + off);
+  off += up((size_t)cap * 4);
+  rs.segs = reinterpret_cast<int2*>(base + off);
+  off += (size_t)cap * max_segs * 8;
+  if (off > kNoAllocBytes) return fail(c, RT_EINVAL, "rt_trace_rays_noalloc: scratch layout");
+  rs.max_segs = max_segs;
+  rs.cap = cap;
+  return trace_with(c, rs, seed, ray_begin, ray_count, ray_weight(c, (double)n_rays_total),
+                    tally_prec == RT_TALLY_F64, false, nullptr, false);
 }
 
 rt_status rt_trace_explicit(rt_ctx c, int n_rays, const int64_t* O, const int64_t* D,
@@ -798,7 +891,8 @@ rt_status rt_debug_segments(rt_ctx c, uint64_t seed, uint64_t ray_begin, uint64_
   std::vector<int64_t> rays;
   for (uint64_t off = 0; off < count; off += (uint64_t)c->batch_rays) {
     const int64_t n = (int64_t)std::min<uint64_t>((uint64_t)c->batch_rays, count - off);
-    RT_HIP(c, rt::launch_raygen(c, seed, ray_begin + off, n, false, c->d_rays_explicit, false,
+    RT_HIP(c, rt::launch_raygen(c, rt::owned_rays(c), seed, ray_begin + off, n, false,
+                                c->d_rays_explicit, false,
                                 nullptr));
     seg.resize((size_t)n * c->max_segs);
     cnt.resize((size_t)n);

@@ -216,30 +216,43 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
 
 }  // namespace
 
-hipError_t launch_order(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count) {
+RayScratch owned_rays(rt_ctx c) {
+  RayScratch s;
+  s.segs = c->d_segs;
+  s.counts = c->d_counts;
+  s.keys = c->d_keys;
+  s.perm = c->d_perm;
+  s.hist = c->d_hist;
+  s.max_segs = c->max_segs;
+  s.cap = c->batch_rays;
+  return s;
+}
+
+hipError_t launch_order(rt_ctx c, const RayScratch& s, uint64_t seed, uint64_t begin,
+                        int64_t count) {
   const int threads = 256;
   const unsigned blocks = (unsigned)((count + threads - 1) / threads);
   hipLaunchKernelGGL(zero_u32_kernel, dim3((kOrderBuckets + threads - 1) / threads), dim3(threads),
-                     0, c->stream, c->d_hist, (int64_t)kOrderBuckets);
+                     0, c->stream, s.hist, (int64_t)kOrderBuckets);
   hipLaunchKernelGGL(order_key_kernel, dim3(blocks), dim3(threads), 0, c->stream, seed, begin,
-                     count, c->nx, c->ny, c->nz, c->d_keys, c->d_hist);
-  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(1024), 0, c->stream, c->d_hist,
+                     count, c->nx, c->ny, c->nz, s.keys, s.hist);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(1024), 0, c->stream, s.hist,
                      kOrderBuckets);
-  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(threads), 0, c->stream, c->d_keys,
-                     count, c->d_hist, c->d_perm);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(threads), 0, c->stream, s.keys,
+                     count, s.hist, s.perm);
   return hipGetLastError();
 }
 
-hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count,
-                         bool explicit_rays, int64_t* rays_out, bool count_work,
+hipError_t launch_raygen(rt_ctx c, const RayScratch& s, uint64_t seed, uint64_t begin,
+                         int64_t count, bool explicit_rays, int64_t* rays_out, bool count_work,
                          const uint32_t* perm) {
   const int threads = 256;
   const int64_t blocks = (count + threads - 1) / threads;
   const double unit_cm = c->cell_m * 100.0 / (double)kCellUnits;
   hipLaunchKernelGGL(raygen_dda_kernel, dim3((unsigned)blocks), dim3(threads), 0, c->stream,
-                     seed, begin, count, c->nx, c->ny, c->nz, unit_cm, c->max_segs,
-                     explicit_rays ? c->d_rays_explicit : nullptr, rays_out, c->d_segs,
-                     c->d_counts, count_work ? c->d_segcount : nullptr, perm);
+                     seed, begin, count, c->nx, c->ny, c->nz, unit_cm, s.max_segs,
+                     explicit_rays ? c->d_rays_explicit : nullptr, rays_out, s.segs,
+                     s.counts, count_work ? c->d_segcount : nullptr, perm);
   return hipGetLastError();
 }
 
@@ -267,7 +280,8 @@ bool planck_needs_quadratic(double T_min, double T_max, double nu0, double dnu, 
   return !(worst < std::ldexp(1.0, -24));
 }
 
-hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev) {
+hipError_t launch_march(rt_ctx c, const RayScratch& s, int64_t count, double weight, bool prec,
+                        float* exit_dev) {
   MarchArgs a;
   a.w.kappa = c->kappa;
   a.w.planck = c->planck;
@@ -286,9 +300,9 @@ hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float
   a.w.ovf = c->d_ovf;
   a.n_chunks = (int)(c->ld / kChunk);
   a.ray_blocks_x = ((count + 3) / 4 + 7) / 8;
-  a.segs = c->d_segs;
-  a.counts = c->d_counts;
-  a.max_segs = c->max_segs;
+  a.segs = s.segs;
+  a.counts = s.counts;
+  a.max_segs = s.max_segs;
   a.n_rays = count;
   a.exit_I = exit_dev;
   const int64_t blocks = 8 * a.ray_blocks_x * a.n_chunks;

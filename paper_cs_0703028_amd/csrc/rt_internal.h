@@ -93,6 +93,19 @@ struct Stats {
   double batch_ms = 0;
 };
 
+// Device memory one batch of rays is traced in: per ray a fixed stride of
+// max_segs (cell, length) segments and their count, the coherent-order key
+// and permutation, and the order's histogram (kOrderBuckets words).
+struct RayScratch {
+  int2* segs = nullptr;
+  int32_t* counts = nullptr;
+  uint32_t* keys = nullptr;
+  uint32_t* perm = nullptr;
+  uint32_t* hist = nullptr;
+  int max_segs = 0;
+  int64_t cap = 0;  // rays per batch
+};
+
 struct BatchPlan;
 struct Surrogate;
 }  // namespace rt
@@ -177,6 +190,8 @@ struct rt_ctx_s {
   float* d_exit = nullptr;
   int64_t exit_cap = 0;
 
+  void* noalloc_scratch = nullptr;  // this device's static scratch (rt_trace_rays_noalloc)
+
   rt::BatchPlan* batch = nullptr;  // prepared batched launch (owned)
   rt::Surrogate* surrogate = nullptr;  // learned form (owned)
 
@@ -218,9 +233,13 @@ hipError_t launch_kappa_table16(rt_ctx c);
 // adds the kept evaluations to *c->d_adapt_evals.
 hipError_t launch_kappa_adaptive(rt_ctx c);
 hipError_t launch_planck(rt_ctx c);
-hipError_t launch_raygen(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count, bool explicit_rays,
-                         int64_t* rays_out, bool count_work, const uint32_t* perm);
-hipError_t launch_order(rt_ctx c, uint64_t seed, uint64_t begin, int64_t count);
+// the handle's own ray scratch (rt_trace_rays, rt_trace_explicit, rt_debug_segments)
+RayScratch owned_rays(rt_ctx c);
+hipError_t launch_raygen(rt_ctx c, const RayScratch& s, uint64_t seed, uint64_t begin,
+                         int64_t count, bool explicit_rays, int64_t* rays_out, bool count_work,
+                         const uint32_t* perm);
+hipError_t launch_order(rt_ctx c, const RayScratch& s, uint64_t seed, uint64_t begin,
+                        int64_t count);
 // whether the plain march needs the second-order term of its Planck expansion
 bool planck_needs_quadratic(double T_min, double T_max, double nu0, double dnu, int n_nu);
 // FP32 arithmetic characterisation (arith.hip): operands each op reads (0 for
@@ -228,7 +247,8 @@ bool planck_needs_quadratic(double T_min, double T_max, double nu0, double dnu, 
 int arith_operands(int op);
 hipError_t launch_arith(rt_ctx c, int op, const float* a, const float* b, const float* z,
                         float* out, int64_t n);
-hipError_t launch_march(rt_ctx c, int64_t count, double weight, bool prec, float* exit_dev);
+hipError_t launch_march(rt_ctx c, const RayScratch& s, int64_t count, double weight, bool prec,
+                        float* exit_dev);
 hipError_t launch_tally(rt_ctx c);
 hipError_t launch_zero(rt_ctx c);
 void destroy_batch(rt_ctx c);

@@ -106,6 +106,8 @@ def _load():
     L.rt_compute_kappa.argtypes = [vp, C.c_int, vp, vp, C.c_int64]
     L.rt_set_line_tolerance.argtypes = [vp, C.c_double]
     L.rt_trace_rays.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int]
+    L.rt_trace_rays_noalloc.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
+                                        C.c_int]
     L.rt_trace_explicit.argtypes = [vp, C.c_int, _i64p, _i64p, C.c_double, C.c_int, vp]
     L.rt_tally.argtypes = [vp, vp, vp, vp]
     L.rt_reset_tally.argtypes = [vp]
@@ -134,7 +136,7 @@ def _load():
               "rt_surrogate_forward", "rt_surrogate_weights", "rt_surrogate_get_stats"):
         getattr(L, f).restype = C.c_int
     for f in ("rt_create", "rt_destroy", "rt_setup_grid", "rt_setup_lines", "rt_compute_kappa",
-              "rt_trace_rays", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
+              "rt_trace_rays", "rt_trace_rays_noalloc", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
               "rt_debug_segments", "rt_get_stats", "rt_batch_default_tuning",
               "rt_batch_workspace_size", "rt_batch_prepare", "rt_batch_launch",
               "rt_batch_results", "rt_batch_autotune", "rt_arith_eval", "rt_setup_gas"):
@@ -281,6 +283,13 @@ class Tracer:
         if count is None:
             count = n_rays_total - begin
         self._check(lib.rt_trace_rays(self._h, seed, n_rays_total, begin, count, prec))
+
+    def trace_rays_noalloc(self, seed, n_rays_total, begin=0, count=None, prec=TALLY_F32):
+        """rt_trace_rays_noalloc: as trace_rays, with the library's static
+        device scratch instead of any allocation."""
+        if count is None:
+            count = n_rays_total - begin
+        self._check(lib.rt_trace_rays_noalloc(self._h, seed, n_rays_total, begin, count, prec))
 
     def trace_explicit(self, O, D, weight, prec=TALLY_F32, want_exit=False):
         O = np.ascontiguousarray(O, np.int64).reshape(-1, 3)
