@@ -49,7 +49,12 @@ typedef enum {
 
 typedef enum {
   RT_KAPPA_PLAIN = 0,        /* FP32 line sum                               */
-  RT_KAPPA_COMPENSATED = 1,  /* FP32 line sum with compensated summation    */
+  RT_KAPPA_COMPENSATED = 1,  /* the precision form's line sum: FP32 only --
+                                compensated summation, and the Eq. (1)
+                                factors from FP32 exponentials (Cody-Waite
+                                range reduction on FP32-pair arguments) of
+                                per-cell and per-line inputs the host forms in
+                                FP64 (1/T_ref - 1/T, c2/T, c2 E, nu, u, p)   */
   RT_KAPPA_SURROGATE = 2,    /* learned form (rt_surrogate_train/load), with
                                 line-sum fallback and a sampled check       */
   RT_KAPPA_TABLE16 = 3,      /* the paper's own formulation (Section 3 and its
@@ -96,8 +101,9 @@ typedef enum {
  *     1 - exp(-tau) from the hardware exponential with a degree-4 series
  *     below tau = 1/16, per-wavefront partial sums in FP32.
  *   RT_TALLY_F64: precision form.  Planck values read from the table of
- *     rt_compute_kappa (required), degree-5 series below tau = 1/4, partial
- *     sums in FP64. */
+ *     rt_compute_kappa (required), degree-5 series below tau = 1/4, all in
+ *     FP32; FP64 only in the tally (per-lane partial sums and the weighted
+ *     values added to the accumulators). */
 typedef enum {
   RT_TALLY_F32 = 0,
   RT_TALLY_F64 = 1
@@ -182,7 +188,9 @@ int rt_march_chunk(void);
 
 /* Eq. (2) with Eq. (1) per cell: kappa_dev[c*ld + j] = kappa_c(nu_j) in
  * cm^-1, and, when planck_dev is not NULL, Eq. (4): planck_dev[c*ld + j] =
- * B(nu_j, T_c) evaluated in FP64 and stored in FP32.  Both are caller
+ * B(nu_j, T_c), evaluated in FP32 (c1 nu^3 over an FP32 expm1 of the pair
+ * product c2 nu / T; within 1e-6 relative).  The walls' row is evaluated the
+ * same way.  Both are caller
  * allocated, 16-byte aligned device buffers of nx*ny*nz rows of `ld` floats,
  * ld a multiple of 1536 and >= rt_required_pitch (columns n_nu .. ld-1 are
  * written with zeros).  The handle keeps both pointers for rt_trace_rays;

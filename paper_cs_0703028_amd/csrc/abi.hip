@@ -81,6 +81,44 @@ void dev_free(T*& p) {
   p = nullptr;
 }
 
+// v as an FP32 pair hi + lo (hi = v rounded, lo = the rest rounded).
+float2 split_pair(double v) {
+  const float h = (float)v;
+  return make_float2(h, (float)(v - (double)h));
+}
+
+// The precision form's per-cell inputs (see rt::CellSet), formed on the host
+// from the FP64 gas state and uploaded: u/(pi dnu), log2(T_ref/T), p/dnu,
+// 1/T_ref - 1/T and c2/T, and each further gas's u/(pi dnu).
+rt_status upload_cells32(rt_ctx c) {
+  const int64_t n = c->n_cells;
+  const double c2 = rt::second_radiation_cm_K();
+  std::vector<float> uf(n), lam(n), P(n);
+  std::vector<float2> beta(n), theta(n);
+  auto dens = [&](double T, double x, double p) {
+    return x * p * rt::kAtm / (rt::kBoltzmann * T) * 1e-6 / (M_PI * c->dnu);
+  };
+  for (int64_t i = 0; i < n; ++i) {
+    const double T = c->hT[i];
+    uf[i] = (float)dens(T, c->hx[i], c->hp[i]);
+    lam[i] = (float)std::log2(c->T_ref / T);
+    P[i] = (float)(c->hp[i] / c->dnu);
+    beta[i] = split_pair(1.0 / c->T_ref - 1.0 / T);
+    theta[i] = split_pair(c2 / T);
+  }
+  RT_HIP(c, hipMemcpy(c->cells.uf, uf.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  RT_HIP(c, hipMemcpy(c->cells.lamf, lam.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  RT_HIP(c, hipMemcpy(c->cells.Pf, P.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  RT_HIP(c, hipMemcpy(c->cells.beta2, beta.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+  RT_HIP(c, hipMemcpy(c->cells.theta2, theta.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+  for (auto& g : c->gas) {
+    if (!g.active) continue;
+    for (int64_t i = 0; i < n; ++i) uf[i] = (float)dens(c->hT[i], g.hx[i], c->hp[i]);
+    RT_HIP(c, hipMemcpy(g.uf, uf.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return RT_OK;
+}
+
 bool finite_all(const double* a, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(a[i])) return false;
@@ -93,6 +131,7 @@ void free_lineset(rt::LineSet& L) {
   dev_free(L.tile16);
   dev_free(L.r64); dev_free(L.S64); dev_free(L.g64); dev_free(L.n64);
   dev_free(L.aE); dev_free(L.rN);
+  dev_free(L.E2p); dev_free(L.nup);
   L.n = 0;
   L.n_tiles16 = 0;
 }
@@ -111,6 +150,8 @@ void free_gases(rt_ctx c) {
     free_lineset(g.lines);
     dev_free(g.x);
     dev_free(g.G);
+    dev_free(g.uf);
+    dev_free(g.Gq);
     g = rt::ExtraGas();
   }
 }
@@ -118,6 +159,8 @@ void free_gases(rt_ctx c) {
 void free_cells(rt_ctx c) {
   rt::CellSet& C = c->cells;
   dev_free(C.G); dev_free(C.beta); dev_free(C.theta); dev_free(C.lam2); dev_free(C.P);
+  dev_free(C.uf); dev_free(C.lamf); dev_free(C.Pf); dev_free(C.beta2); dev_free(C.theta2);
+  dev_free(C.Gq);
 }
 
 void free_events(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
@@ -281,6 +324,7 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   c->have_grid = false;
   c->have_kappa = false;
   c->cells_valid = false;
+  c->cells32_valid = false;
   RT_HIP(c, dev_alloc(&c->d_T, n));
   RT_HIP(c, dev_alloc(&c->d_x, n));
   RT_HIP(c, dev_alloc(&c->d_p, n));
@@ -294,9 +338,18 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   RT_HIP(c, dev_alloc(&c->cells.theta, n));
   RT_HIP(c, dev_alloc(&c->cells.lam2, n));
   RT_HIP(c, dev_alloc(&c->cells.P, n));
+  RT_HIP(c, dev_alloc(&c->cells.uf, n));
+  RT_HIP(c, dev_alloc(&c->cells.lamf, n));
+  RT_HIP(c, dev_alloc(&c->cells.Pf, n));
+  RT_HIP(c, dev_alloc(&c->cells.beta2, n));
+  RT_HIP(c, dev_alloc(&c->cells.theta2, n));
+  RT_HIP(c, dev_alloc(&c->cells.Gq, n));
   RT_HIP(c, hipMemcpyAsync(c->d_T, T, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   RT_HIP(c, hipMemcpyAsync(c->d_x, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   RT_HIP(c, hipMemcpyAsync(c->d_p, p, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  c->hT.assign(T, T + n);
+  c->hx.assign(x, x + n);
+  c->hp.assign(p, p + n);
   RT_HIP(c, hipStreamSynchronize(c->stream));  // host arrays may be freed on return
   c->nx = nx; c->ny = ny; c->nz = nz;
   c->n_cells = n;
@@ -355,6 +408,7 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   std::vector<int32_t> hm(nl), hwlo(nl), hwhi(nl);
   std::vector<float> hphi(nl), hS(nl), hg(nl), hn(nl);
   std::vector<double> hE2(nl), hnu(nl);
+  std::vector<float2> hE2p(nl), hnup(nl);
   std::vector<double> hr64(nl), hS64(nl), hg64(nl), hn64(nl), haE(nl), hrN(nl);
   std::vector<float> hprof((size_t)nl * 16);
   for (int k = 0; k < nl; ++k) {
@@ -379,6 +433,8 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
     hS[k] = (float)(E ? S[i] / (-std::expm1(-c2 * nu[i] / T_ref)) : S[i]);
     hE2[k] = E ? c2 * E[i] : 0.0;
     hnu[k] = nu[i];
+    hE2p[k] = split_pair(hE2[k]);
+    hnup[k] = split_pair(nu[i]);
     hg[k] = (float)gamma[i];
     hn[k] = (float)n_T[i];
     // binary64 data of the adaptive windows: the centre in grid units as
@@ -401,6 +457,8 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   RT_HIP(c, dev_alloc(&L.gamma, nl));
   RT_HIP(c, dev_alloc(&L.nexp, nl));
   RT_HIP(c, dev_alloc(&L.prof16, (size_t)nl * 16));
+  RT_HIP(c, dev_alloc(&L.E2p, nl));
+  RT_HIP(c, dev_alloc(&L.nup, nl));
   {
     double** d64[6] = {&L.r64, &L.S64, &L.g64, &L.n64, &L.aE, &L.rN};
     const std::vector<double>* h64[6] = {&hr64, &hS64, &hg64, &hn64, &haE, &hrN};
@@ -433,6 +491,8 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
     RT_HIP(c, hipMemcpy(L.nu, hnu.data(), nl * sizeof(double), hipMemcpyHostToDevice));
     RT_HIP(c, hipMemcpy(L.gamma, hg.data(), nl * sizeof(float), hipMemcpyHostToDevice));
     RT_HIP(c, hipMemcpy(L.nexp, hn.data(), nl * sizeof(float), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.E2p, hE2p.data(), nl * sizeof(float2), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(L.nup, hnup.data(), nl * sizeof(float2), hipMemcpyHostToDevice));
   }
   L.n = nl;
   return RT_OK;
@@ -462,6 +522,7 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
   c->have_lines = false;
   c->have_kappa = false;
   c->cells_valid = false;
+  c->cells32_valid = false;
   double evals = 0;
   if (rt_status s = build_lines(c, "rt_setup_lines", n_lines, nu, S, gamma, n_T, E, T_ref, K,
                                 nu0, dnu, n_nu, c->lines, evals)) {
@@ -500,9 +561,12 @@ rt_status rt_setup_gas(rt_ctx c, int gas, const double* x, int n_lines, const do
   free_lineset(g.lines);
   dev_free(g.x);
   dev_free(g.G);
+  dev_free(g.uf);
+  dev_free(g.Gq);
   g = rt::ExtraGas();
   c->have_kappa = false;
   c->cells_valid = false;
+  c->cells32_valid = false;
   if (n_lines == 0) return RT_OK;  // gas removed
   double evals = 0;
   rt_status st = build_lines(c, "rt_setup_gas", n_lines, nu, S, gamma, n_T, E, c->T_ref, c->K,
@@ -510,6 +574,8 @@ rt_status rt_setup_gas(rt_ctx c, int gas, const double* x, int n_lines, const do
   if (st == RT_OK) {
     hipError_t e = dev_alloc(&g.x, (size_t)c->n_cells);
     if (e == hipSuccess) e = dev_alloc(&g.G, (size_t)c->n_cells);
+    if (e == hipSuccess) e = dev_alloc(&g.uf, (size_t)c->n_cells);
+    if (e == hipSuccess) e = dev_alloc(&g.Gq, (size_t)c->n_cells);
     if (e == hipSuccess)
       e = hipMemcpy(g.x, x, (size_t)c->n_cells * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) st = hip_fail(c, e, "rt_setup_gas: device arrays");
@@ -518,9 +584,12 @@ rt_status rt_setup_gas(rt_ctx c, int gas, const double* x, int n_lines, const do
     free_lineset(g.lines);
     dev_free(g.x);
     dev_free(g.G);
+    dev_free(g.uf);
+    dev_free(g.Gq);
     g = rt::ExtraGas();
     return st;
   }
+  g.hx.assign(x, x + c->n_cells);
   g.have_E = E != nullptr;
   g.line_evals_per_cell = evals;
   g.active = true;
@@ -552,6 +621,17 @@ rt_status rt_set_line_tolerance(rt_ctx c, double eps) {
   if (!c) return fail(c, RT_EINVAL, "rt_set_line_tolerance: NULL handle");
   if (!(eps > 0 && eps < 1)) return fail(c, RT_EINVAL, "rt_set_line_tolerance: eps must be in (0, 1)");
   c->line_tol = eps;
+  return RT_OK;
+}
+
+// The FP64-derived cell factors (c->cells: G, beta, theta, lam2, P and the
+// further gases' G), formed once per grid and line list.
+static rt_status ensure_cells(rt_ctx c) {
+  if (c->cells_valid) return RT_OK;
+  RT_HIP(c, rt::launch_cell_params(c));
+  for (int g = 1; g < rt::kMaxGases; ++g)
+    if (c->gas[g - 1].active) RT_HIP(c, rt::launch_gas_factor(c, g));
+  c->cells_valid = true;
   return RT_OK;
 }
 
@@ -619,13 +699,16 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
   c->kappa = kappa_dev;
   c->planck = planck_dev;
   c->ld = ld;
-  if (rt_status s = record_begin(c, c->kappa_events)) return s;
-  if (!c->cells_valid) {
-    RT_HIP(c, rt::launch_cell_params(c));
-    for (int g = 1; g < rt::kMaxGases; ++g)
-      if (c->gas[g - 1].active) RT_HIP(c, rt::launch_gas_factor(c, g));
-    c->cells_valid = true;
+  if (!c->cells32_valid) {  // the precision form's line sum, the Planck table, the walls
+    if (rt_status s = upload_cells32(c)) return s;
+    RT_HIP(c, rt::launch_cell_params32(c));
+    c->cells32_valid = true;
   }
+  if (rt_status s = record_begin(c, c->kappa_events)) return s;
+  // the FP64-derived cell factors serve every form but the precision form,
+  // whose line sum runs on its FP32 inputs alone
+  if (mode != RT_KAPPA_COMPENSATED)
+    if (rt_status s = ensure_cells(c)) return s;
   if (mode == RT_KAPPA_SURROGATE) {
     if (rt_status s = rt::surrogate_kappa(c)) return s;
   } else if (mode == RT_KAPPA_TABLE16) {
@@ -695,7 +778,9 @@ static rt_status trace_batches(rt_ctx c, uint64_t seed, uint64_t begin, uint64_t
                     exit_dev, true);
 }
 
-// Checks shared by rt_trace_rays and rt_trace_rays_noalloc.
+// Checks shared by rt_trace_rays and rt_trace_rays_noalloc.  The plain march
+// reads c2/T of the FP64-derived cell factors, which a compute_kappa in the
+// precision form does not form.
 static rt_status check_trace(rt_ctx c, const char* who, uint64_t n_rays_total,
                              uint64_t ray_begin, uint64_t ray_count, int tally_prec) {
   const std::string w(who);
@@ -708,7 +793,9 @@ static rt_status check_trace(rt_ctx c, const char* who, uint64_t n_rays_total,
   if (tally_prec == RT_TALLY_F64 && !c->planck)
     return fail(c, RT_ESTATE, w + ": the precision form needs the Planck table "
                                   "(pass planck_dev to rt_compute_kappa)");
-  return RT_OK;
+  if (tally_prec == RT_TALLY_F32)
+    if (rt_status s = set_device(c)) return s;
+  return tally_prec == RT_TALLY_F32 ? ensure_cells(c) : RT_OK;
 }
 
 rt_status rt_trace_rays(rt_ctx c, uint64_t seed, uint64_t n_rays_total, uint64_t ray_begin,
@@ -803,6 +890,8 @@ rt_status rt_trace_explicit(rt_ctx c, int n_rays, const int64_t* O, const int64_
     }
   }
   if (rt_status s = set_device(c)) return s;
+  if (tally_prec == RT_TALLY_F32)
+    if (rt_status s = ensure_cells(c)) return s;
   if (c->explicit_cap < n_rays) {
     dev_free(c->d_rays_explicit);
     RT_HIP(c, dev_alloc(&c->d_rays_explicit, (size_t)n_rays * 6));

@@ -118,6 +118,13 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
     const double area = 2.0 * h * h * ((double)q.nx * q.ny + (double)q.ny * q.nz + (double)q.nz * q.nx);
     b.weight = M_PI * area * c->dnu / (double)q.n_rays;
     b.unit_cm = q.cell_m * 100.0 / (double)kCellUnits;
+    if (q.T_wall_K > 0) {
+      const double th = second_radiation_cm_K() / q.T_wall_K;
+      const float h = (float)th;
+      b.theta_wall = make_float2(h, (float)(th - (double)h));
+    } else {
+      b.theta_wall = make_float2(0.f, 0.f);
+    }
     cell_off += b.n_cells;
     seg_off += b.n_rays * b.max_segs;
     ray_off += b.n_rays;

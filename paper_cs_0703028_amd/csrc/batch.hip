@@ -355,29 +355,33 @@ __global__ void fill_f64_kernel(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-// B(nu_j, T_wall) rows per case, FP64 evaluated, FP32 stored.
-__global__ void case_wall_kernel(const double* T_wall, int n_cases, int n_nu, int64_t ld,
-                                 double nu0, double dnu, double c1, double c2, float* bw) {
+// B(nu_j, T_wall) rows per case, evaluated in FP32 as the single-case walls'
+// row (planck_f32).
+__global__ void case_wall_kernel(const BatchCase* __restrict__ cases, int n_cases, int n_nu,
+                                 int64_t ld, float2 nu0, float2 dnu, float c1, float* bw) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n_cases * ld) return;
   const int cs = (int)(i / ld);
   const int64_t j = i % ld;
+  const float2 th = cases[cs].theta_wall;
   float v = 0.f;
-  if (j < n_nu && T_wall[cs] > 0.0) {
-    const double nu = nu0 + (double)j * dnu;
-    v = (float)(c1 * nu * nu * nu / expm1(c2 * nu / T_wall[cs]));
-  }
+  if (j < n_nu && th.x > 0.f) v = planck_f32(nu_at(j, pair_of(nu0), pair_of(dnu)), pair_of(th), c1);
   bw[i] = v;
 }
 
 }  // namespace
 
+static float2 host_pair(double v) {
+  const float h = (float)v;
+  return make_float2(h, (float)(v - (double)h));
+}
+
 hipError_t launch_batch_prep(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
-  const double c1 = first_radiation_wavenumber(), c2 = second_radiation_cm_K();
+  const float c1 = (float)first_radiation_wavenumber();
   const int64_t nw = (int64_t)pl.n_cases * pl.bwall_ld;
   hipLaunchKernelGGL(case_wall_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s,
-                     pl.d_T_wall, pl.n_cases, c->n_nu, pl.bwall_ld, c->nu0, c->dnu, c1, c2,
-                     pl.d_bwall);
+                     pl.d_cases, pl.n_cases, c->n_nu, pl.bwall_ld, host_pair(c->nu0),
+                     host_pair(c->dnu), c1, pl.d_bwall);
   return hipGetLastError();
 }
 

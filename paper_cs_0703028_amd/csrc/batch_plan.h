@@ -28,6 +28,7 @@ struct BatchCase {
   int64_t n_cells, cell_off, n_rays, seg_off, ray_off;
   uint64_t seed;
   double weight, unit_cm;
+  float2 theta_wall;  // c2 / T_wall as an FP32 pair (0: cold walls)
 };
 
 struct BatchPlan {

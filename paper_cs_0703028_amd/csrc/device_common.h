@@ -48,6 +48,85 @@ __device__ __forceinline__ float one_minus_exp_neg_d(double x) {
   return 1.0f - exp_split(-x);
 }
 
+// ------------------------------------------------- FP32 exponentials (pairs)
+// The precision form evaluates every exponential in FP32.  An argument comes
+// as an FP32 pair x = h + l (products of pairs keep about 46 bits, so the
+// argument's own rounding does not limit the result), e^x is taken by Cody
+// and Waite's range reduction with log2(e) split as L_h + L_l:
+//   n = rint(h L_h),  f = fma(h, L_h, -n) + (h L_l + l L_h),  e^x = 2^n 2^f,
+// |f| <= 1/2 + 2^-20, with the hardware base-2 exponential for 2^f (below
+// one ulp) and an exact scaling by 2^n.  Relative error about 1e-7 for
+// |x| < 80.
+struct Pair {
+  float h, l;
+};
+
+__device__ __forceinline__ Pair pair_of(float2 v) { return Pair{v.x, v.y}; }
+
+// (a.h + a.l)(b.h + b.l) to about 2^-46 relative: the exact rounding error
+// of a.h b.h (one FMA) plus the cross terms; a.l b.l is dropped.
+__device__ __forceinline__ Pair pair_mul(Pair a, Pair b) {
+  const float p = a.h * b.h;
+  const float e = fmaf(a.h, b.l, fmaf(a.l, b.h, fmaf(a.h, b.h, -p)));
+  return Pair{p, e};
+}
+
+__device__ __forceinline__ float exp_pair(Pair x) {
+  constexpr float L_h = 1.44269502162933349609375f;  // log2(e) rounded to FP32
+  constexpr float L_l = 1.925962989e-08f;             // log2(e) - L_h
+  const float n = rintf(x.h * L_h);
+  const float f = fmaf(x.h, L_h, -n) + fmaf(x.h, L_l, x.l * L_h);
+  return ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
+}
+
+// e^x - 1 for x >= 0: below 1/2 the Taylor series to degree 10 (truncation
+// below 3e-10 relative) in Horner form, otherwise exp_pair(x) - 1 (the
+// subtraction loses at most a factor e^(1/2)/(e^(1/2) - 1) = 2.5).
+__device__ __forceinline__ float expm1_pair(Pair x) {
+  if (x.h < 0.5f) {
+    const float t = x.h + x.l;
+    float p = 1.0f + t * (1.0f / 10.0f);
+#pragma unroll
+    for (int k = 9; k >= 2; --k) p = fmaf(t * (1.0f / (float)k), p, 1.0f);
+    return t * p;
+  }
+  return exp_pair(x) - 1.0f;
+}
+
+// 1 - e^{-x} for x >= 0: the alternating series to degree 10 below 1/2,
+// otherwise 1 - exp_pair(-x) (loses at most a factor 1/(1 - e^(-1/2)) = 2.5).
+__device__ __forceinline__ float one_minus_exp_neg_pair(Pair x) {
+  if (x.h < 0.5f) {
+    const float t = x.h + x.l;
+    float p = 1.0f - t * (1.0f / 10.0f);
+#pragma unroll
+    for (int k = 9; k >= 2; --k) p = fmaf(-t * (1.0f / (float)k), p, 1.0f);
+    return t * p;
+  }
+  return 1.0f - exp_pair(Pair{-x.h, -x.l});
+}
+
+// nu_j = nu0 + j dnu as an FP32 pair, from the pairs of nu0 and dnu: the
+// product j dnu.h with its exact rounding error (one FMA), then Knuth's
+// TwoSum with nu0.h.
+__device__ __forceinline__ Pair nu_at(int64_t j, Pair nu0, Pair dnu) {
+  const float jf = (float)j;  // exact below 2^24
+  const float ph = jf * dnu.h;
+  const float pl = fmaf(jf, dnu.h, -ph) + jf * dnu.l;
+  const float s = nu0.h + ph;
+  const float bp = s - nu0.h;
+  const float err = (nu0.h - (s - bp)) + (ph - bp);
+  return Pair{s, err + pl + nu0.l};
+}
+
+// Eq. (4) in FP32: B = c1 nu^3 / expm1(theta nu), theta = c2 / T, with the
+// argument theta nu formed as a pair product and expm1_pair.
+__device__ __forceinline__ float planck_f32(Pair nu, Pair theta, float c1) {
+  const float em1 = expm1_pair(pair_mul(nu, theta));
+  const float v = nu.h + nu.l;
+  return c1 * v * v * v / em1;
+}
+
 __device__ __forceinline__ int first_ge(const int32_t* a, int n, int v) {
   int lo = 0, hi = n;
   while (lo < hi) {
@@ -90,6 +169,22 @@ __device__ __forceinline__ void line_cell_params(const LineSet& L, const CellSet
   if (have_E) {
     a *= exp_split(L.E2[i] * C.beta[cell]);
     a *= one_minus_exp_neg_d(L.nu[i] * C.theta[cell]);
+  }
+  amp = a;
+  g2 = gp * gp;
+}
+
+// The same record in FP32 only (the precision form): the Eq. (1) factors from
+// the host-formed FP32 inputs with exp_pair, the half width's temperature
+// power and the partition ratio (in Gq) with the hardware base-2 exponential.
+__device__ __forceinline__ void line_cell_params_f32(const LineSet& L, const CellSet& C, int i,
+                                                     int64_t cell, int have_E, float& amp,
+                                                     float& g2) {
+  const float gp = L.gamma[i] * C.Pf[cell] * fast_exp2(L.nexp[i] * C.lamf[cell]);
+  float a = C.Gq[cell] * L.S[i] * gp;
+  if (have_E) {
+    a *= exp_pair(pair_mul(pair_of(L.E2p[i]), pair_of(C.beta2[cell])));
+    a *= one_minus_exp_neg_pair(pair_mul(pair_of(L.nup[i]), pair_of(C.theta2[cell])));
   }
   amp = a;
   g2 = gp * gp;
@@ -175,7 +270,8 @@ struct TileGate {
   int n_chunks = 0;
 };
 
-template <bool COMP>
+// F32: line records from line_cell_params_f32 (the precision form).
+template <bool COMP, bool F32 = false>
 __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds) {
   constexpr int C = kKappaCells, P = kKappaPoints;
   constexpr int REC = kLineRec;
@@ -253,7 +349,10 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
         rec[2] = (float)(a.L.wlo[i] - a.L.m[i]);  // -K + [phi > 0]
         rec[3] = (float)a.K;
       }
-      line_cell_params(a.L, a.C, i, cell, a.have_E, rec[4 + 2 * cc], rec[5 + 2 * cc]);
+      if (F32)
+        line_cell_params_f32(a.L, a.C, i, cell, a.have_E, rec[4 + 2 * cc], rec[5 + 2 * cc]);
+      else
+        line_cell_params(a.L, a.C, i, cell, a.have_E, rec[4 + 2 * cc], rec[5 + 2 * cc]);
     }
     __syncthreads();
 

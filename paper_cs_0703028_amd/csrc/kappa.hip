@@ -4,7 +4,8 @@
 //   kappa_linesum : Eq. (2) with the Eq. (1) strength ratio (line tiles staged
 //                   in LDS, each lane owns 2 nu points of 8 cells, kappa
 //                   written coalesced along nu; see dev::kappa_tile)
-//   planck_table  : Eq. (4), wavenumber form, per (cell, nu) and for the walls
+//   planck_table  : Eq. (4), wavenumber form, per (cell, nu) and for the walls,
+//                   evaluated in FP32 (pair arguments, exp_pair/expm1_pair)
 #include "batch_plan.h"
 #include "device_common.h"
 
@@ -39,6 +40,16 @@ __global__ void cell_params_kernel(int64_t n, const double* __restrict__ T,
   P[c] = (float)(p[c] / dnu);
 }
 
+// The precision form's Gq = u q / (pi dnu) per cell, in FP32: u/(pi dnu) and
+// log2(T_ref/T) come from the host, q = 2^(1.5 log2(T_ref/T)) with energies
+// (the partition ratio of Eq. (1)), 1 without.
+__global__ void cell_params32_kernel(int64_t n, const float* __restrict__ uf,
+                                     const float* __restrict__ lamf, int have_E, float* Gq) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  Gq[c] = have_E ? uf[c] * fast_exp2(1.5f * lamf[c]) : uf[c];
+}
+
 // G of a further gas: its own mole fraction and partition-ratio choice.
 __global__ void gas_factor_kernel(int64_t n, const double* __restrict__ T,
                                   const double* __restrict__ x, const double* __restrict__ p,
@@ -57,7 +68,7 @@ struct KappaArgs {
   int64_t part_stride = 0;   // floats between the shares' outputs
 };
 
-template <bool COMP>
+template <bool COMP, bool F32 = false>
 __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs a) {
   __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
   const int part = (int)(blockIdx.x % (unsigned)a.parts);
@@ -79,40 +90,34 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs 
     t.line_parts = a.parts;
     t.line_part = part;
     t.out += part * a.part_stride;
-    kappa_tile<COMP>(t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
+    kappa_tile<COMP, F32>(t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
     return;
   }
-  kappa_tile<COMP>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
+  kappa_tile<COMP, F32>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
 }
 
-// Eq. (4): B = c1 nu^3 / (exp(c2 nu / T) - 1), evaluated in FP64 and stored
-// in FP32; one block per (cell, 256-point segment of the row).
-__global__ void planck_table_kernel(const double* __restrict__ T, int64_t n_cells,
-                                    int n_nu, int64_t ld, int tiles_per_row,
-                                    double nu0, double dnu, double c1, double c2,
-                                    float* __restrict__ B) {
+// Planck table: one block per (cell, 256-point segment of the row).
+__global__ void planck_table_kernel(const float2* __restrict__ theta2, int64_t n_cells,
+                                    int n_nu, int64_t ld, int tiles_per_row, float2 nu0,
+                                    float2 dnu, float c1, float* __restrict__ B) {
   const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   const int64_t cell = b / tiles_per_row;
   if (cell >= n_cells) return;
   const int64_t j = (b % tiles_per_row) * 256 + threadIdx.x;
   if (j >= ld) return;
   float v = 0.f;
-  if (j < n_nu) {
-    double nu = nu0 + (double)j * dnu;
-    v = (float)(c1 * nu * nu * nu / expm1(c2 * nu / T[cell]));
-  }
+  if (j < n_nu) v = planck_f32(nu_at(j, pair_of(nu0), pair_of(dnu)), pair_of(theta2[cell]), c1);
   B[cell * ld + j] = v;
 }
 
-__global__ void wall_table_kernel(double T_wall, int n_nu, int64_t ld, double nu0,
-                                  double dnu, double c1, double c2, float* bw) {
+// The walls' row B(nu_j, T_wall); theta_wall = c2 / T_wall (zero: cold walls).
+__global__ void wall_table_kernel(float2 theta_wall, int n_nu, int64_t ld, float2 nu0,
+                                  float2 dnu, float c1, float* bw) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ld) return;
   float v = 0.f;
-  if (j < n_nu && T_wall > 0.0) {
-    double nu = nu0 + (double)j * dnu;
-    v = (float)(c1 * nu * nu * nu / expm1(c2 * nu / T_wall));
-  }
+  if (j < n_nu && theta_wall.x > 0.f)
+    v = planck_f32(nu_at(j, pair_of(nu0), pair_of(dnu)), pair_of(theta_wall), c1);
   bw[j] = v;
 }
 
@@ -239,6 +244,20 @@ hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const dou
   return hipGetLastError();
 }
 
+hipError_t launch_cell_params32(rt_ctx c) {
+  const int64_t n = c->n_cells;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(cell_params32_kernel, dim3(blocks), dim3(256), 0, c->stream, n, c->cells.uf,
+                     c->cells.lamf, c->have_E ? 1 : 0, c->cells.Gq);
+  for (int g = 1; g < kMaxGases; ++g) {
+    const ExtraGas& gs = c->gas[g - 1];
+    if (!gs.active) continue;
+    hipLaunchKernelGGL(cell_params32_kernel, dim3(blocks), dim3(256), 0, c->stream, n, gs.uf,
+                       c->cells.lamf, gs.have_E ? 1 : 0, gs.Gq);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_gas_factor(rt_ctx c, int g) {
   const ExtraGas& gs = c->gas[g - 1];
   const int64_t n = c->n_cells;
@@ -265,9 +284,9 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
   const int64_t blocks = groups * a.n_tiles;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   auto launch = [&]() {
-    if (compensated)
-      hipLaunchKernelGGL((kappa_linesum_kernel<true>), dim3((unsigned)blocks), dim3(kKappaThreads),
-                         0, c->stream, a);
+    if (compensated)  // the precision form: FP32 line parameters
+      hipLaunchKernelGGL((kappa_linesum_kernel<true, true>), dim3((unsigned)blocks),
+                         dim3(kKappaThreads), 0, c->stream, a);
     else
       hipLaunchKernelGGL((kappa_linesum_kernel<false>), dim3((unsigned)blocks),
                          dim3(kKappaThreads), 0, c->stream, a);
@@ -280,6 +299,7 @@ hipError_t launch_kappa(rt_ctx c, bool compensated) {
     if (!gs.active) continue;
     a.t.L = gs.lines;
     a.t.C.G = gs.G;
+    a.t.C.Gq = gs.Gq;
     a.t.have_E = gs.have_E ? 1 : 0;
     a.t.accumulate = 1;
     e = launch();
@@ -309,20 +329,30 @@ hipError_t launch_kappa_tiles(rt_ctx c, const KappaTile& t, int64_t n_cell_group
   return hipGetLastError();
 }
 
+// v as an FP32 pair hi + lo (host).
+static float2 host_pair(double v) {
+  const float h = (float)v;
+  return make_float2(h, (float)(v - (double)h));
+}
+
 hipError_t launch_planck(rt_ctx c) {
-  const double c1 = first_radiation_wavenumber(), c2 = second_radiation_cm_K();
+  const float c1 = (float)first_radiation_wavenumber();
+  const double c2 = second_radiation_cm_K();
+  const float2 nu0 = host_pair(c->nu0), dnu = host_pair(c->dnu);
   const int tiles = (int)((c->ld + 255) / 256);
   if (c->planck) {
     const int64_t blocks = c->n_cells * tiles;
     const unsigned gx = (unsigned)std::min<int64_t>(blocks, 65536);
     const unsigned gy = (unsigned)((blocks + gx - 1) / gx);
-    hipLaunchKernelGGL(planck_table_kernel, dim3(gx, gy), dim3(256), 0, c->stream, c->d_T,
-                       c->n_cells, c->n_nu, c->ld, tiles, c->nu0, c->dnu, c1, c2, c->planck);
+    hipLaunchKernelGGL(planck_table_kernel, dim3(gx, gy), dim3(256), 0, c->stream,
+                       c->cells.theta2, c->n_cells, c->n_nu, c->ld, tiles, nu0, dnu, c1,
+                       c->planck);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  const float2 theta_wall = c->T_wall > 0.0 ? host_pair(c2 / c->T_wall) : make_float2(0.f, 0.f);
   hipLaunchKernelGGL(wall_table_kernel, dim3((unsigned)((c->ld + 255) / 256)), dim3(256), 0,
-                     c->stream, c->T_wall, c->n_nu, c->ld, c->nu0, c->dnu, c1, c2, c->d_bwall);
+                     c->stream, theta_wall, c->n_nu, c->ld, nu0, dnu, c1, c->d_bwall);
   return hipGetLastError();
 }
 

@@ -58,6 +58,10 @@ struct LineSet {
   double* n64 = nullptr;
   double* aE = nullptr;
   double* rN = nullptr;
+  // inputs of the precision form's FP32 line parameters: c2 E and the centre
+  // nu, each split on the host into an FP32 pair hi + lo
+  float2* E2p = nullptr;
+  float2* nup = nullptr;
 };
 
 // Per-cell derived parameters (device), from FP64 on the device.
@@ -67,6 +71,17 @@ struct CellSet {
   double* theta = nullptr;  // c2 / T
   float* lam2 = nullptr;    // log2(T_ref / T)
   float* P = nullptr;       // p / dnu
+  // The precision form's per-cell inputs, FP32 on the device: the host forms
+  // u/(pi dnu), log2(T_ref/T) and p/dnu and the exponent factors 1/T_ref - 1/T
+  // and c2/T (as FP32 pairs hi + lo) from the FP64 gas state; every
+  // exponential, Gq = u q / (pi dnu) with q = 2^(1.5 log2(T_ref/T)) among
+  // them, is evaluated on the device in FP32.
+  float* uf = nullptr;
+  float* lamf = nullptr;
+  float* Pf = nullptr;
+  float2* beta2 = nullptr;
+  float2* theta2 = nullptr;
+  float* Gq = nullptr;
 };
 
 // A further absorbing gas: lines, mole fraction per cell (FP64, device) and
@@ -79,6 +94,9 @@ struct ExtraGas {
   double* x = nullptr;
   float* G = nullptr;
   double line_evals_per_cell = 0;
+  std::vector<double> hx;     // host copy of x (for the precision form's uf)
+  float* uf = nullptr;        // u/(pi dnu) from the host, FP32
+  float* Gq = nullptr;        // u q/(pi dnu), FP32 on the device
 };
 
 struct Stats {
@@ -126,6 +144,7 @@ struct rt_ctx_s {
   double* d_T = nullptr;
   double* d_x = nullptr;
   double* d_p = nullptr;
+  std::vector<double> hT, hx, hp;  // host copies (the precision form's inputs)
 
   // lines + spectral grid
   bool have_lines = false;
@@ -160,6 +179,7 @@ struct rt_ctx_s {
   // derived per-cell parameters and tables
   rt::CellSet cells;
   bool cells_valid = false;
+  bool cells32_valid = false;  // the precision form's FP32 fields of `cells`
   bool have_kappa = false;
   float* kappa = nullptr;   // caller owned
   float* planck = nullptr;  // caller owned
@@ -225,6 +245,8 @@ hipError_t launch_cell_params(rt_ctx c);
 // per-cell factor G of extra gas g (after launch_cell_params' other tables)
 hipError_t launch_gas_factor(rt_ctx c, int g);
 hipError_t launch_kappa(rt_ctx c, bool compensated);
+// the precision form's Gq per cell (gas 0 and every further gas), FP32
+hipError_t launch_cell_params32(rt_ctx c);
 // The paper's kappa formulation (16 tabulated points per line, multiply-adds
 // only), every gas, into c->kappa.
 hipError_t launch_kappa_table16(rt_ctx c);
@@ -232,6 +254,8 @@ hipError_t launch_kappa_table16(rt_ctx c);
 // window table (c->d_win, sized by the caller) and the windowed line sum;
 // adds the kept evaluations to *c->d_adapt_evals.
 hipError_t launch_kappa_adaptive(rt_ctx c);
+// the Planck table (when c->planck is set) and the wall row, both evaluated in
+// FP32 from the precision form's inputs
 hipError_t launch_planck(rt_ctx c);
 // the handle's own ray scratch (rt_trace_rays, rt_trace_explicit, rt_debug_segments)
 RayScratch owned_rays(rt_ctx c);

@@ -3,17 +3,20 @@
 Bars (stated per result):
 * traversal (integer work): cells, segment counts, origins and directions
   bit-exact; lengths equal to the oracle's FP64 length rounded to FP32;
-* kappa and Planck tables: 1e-5 relative per element, exact zeros where the
+* kappa and Planck tables: 1e-5 relative per element (the Planck table, all
+  FP32, also within its own rounding bound of 1e-6), exact zeros where the
   oracle has zeros (window membership is integer work);
 * per-cell absorbed and emitted power and the energy balance: 1e-5 relative
   (the floating-point tolerance of the method's FP32 path); cells the oracle
   leaves at exactly zero must be exactly zero.
 """
 import math
+from dataclasses import replace
 
 import numpy as np
 import pytest
 
+import oracle_pool
 from paper_cs_0703028_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -96,7 +99,11 @@ def test_kappa_and_planck_tables(rt, O, wl, mode):
     rb = _rel(bg[:, :w.lines.n_nu], bo)
     _say(f"  kappa rel err max {rk.max():.3e} median {np.median(rk):.3e}; planck {rb.max():.3e}")
     assert rk.max() <= REL
-    assert rb.max() <= 2e-7
+    # the table is evaluated in FP32 (pair arguments, Cody-Waite exponential):
+    # at most about 14 roundings of 2^-24 each (nu, nu^3 and c1: 8; the
+    # exponential and its subtraction of 1, which can amplify by 2.5: 5; the
+    # division: 1), i.e. 8.3e-7
+    assert rb.max() <= 1e-6
     st = t.stats()
     assert st["line_evals"] > 0
     t.close()
@@ -144,8 +151,8 @@ def test_ray_ranges_add_up(rt, O):
     for b, c in ((300, 400), (0, 100), (100, 200)):
         t.trace_rays(w.seed, w.n_rays, b, c)
     a2, e2, b2 = t.tally()
-    np.testing.assert_allclose(a2, a1, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(e2, e1, rtol=1e-12, atol=0)
+    # exact fixed-point sums: the split of the rays over calls does not matter
+    assert np.array_equal(a2, a1) and np.array_equal(e2, e1) and np.array_equal(b2, b1)
     t.close()
 
 
@@ -210,14 +217,15 @@ def test_abi_errors(rt):
 @pytest.mark.slow
 def test_full_size_32cube_sampled(rt, O):
     """The 32^3 / 20,000-line / 50,000-point workload at full size on the GPU:
-    kappa of sampled cells and the tallies of a sampled ray range against the
-    oracle (which computes only the cells those rays visit)."""
+    kappa of 64 sampled cells (every point) and the tallies of a sampled ray
+    range against the oracle (which computes only the cells those rays
+    visit)."""
     w = I.plain_32cube()
     t = _tracer(rt, w)
     _say("full-size 32^3 compute_kappa (plain)")
     kap, B = t.compute_kappa(0)
     rng = np.random.default_rng(11)
-    cells = np.sort(rng.choice(w.grid.n_cells, 12, replace=False)).astype(np.int32)
+    cells = np.sort(rng.choice(w.grid.n_cells, 64, replace=False)).astype(np.int32)
     kg = kap[cells.tolist()].cpu().numpy()[:, :w.lines.n_nu]
     ko = O.kappa(w.grid, w.lines, cells)
     rk = _rel(kg, ko)
@@ -236,6 +244,58 @@ def test_full_size_32cube_sampled(rt, O):
     t.close()
 
 
+def _check_tallies(tag, got, ref):
+    ag, eg, bg = got
+    ra = _rel(ag, ref["absorbed"])
+    re_ = _rel(eg, ref["emitted"])
+    rb = _rel(bg, ref["balance"])
+    _say(f"  {tag}: absorbed max {ra.max():.3e} median {np.median(ra):.3e}, "
+         f"emitted max {re_.max():.3e}, balance {rb.max():.3e}")
+    assert ra.max() <= REL and re_.max() <= REL and rb.max() <= REL
+
+
+@pytest.mark.slow
+def test_plain_8cube_coherent_call_matches_oracle(rt, O):
+    """The 8^3 workload with 2^15 rays in one rt_trace_rays call: a batch of
+    2^15 rays or more runs in the coherent order, the path full-size calls
+    take.  Per cell against the oracle over the same rays (marched on host
+    threads)."""
+    w = I.plain_8cube()
+    n = 1 << 15
+    t = _tracer(rt, w)
+    t.compute_kappa(0)
+    _say(f"plain_8cube: {n} rays in one call")
+    t.trace_rays(w.seed, n, 0, n, rt.TALLY_F32)
+    got = t.tally()
+    assert t.stats()["march_launches"] == 1
+    t.close()
+    _say(f"  oracle on {oracle_pool.threads()} threads")
+    _check_tallies("8^3, 2^15 rays, coherent order", got,
+                   oracle_pool.run(w.grid, w.lines, n, seed=w.seed))
+
+
+@pytest.mark.slow
+def test_32cube_coherent_call_two_chunks_matches_oracle(rt, O):
+    """The 32^3 grid, 20,000-line list and 2^15 rays of the full-size
+    workload, traced in one call (coherent order, the XCD-major block map over
+    two spectral chunks) on the first 3,072 points of its spectral grid, where
+    the oracle's kappa of every cell is affordable.  Per cell against the
+    oracle."""
+    w = I.plain_32cube()
+    w = replace(w, lines=replace(w.lines, n_nu=2 * rt.MARCH_CHUNK))
+    n = 1 << 15
+    t = _tracer(rt, w)
+    t.compute_kappa(0)
+    _say(f"32^3, {w.lines.n_nu} points: {n} rays in one call")
+    t.trace_rays(w.seed, n, 0, n, rt.TALLY_F32)
+    got = t.tally()
+    assert t.stats()["march_launches"] == 1
+    t.close()
+    _say(f"  oracle on {oracle_pool.threads()} threads")
+    _check_tallies("32^3, 2 chunks, 2^15 rays", got,
+                   oracle_pool.run(w.grid, w.lines, n, seed=w.seed))
+
+
 def test_coherent_order_matches_natural_order(rt):
     """A batch of >= 2^15 rays is marched in the coherent (sorted) order; the
     same rays traced in pieces below that size run in index order.  Only the
@@ -252,10 +312,8 @@ def test_coherent_order_matches_natural_order(rt):
     for b in range(0, n, 1 << 14):
         t.trace_rays(w.seed, n, b, 1 << 14)
     a2, e2, b2 = t.tally()
-    assert (a1 > 0).sum() == (a2 > 0).sum()
-    np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(e1, e2, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(b1, b2, rtol=1e-12, atol=0)
+    # exact fixed-point sums of the same per-segment values
+    assert np.array_equal(a1, a2) and np.array_equal(e1, e2) and np.array_equal(b1, b2)
     t.close()
 
 
@@ -307,9 +365,7 @@ def test_coherent_order_across_several_batches(rt):
     for b in range(0, w.n_rays, 1 << 14):
         t.trace_rays(w.seed, w.n_rays, b, 1 << 14)
     a2, e2, b2 = t.tally()
-    np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(e1, e2, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(b1, b2, rtol=1e-12, atol=0)
+    assert np.array_equal(a1, a2) and np.array_equal(e1, e2) and np.array_equal(b1, b2)
     t.close()
 
 
