@@ -849,7 +849,7 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
     // the flush below (the scheduler would otherwise sink the updates past
     // them and keep a[] and B[] live across the flush)
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) asm volatile("" : "+v"(I[q]));
+    for (int q = 0; q < kQ; ++q) asm volatile("" ::"v"(I[q]));
     PT* st = stage + np * 128;
     st[lane] = ab;
     st[64 + lane] = em;

@@ -151,26 +151,25 @@ __global__ void act_bwd_kernel(const float* __restrict__ dH, const float* __rest
   if (dZT) dZT[(int64_t)n * M + m] = (bf16)g;
 }
 
-// db[n] = sum_m G[m][n] (FP32 or BF16 source): block (64 columns, 256 rows),
-// 4 row groups per block reduced in LDS, one atomic per column and block;
-// db must be zero on entry.
+// db[n] = sum_m G[m][n] (FP32 or BF16 source): one block per 64 columns over
+// all M rows, 4 row groups (rows g, g + 4, ...) reduced in LDS in a fixed
+// order, so training repeats bit for bit.
 template <class T>
 __global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ G, int M, int N,
                                                      float* db) {
   __shared__ float red[4][64];
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + c;
-  const int m0 = blockIdx.y * 256;
   float s = 0.f;
   if (n < N)
-    for (int m = m0 + g; m < min(m0 + 256, M); m += 4) s += (float)G[(int64_t)m * N + n];
+    for (int m = g; m < M; m += 4) s += (float)G[(int64_t)m * N + n];
   red[g][c] = s;
   __syncthreads();
-  if (g == 0 && n < N) atomicAdd(db + n, red[0][c] + red[1][c] + red[2][c] + red[3][c]);
+  if (g == 0 && n < N) db[n] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
 }
 
 // dW1[k][n] = sum_m X0[m][k] dZ1[m][n] and db1[n] = sum_m dZ1[m][n], same
-// decomposition as colsum_kernel; outputs must be zero on entry.
+// decomposition and fixed order as colsum_kernel.
 __global__ __launch_bounds__(256) void layer1_wgrad_kernel(const float* __restrict__ X0,
                                                            const float* __restrict__ dZ1, int M,
                                                            float* dW1, float* db1) {
@@ -178,9 +177,8 @@ __global__ __launch_bounds__(256) void layer1_wgrad_kernel(const float* __restri
   const int N = kMlpDims[1];
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + c;
-  const int m0 = blockIdx.y * 256;
   float s[5] = {0, 0, 0, 0, 0};
-  for (int m = m0 + g; m < min(m0 + 256, M); m += 4) {
+  for (int m = g; m < M; m += 4) {
     const float d = dZ1[(int64_t)m * N + n];
     for (int k = 0; k < 4; ++k) s[k] = fmaf(X0[4 * m + k], d, s[k]);
     s[4] += d;
@@ -189,8 +187,8 @@ __global__ __launch_bounds__(256) void layer1_wgrad_kernel(const float* __restri
   __syncthreads();
   if (g == 0) {
     for (int k = 0; k < 4; ++k)
-      atomicAdd(dW1 + k * N + n, red[k][0][c] + red[k][1][c] + red[k][2][c] + red[k][3][c]);
-    atomicAdd(db1 + n, red[4][0][c] + red[4][1][c] + red[4][2][c] + red[4][3][c]);
+      dW1[k * N + n] = (red[k][0][c] + red[k][1][c]) + (red[k][2][c] + red[k][3][c]);
+    db1[n] = (red[4][0][c] + red[4][1][c]) + (red[4][2][c] + red[4][3][c]);
   }
 }
 
@@ -779,9 +777,7 @@ void forward(const Surrogate& S, Acts& a, bool train, hipStream_t s) {
 }
 
 void colsum_bf16(const bf16* G, int M, int N, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(N)), dim3(256), 0, s, db, (int64_t)N);
-  hipLaunchKernelGGL(colsum_kernel<bf16>, dim3((N + 63) / 64, (M + 255) / 256), dim3(256), 0, s,
-                     G, M, N, db);
+  hipLaunchKernelGGL(colsum_kernel<bf16>, dim3((N + 63) / 64), dim3(256), 0, s, G, M, N, db);
 }
 
 void backward(const Surrogate& S, Acts& a, hipStream_t s) {
@@ -799,10 +795,8 @@ void backward(const Surrogate& S, Acts& a, hipStream_t s) {
   }
   hipLaunchKernelGGL(act_bwd_kernel, dim3(grid1((int64_t)M * W)), dim3(256), 0, s, a.dH, a.Z[0],
                      M, W, (bf16*)nullptr, (bf16*)nullptr, a.dZ1);
-  hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(4 * W)), dim3(256), 0, s, a.gW[0], (int64_t)4 * W);
-  hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(W)), dim3(256), 0, s, a.gb[0], (int64_t)W);
-  hipLaunchKernelGGL(layer1_wgrad_kernel, dim3(W / 64, (M + 255) / 256), dim3(256), 0, s, a.X0,
-                     a.dZ1, M, a.gW[0], a.gb[0]);
+  hipLaunchKernelGGL(layer1_wgrad_kernel, dim3(W / 64), dim3(256), 0, s, a.X0, a.dZ1, M,
+                     a.gW[0], a.gb[0]);
 }
 
 void adam(Surrogate& S, Acts& a, int total_steps, float lr, hipStream_t s) {

@@ -2,11 +2,15 @@
 
 * the network's forward pass (BF16 MFMA GEMMs) equals a PyTorch CPU FP32
   evaluation of the same network with the same BF16 roundings;
-* with the range check, the sampled check and the line-sum fallback, the
-  per-cell absorbed and emitted power of the march driven by the surrogate
-  match the plain line-sum path within 1e-3 relative (the surrogate bar),
-  and out-of-range cells receive the exact line-sum kappa;
-* save / load reproduces the network exactly.
+* trained as the benchmark trains it (2^16 states, 40 epochs), the network's
+  kappa drives the 8^3 workload's march with at most half of the spectral
+  chunks falling back to the line sum, and the per-cell absorbed and emitted
+  power stay within 1e-3 relative of the plain line-sum path (the surrogate
+  bar, judged by the plain method);
+* a network that fails the sampled check everywhere falls back to the line
+  sum on every chunk, and out-of-range cells receive the exact line-sum
+  kappa;
+* training repeats bit for bit; save / load reproduces the network exactly.
 """
 import numpy as np
 import pytest
@@ -41,6 +45,36 @@ def trained(rt):
     t.close()
 
 
+@pytest.fixture(scope="module")
+def bench_trained(rt):
+    """The benchmark's training: 2^16 gas states, 40 epochs of batch 1024,
+    check tolerance 5e-4 on 32 sampled cells."""
+    w = I.plain_8cube()
+    t = rt.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(w.lines)
+    T, x, p = I.surrogate_samples(1 << 16, seed=0)
+    print("training the benchmark's surrogate (2^16 states, 40 epochs)", flush=True)
+    loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=40, batch=1024, lr=1e-3, seed=0,
+                             check_cells=32, tolerance=5e-4)
+    print(f"  loss {loss:.4e}", flush=True)
+    yield t, w
+    t.close()
+
+
+def _plain_run(rt, w):
+    """Tallies and kappa of the plain line-sum path on a handle of its own."""
+    r = rt.Tracer(0)
+    r.setup_grid(w.grid)
+    r.setup_lines(w.lines)
+    r.compute_kappa(rt.KAPPA_PLAIN, *r.alloc_tables())
+    r.trace_rays(w.seed, w.n_rays)
+    a0, e0, _ = r.tally()
+    k0 = r._tables[0].cpu().numpy()
+    r.close()
+    return a0, e0, k0
+
+
 def _bf16(a):
     import torch
     return torch.as_tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float32)
@@ -64,20 +98,67 @@ def test_forward_matches_torch(rt, trained):
     err = np.abs(got - ref).max()
     scale = 1.0 + np.abs(ref).max()
     print(f"forward max abs err {err:.3e} (scale {scale:.3e})", flush=True)
-    assert err <= 2e-2 * scale
+    # FP32 sums in another order can move a hidden activation across a BF16
+    # rounding boundary (2^-8 relative) now and then
+    assert err <= 5e-4 * scale
 
 
-def test_surrogate_tallies_within_1e3_of_plain(rt, trained):
+def test_trained_network_drives_the_march(rt, bench_trained):
+    """The learned form's contract on the 8^3 workload: the network's kappa
+    (not the fallback) drives the march for most chunks, and the per-cell
+    power stays within 1e-3 of the plain line sum's."""
+    t, w = bench_trained
+    a0, e0, k0 = _plain_run(rt, w)
+    kap, _ = t.alloc_tables()
+    t.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
+    st = t.surrogate_stats()
+    print("surrogate stats", st, flush=True)
+    print(f"fallback chunks: {st['fallback_chunks']} of {st['n_chunks']}", flush=True)
+    assert st["fallback_cells"] == 0
+    assert st["fallback_chunks"] <= st["n_chunks"] // 2
+    k1 = kap.cpu().numpy()
+    nz = w.lines.n_nu
+    from_net = [k for k in range(st["n_chunks"])
+                if not np.array_equal(k1[:, 256 * k:min(256 * (k + 1), nz)],
+                                      k0[:, 256 * k:min(256 * (k + 1), nz)])]
+    print(f"chunks whose kappa comes from the network: {len(from_net)}", flush=True)
+    # the fallback recomputes whole 512-point line-sum tiles, so a chunk that
+    # shares its tile with a fallback chunk is exact as well
+    assert len(from_net) >= st["n_chunks"] - 2 * st["fallback_chunks"] > 0
+    t.reset_tally()
+    t.trace_rays(w.seed, w.n_rays)
+    a1, e1, _ = t.tally()
+    ra = np.abs(a1 - a0)[a0 > 0] / a0[a0 > 0]
+    re_ = np.abs(e1 - e0)[e0 > 0] / e0[e0 > 0]
+    print(f"per-cell absorbed rel err max {ra.max():.3e} median {np.median(ra):.3e}, "
+          f"emitted max {re_.max():.3e}", flush=True)
+    assert ra.max() <= 1e-3 and re_.max() <= 1e-3
+
+
+def test_training_repeats_bit_for_bit(rt, bench_trained):
+    """A second training from the same seed and states gives the same
+    weights (fixed-order gradient sums, seeded shuffles)."""
+    t, w = bench_trained
+    u = rt.Tracer(0)
+    u.setup_grid(w.grid)
+    u.setup_lines(w.lines)
+    T, x, p = I.surrogate_samples(4096, seed=5)
+    runs = []
+    for _ in range(2):
+        u.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=2, batch=1024, lr=1e-3, seed=7,
+                          check_cells=8, tolerance=5e-4)
+        runs.append(u.surrogate_weights())
+    u.close()
+    for (W0, b0), (W1, b1) in zip(*runs):
+        assert np.array_equal(W0, W1) and np.array_equal(b0, b1)
+
+
+def test_fallback_keeps_tallies_within_1e3_of_plain(rt, trained):
+    """A briefly trained network (12 epochs on 4,096 states) fails the
+    sampled check on most chunks: the line-sum fallback recomputes them bit
+    for bit and the tallies stay within the 1e-3 bar."""
     t, w = trained
-    # plain line-sum reference on a separate handle
-    r = rt.Tracer(0)
-    r.setup_grid(w.grid)
-    r.setup_lines(w.lines)
-    r.compute_kappa(rt.KAPPA_PLAIN, *r.alloc_tables())
-    r.trace_rays(w.seed, w.n_rays)
-    a0, e0, b0 = r.tally()
-    k0 = r._tables[0].cpu().numpy()
-    r.close()
+    a0, e0, k0 = _plain_run(rt, w)
     kap, B = t.alloc_tables()
     t.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
     st = t.surrogate_stats()
