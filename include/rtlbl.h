@@ -126,7 +126,14 @@ typedef struct {
 
 /* Create a handle bound to HIP device `hip_device` and the borrowed stream
  * `hip_stream` (a hipStream_t; NULL = the null stream).  The stream is not
- * owned: it must outlive the handle. */
+ * owned: it must outlive the handle.
+ * hip_device = RT_NO_DEVICE (stream NULL) creates a host-only handle, for
+ * checking inputs where there is no GPU: it makes no HIP call, checks every
+ * call's arguments and the call order exactly as a device handle does
+ * (RT_EINVAL, RT_ESTATE), accepts rt_setup_grid and rt_setup_lines (keeping
+ * only their sizes and spectral grid), and returns RT_EUNSUPPORTED from every
+ * call that would run on a device. */
+#define RT_NO_DEVICE (-1)
 rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream);
 
 /* Synchronise the stream and free everything the handle owns. */

@@ -197,7 +197,10 @@ rt_status drain_events(rt_ctx c, std::vector<std::pair<hipEvent_t, hipEvent_t>>&
   return RT_OK;
 }
 
+// Makes the handle's device current; a host-only handle has none.
 rt_status set_device(rt_ctx c) {
+  if (c->device < 0)
+    return fail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_HIP(c, hipSetDevice(c->device));
   return RT_OK;
 }
@@ -240,6 +243,14 @@ extern "C" {
 rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream) {
   if (!out) return fail(nullptr, RT_EINVAL, "rt_create: out is NULL");
   *out = nullptr;
+  if (hip_device == RT_NO_DEVICE) {  // argument and call-order checks only
+    if (hip_stream) return fail(nullptr, RT_EINVAL, "rt_create: a host-only handle takes no stream");
+    rt_ctx c = new (std::nothrow) rt_ctx_s();
+    if (!c) return fail(nullptr, RT_ENOMEM, "rt_create: out of host memory");
+    c->device = RT_NO_DEVICE;
+    *out = c;
+    return RT_OK;
+  }
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess || n == 0)
@@ -273,6 +284,10 @@ rt_status rt_create(rt_ctx* out, int hip_device, void* hip_stream) {
 
 rt_status rt_destroy(rt_ctx c) {
   if (!c) return RT_OK;
+  if (c->device < 0) {  // host-only: no device memory, nothing in flight
+    delete c;
+    return RT_OK;
+  }
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   free_lines(c);
@@ -313,6 +328,18 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
     if (!(T[i] > 0)) return fail(c, RT_EINVAL, "rt_setup_grid: T must be > 0");
     if (!(x[i] >= 0 && x[i] <= 1)) return fail(c, RT_EINVAL, "rt_setup_grid: x_h2o must be in [0, 1]");
     if (!(p[i] > 0)) return fail(c, RT_EINVAL, "rt_setup_grid: p must be > 0");
+  }
+  if (c->device < 0) {  // host-only: record the grid, allocate nothing
+    free_gases(c);
+    c->nx = nx; c->ny = ny; c->nz = nz;
+    c->n_cells = n;
+    c->cell_m = cell_m;
+    c->T_wall = T_wall;
+    c->have_grid = true;
+    c->have_kappa = false;
+    c->cells_valid = false;
+    c->cells32_valid = false;
+    return RT_OK;
   }
   if (rt_status s = set_device(c)) return s;
   RT_HIP(c, hipStreamSynchronize(c->stream));
@@ -366,13 +393,10 @@ rt_status rt_setup_grid(rt_ctx c, int nx, int ny, int nz, double cell_m, const d
   return RT_OK;
 }
 
-// Validates one line list, keeps the lines whose window [m - K + [phi > 0],
-// m + K] meets [0, n_nu - 1], sorts them by r = (nu - nu0)/dnu = m + phi and
-// uploads them into L (device arrays allocated here; L must be empty).
-// evals: in-grid window points summed over the kept lines.
-rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, const double* S,
-                      const double* gamma, const double* n_T, const double* E, double T_ref,
-                      int K, double nu0, double dnu, int n_nu, rt::LineSet& L, double& evals) {
+// The per-line checks of rt_setup_lines and rt_setup_gas.
+rt_status check_line_arrays(rt_ctx c, const char* who, int n_lines, const double* nu,
+                            const double* S, const double* gamma, const double* n_T,
+                            const double* E) {
   const std::string w(who);
   if (n_lines < 0) return fail(c, RT_EINVAL, w + ": n_lines must be >= 0");
   if (n_lines > 0 && (!nu || !S || !gamma || !n_T))
@@ -387,6 +411,18 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
       if (E && !(E[i] >= 0)) return fail(c, RT_EINVAL, w + ": E_lower must be >= 0");
     }
   }
+  return RT_OK;
+}
+
+// Validates one line list, keeps the lines whose window [m - K + [phi > 0],
+// m + K] meets [0, n_nu - 1], sorts them by r = (nu - nu0)/dnu = m + phi and
+// uploads them into L (device arrays allocated here; L must be empty).
+// evals: in-grid window points summed over the kept lines.
+rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, const double* S,
+                      const double* gamma, const double* n_T, const double* E, double T_ref,
+                      int K, double nu0, double dnu, int n_nu, rt::LineSet& L, double& evals) {
+  const std::string w(who);
+  if (rt_status s = check_line_arrays(c, who, n_lines, nu, S, gamma, n_T, E)) return s;
   const double c2 = rt::second_radiation_cm_K();
   struct Rec { double r; int64_t m; double phi; int src; };
   std::vector<Rec> recs;
@@ -515,6 +551,22 @@ rt_status rt_setup_lines(rt_ctx c, int n_lines, const double* nu, const double* 
   if ((double)n_nu + 2.0 * Kr + 2.0 >= 16777216.0)
     return fail(c, RT_EINVAL, "rt_setup_lines: n_nu + 2*cutoff/dnu must stay below 2^24");
   const int K = (int)Kr;
+  if (c->device < 0) {  // host-only: check the lines, record the spectral grid
+    if (rt_status s = check_line_arrays(c, "rt_setup_lines", n_lines, nu, S, gamma, n_T, E))
+      return s;
+    free_gases(c);
+    c->have_E = E != nullptr;
+    c->n_nu = n_nu;
+    c->K = K;
+    c->nu0 = nu0;
+    c->dnu = dnu;
+    c->T_ref = T_ref;
+    c->have_lines = true;
+    c->have_kappa = false;
+    c->cells_valid = false;
+    c->cells32_valid = false;
+    return RT_OK;
+  }
   if (rt_status s = set_device(c)) return s;
   RT_HIP(c, hipStreamSynchronize(c->stream));
   free_lines(c);

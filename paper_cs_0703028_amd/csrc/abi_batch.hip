@@ -270,6 +270,7 @@ rt_status materialize(rt_ctx c, int n_cases, const rt_case* cases, BatchPlan& pl
     std::memcpy(&p[b.cell_off], cases[k].p_atm, b.n_cells * 8);
     Tw[k] = cases[k].T_wall_K;
   }
+  if (c->device < 0) return bfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_BHIP(c, hipSetDevice(c->device));
   RT_BHIP(c, hipMemcpy(pl.d_T, T.data(), T.size() * 8, hipMemcpyHostToDevice));
   RT_BHIP(c, hipMemcpy(pl.d_x, x.data(), x.size() * 8, hipMemcpyHostToDevice));
@@ -420,6 +421,7 @@ rt_status rt_batch_prepare(rt_ctx c, int n_cases, const rt_case* cases, int kapp
 rt_status rt_batch_launch(rt_ctx c) {
   if (!c) return RT_EINVAL;
   if (!c->batch || !c->batch->exec) return bfail(c, RT_ESTATE, "rt_batch_launch: call rt_batch_prepare first");
+  if (c->device < 0) return bfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_BHIP(c, hipSetDevice(c->device));
   hipEvent_t a, b;
   RT_BHIP(c, hipEventCreate(&a));
@@ -435,6 +437,7 @@ rt_status rt_batch_results(rt_ctx c, double* absorbed, double* emitted, double* 
   if (!c) return RT_EINVAL;
   if (!c->batch) return bfail(c, RT_ESTATE, "rt_batch_results: call rt_batch_prepare first");
   BatchPlan& pl = *c->batch;
+  if (c->device < 0) return bfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_BHIP(c, hipSetDevice(c->device));
   RT_BHIP(c, hipStreamSynchronize(c->stream));
   unsigned err = 0, ovf = 0;
@@ -477,6 +480,7 @@ rt_status rt_batch_run(rt_ctx c, int n_cases, const rt_case* cases, int kappa_mo
   if (!c) return RT_EINVAL;
   int64_t bytes = 0;
   if (rt_status s = rt_batch_workspace_size(c, n_cases, cases, tuning, &bytes)) return s;
+  if (c->device < 0) return bfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_BHIP(c, hipSetDevice(c->device));
   void* ws = nullptr;
   hipError_t e = hipMalloc(&ws, (size_t)bytes);

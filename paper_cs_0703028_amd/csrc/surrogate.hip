@@ -1093,6 +1093,7 @@ rt_status rt_surrogate_train(rt_ctx c, const rt_surrogate_cfg* cfg, double* fina
   for (int i = 0; i < n; ++i)
     if (!(cfg->T_K[i] > 0) || !(cfg->x_h2o[i] >= 0 && cfg->x_h2o[i] <= 1) || !(cfg->p_atm[i] > 0))
       return sfail(c, RT_EINVAL, "rt_surrogate_train: invalid sample state");
+  if (c->device < 0) return sfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_SHIP(c, hipSetDevice(c->device));
   free_surrogate(c);
   Surrogate& S = surrogate(c);
@@ -1358,6 +1359,7 @@ rt_status rt_surrogate_load(rt_ctx c, const char* path) {
   for (int l = 0; l < kMlpLayers; ++l) need += ((int64_t)kMlpDims[l] * kMlpDims[l + 1] + kMlpDims[l + 1]) * 4;
   need += 2LL * hdr[2] * kMlpWidth * 4;
   if ((int64_t)blob.size() != (int64_t)off + need + 8) return sfail(c, RT_EINVAL, "rt_surrogate_load: size mismatch");
+  if (c->device < 0) return sfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_SHIP(c, hipSetDevice(c->device));
   free_surrogate(c);
   Surrogate& S = surrogate(c);

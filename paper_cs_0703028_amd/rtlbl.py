@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtlbl.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RT_NO_DEVICE = -1    # rt_create: a host-only handle (argument and call-order checks)
 (KAPPA_PLAIN, KAPPA_COMPENSATED, KAPPA_SURROGATE, KAPPA_TABLE16, KAPPA_ADAPTIVE,
  KAPPA_ADAPTIVE_WINGS) = 0, 1, 2, 3, 4, 5
 ADAPTIVE_GROUP = 8   # RT_ADAPTIVE_GROUP: cells sharing one line window
@@ -176,6 +177,24 @@ class Tracer:
         self.grid = None
         self.lines = None
         self._tables = None
+
+    @classmethod
+    def host_only(cls) -> "Tracer":
+        """A host-only handle (RT_NO_DEVICE): it checks arguments and the call
+        order like a device handle and runs nothing on a device."""
+        obj = cls.__new__(cls)
+        obj.device = None
+        obj.stream = None
+        h = C.c_void_p()
+        s = lib.rt_create(C.byref(h), RT_NO_DEVICE, None)
+        if s != RT_OK:
+            raise RtError(s, lib.rt_last_error(None).decode())
+        obj._h = h
+        obj.grid = None
+        obj.lines = None
+        obj._tables = None
+        obj.gases = {}
+        return obj
 
     # ------------------------------------------------------------ plumbing
     def _check(self, s):
