@@ -42,6 +42,10 @@ TRANS_SLOTS = 2.0
 # (1 FMA): 4 FP32 flops in 2 full-rate slots plus one half-rate reciprocal.
 LINE_FLOPS_PER_EVAL = 4.0
 LINE_SLOTS_PER_EVAL = 2.0 + TRANS_SLOTS
+# MI355X published vector peaks: FP32 157.3 TFLOP/s counts packed (dual) FP32
+# FMAs, which this build does not use; one FMA per lane and cycle is 78.6.
+FP32_PUBLISHED_PEAK = 157.3e12
+FP32_UNPACKED_FMA_PEAK = 78.6e12
 BF16_DENSE_PEAK = 2.5e15
 MLP_WEIGHTS = 4 * 512 + 512 * 512 + 512 * 512 + 512 * 256
 TUNING_CACHE = os.path.join(ROOT, "paper_cs_0703028_amd", "tuning", "batch_tune.json")
@@ -644,13 +648,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "cells": w.grid.n_cells, "lines": int(len(w.lines.nu)),
                    "n_nu": w.lines.n_nu, "rays": w.n_rays, "kappa_mode": "plain",
-                   "tally": "f32 partials, f64 accumulators"},
+                   "tally": "f32 partials, exact fixed-point accumulators"},
         "kappa_ms_per_step": kappa_ms / args.steps,
         "march_ms_per_step": march_ms / args.steps,
         "line_evals_per_s": line_rate,
         "line_sum_alu": {"achieved": line_rate * LINE_FLOPS_PER_EVAL / 1e12,
                          "peak": line_peak_evals_per_s() * LINE_FLOPS_PER_EVAL / 1e12,
-                         "unit": "TFLOP/s", "frac": line_rate / line_peak_evals_per_s()},
+                         "unit": "TFLOP/s", "frac": line_rate / line_peak_evals_per_s(),
+                         "frac_of_published_fp32_peak":
+                             line_rate * LINE_FLOPS_PER_EVAL / FP32_PUBLISHED_PEAK,
+                         "frac_of_unpacked_fp32_fma_peak":
+                             line_rate * LINE_FLOPS_PER_EVAL / FP32_UNPACKED_FMA_PEAK},
         "trace_updates_per_s": march_rate,
         "energy_balance_rel": float(abs(bal[0] + bal[1] - bal[2] - bal[3]) / (bal[0] + bal[1])),
         "roofline": {
@@ -660,6 +668,17 @@ def main():
             "peak": peak * MARCH_FLOPS_PER_UPDATE / 1e12,
             "unit": "TFLOP/s",
             "frac": march_rate / peak,
+            # the same achieved rate against MI355X's published FP32 vector
+            # peak (packed FMAs), and against one FMA per lane and cycle
+            "published_fp32_peak": FP32_PUBLISHED_PEAK / 1e12,
+            "frac_of_published_fp32_peak":
+                march_rate * MARCH_FLOPS_PER_UPDATE / FP32_PUBLISHED_PEAK,
+            "frac_of_unpacked_fp32_fma_peak":
+                march_rate * MARCH_FLOPS_PER_UPDATE / FP32_UNPACKED_FMA_PEAK,
+            "peak_derivation": ("256 CUs x 64 lanes x 2.4 GHz = 39.32e12 lane-slots/s; an update "
+                                "takes 6 full-rate slots and one base-2 exponential issued at "
+                                "half rate (2 slots, profiles/alu_rates_probe.md): 8 slots, "
+                                "9 flops"),
             "traffic": traffic,
             "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
             # those bytes over the launch time: the rate past L2 (Infinity
