@@ -416,7 +416,10 @@ typedef struct {
   int fallback_chunks;        /* chunks recomputed with the line sum         */
   int fallback_cells;         /* out-of-range cells recomputed               */
   int n_chunks;
-  double infer_ms, check_ms, fallback_ms;  /* device times, last inference   */
+  double infer_ms, check_ms, fallback_ms;  /* device times, last inference:
+                                 the network; from its end to the end of the
+                                 check (whose exact line sum runs beside the
+                                 network on a second stream); the fallback  */
   double train_loss;          /* mean squared normalised error, last epoch   */
   double param_count;
 } rt_surrogate_stats;

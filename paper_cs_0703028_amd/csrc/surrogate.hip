@@ -151,45 +151,69 @@ __global__ void act_bwd_kernel(const float* __restrict__ dH, const float* __rest
   if (dZT) dZT[(int64_t)n * M + m] = (bf16)g;
 }
 
-// db[n] = sum_m G[m][n] (FP32 or BF16 source): one block per 64 columns over
-// all M rows, 4 row groups (rows g, g + 4, ...) reduced in LDS in a fixed
-// order, so training repeats bit for bit.
+// Column sums in two passes with a fixed order (training repeats bit for
+// bit): pass 1, one block per (64 columns, 64 rows), 4 row groups (rows g,
+// g + 4, ...) reduced in LDS into part[row block][column]; pass 2 adds the
+// row blocks' partials in order.
+// db[n] = sum_m G[m][n] (FP32 or BF16 source), pass 1.
 template <class T>
 __global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ G, int M, int N,
-                                                     float* db) {
+                                                     float* part) {
   __shared__ float red[4][64];
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + c;
+  const int m0 = blockIdx.y * 64;
   float s = 0.f;
   if (n < N)
-    for (int m = g; m < M; m += 4) s += (float)G[(int64_t)m * N + n];
+    for (int m = m0 + g; m < min(m0 + 64, M); m += 4) s += (float)G[(int64_t)m * N + n];
   red[g][c] = s;
   __syncthreads();
-  if (g == 0 && n < N) db[n] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  if (g == 0 && n < N)
+    part[(int64_t)blockIdx.y * N + n] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
 }
 
-// dW1[k][n] = sum_m X0[m][k] dZ1[m][n] and db1[n] = sum_m dZ1[m][n], same
-// decomposition and fixed order as colsum_kernel.
+// out[i] = sum_b part[b][i] over nb row blocks, in order (pass 2).
+__global__ void sum_blocks_kernel(const float* __restrict__ part, int nb, int n, float* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * n + i];
+  out[i] = s;
+}
+
+// dW1[k][n] = sum_m X0[m][k] dZ1[m][n] and db1[n] = sum_m dZ1[m][n], pass 1
+// (part[row block][q][n], q = k or 4 for the bias), same decomposition.
 __global__ __launch_bounds__(256) void layer1_wgrad_kernel(const float* __restrict__ X0,
                                                            const float* __restrict__ dZ1, int M,
-                                                           float* dW1, float* db1) {
+                                                           float* part) {
   __shared__ float red[5][4][64];
   const int N = kMlpDims[1];
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + c;
+  const int m0 = blockIdx.y * 64;
   float s[5] = {0, 0, 0, 0, 0};
-  for (int m = g; m < M; m += 4) {
+  for (int m = m0 + g; m < min(m0 + 64, M); m += 4) {
     const float d = dZ1[(int64_t)m * N + n];
     for (int k = 0; k < 4; ++k) s[k] = fmaf(X0[4 * m + k], d, s[k]);
     s[4] += d;
   }
   for (int q = 0; q < 5; ++q) red[q][g][c] = s[q];
   __syncthreads();
-  if (g == 0) {
-    for (int k = 0; k < 4; ++k)
-      dW1[k * N + n] = (red[k][0][c] + red[k][1][c]) + (red[k][2][c] + red[k][3][c]);
-    db1[n] = (red[4][0][c] + red[4][1][c]) + (red[4][2][c] + red[4][3][c]);
-  }
+  if (g == 0)
+    for (int q = 0; q < 5; ++q)
+      part[((int64_t)blockIdx.y * 5 + q) * N + n] =
+          (red[q][0][c] + red[q][1][c]) + (red[q][2][c] + red[q][3][c]);
+}
+
+// dW1 [4][N] and db1 [N] from the pass-1 partials of layer1_wgrad_kernel.
+__global__ void layer1_sum_kernel(const float* __restrict__ part, int nb, float* dW1, float* db1) {
+  const int N = kMlpDims[1];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // q * N + n
+  if (i >= 5 * N) return;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * 5 * N + i];
+  if (i < 4 * N) dW1[i] = s;
+  else db1[i - 4 * N] = s;
 }
 
 __global__ void zero_f32_kernel(float* p, int64_t n) {
@@ -608,27 +632,28 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(float* __restrict__ x, i
   x[i] = v;
 }
 
-__global__ __launch_bounds__(256) void check_kernel(const float* __restrict__ kappa, int64_t ld,
-                                                    const float* __restrict__ exact, int64_t ld_e,
-                                                    const int32_t* __restrict__ cells, int n_check,
-                                                    int n_nu, float l_cm,
-                                                    const unsigned* __restrict__ cell_flag,
-                                                    unsigned epoch, float* err) {
+// One block of 1024 threads per chunk: thread t owns point k * 256 + t % 256
+// of the sampled cells t / 256, t / 256 + 4, ...; the block's sums are
+// reduced in a fixed tree.
+constexpr int kCheckThreads = 1024;
+__global__ __launch_bounds__(kCheckThreads) void check_kernel(
+    const float* __restrict__ kappa, int64_t ld, const float* __restrict__ exact, int64_t ld_e,
+    const int32_t* __restrict__ cells, int n_check, int n_nu, float l_cm,
+    const unsigned* __restrict__ cell_flag, unsigned epoch, float* err) {
   const int k = blockIdx.x;  // chunk
   const int t = threadIdx.x;
+  constexpr int kGroups = kCheckThreads / kMlpWidth;
   __shared__ int64_t row[kMaxCheckCells];  // kappa row offset, -1: left out
-  __shared__ float rd[256], rs[256];
-  for (int ci = t; ci < n_check; ci += 256) {
+  __shared__ float rd[kCheckThreads], rs[kCheckThreads];
+  for (int ci = t; ci < n_check; ci += kCheckThreads) {
     const int cell = cells[ci];
     row[ci] = cell_flag[cell] == epoch ? -1 : (int64_t)cell * ld;
   }
   __syncthreads();
-  // thread t owns point k * 256 + t of every sampled cell
-  const int j = k * kMlpWidth + t;
+  const int j = k * kMlpWidth + (t % kMlpWidth);
   float d = 0, s = 0;
   if (j < n_nu) {
-#pragma unroll 4
-    for (int ci = 0; ci < n_check; ++ci) {
+    for (int ci = t / kMlpWidth; ci < n_check; ci += kGroups) {
       if (row[ci] < 0) continue;
       const float e = -expm1f(-exact[(int64_t)ci * ld_e + j] * l_cm);
       const float g = -expm1f(-kappa[row[ci] + j] * l_cm);
@@ -639,7 +664,7 @@ __global__ __launch_bounds__(256) void check_kernel(const float* __restrict__ ka
   rd[t] = d;
   rs[t] = s;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = kCheckThreads / 2; off > 0; off >>= 1) {
     if (t < off) { rd[t] += rd[t + off]; rs[t] += rs[t + off]; }
     __syncthreads();
   }
@@ -714,6 +739,7 @@ struct Acts {
   float *X0 = nullptr, *Z[3] = {}, *P = nullptr, *Y = nullptr, *dH = nullptr, *dZ1 = nullptr;
   bf16 *H[3] = {}, *HT[3] = {}, *dP = nullptr, *dPT = nullptr, *dZ[3] = {}, *dZT[3] = {};
   float *gW[kMlpLayers] = {}, *gb[kMlpLayers] = {};
+  float* part = nullptr;  // column-sum partials: [M / 64][5][512]
   int32_t* row_chunk = nullptr;
   double* sse = nullptr;
   int* step = nullptr;
@@ -721,6 +747,7 @@ struct Acts {
     dfree(X0); dfree(P); dfree(Y); dfree(dH); dfree(dZ1); dfree(dP); dfree(dPT);
     for (int l = 0; l < 3; ++l) { dfree(Z[l]); dfree(H[l]); dfree(HT[l]); dfree(dZ[l]); dfree(dZT[l]); }
     for (int l = 0; l < kMlpLayers; ++l) { dfree(gW[l]); dfree(gb[l]); }
+    dfree(part);
     dfree(row_chunk); dfree(sse); dfree(step);
   }
 };
@@ -738,6 +765,7 @@ rt_status alloc_acts(rt_ctx c, Acts& a, int M, bool train) {
   RT_SHIP(c, dalloc(&a.Y, (int64_t)M * kMlpWidth));
   RT_SHIP(c, dalloc(&a.dH, (int64_t)M * W));
   RT_SHIP(c, dalloc(&a.dZ1, (int64_t)M * W));
+  RT_SHIP(c, dalloc(&a.part, (int64_t)(M / 64) * 5 * W));
   RT_SHIP(c, dalloc(&a.dP, (int64_t)M * kMlpWidth));
   RT_SHIP(c, dalloc(&a.dPT, (int64_t)M * kMlpWidth));
   for (int l = 0; l < 3; ++l) {
@@ -776,26 +804,31 @@ void forward(const Surrogate& S, Acts& a, bool train, hipStream_t s) {
                      S.b[3], M, kMlpWidth);
 }
 
-void colsum_bf16(const bf16* G, int M, int N, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel<bf16>, dim3((N + 63) / 64), dim3(256), 0, s, G, M, N, db);
+void colsum_bf16(const bf16* G, int M, int N, float* part, float* db, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_kernel<bf16>, dim3((N + 63) / 64, M / 64), dim3(256), 0, s, G, M, N,
+                     part);
+  hipLaunchKernelGGL(sum_blocks_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, M / 64, N,
+                     db);
 }
 
 void backward(const Surrogate& S, Acts& a, hipStream_t s) {
   const int M = a.M, W = 512, O = kMlpWidth;
   // layer 4: dW4^T [256][512] = dP^T H3^T^T ; dH3 = dP W4
   gemm(a.dPT, M, a.HT[2], M, a.gW[3], W, O, W, M, s);
-  colsum_bf16(a.dP, M, O, a.gb[3], s);
+  colsum_bf16(a.dP, M, O, a.part, a.gb[3], s);
   gemm(a.dP, O, S.wk[3], O, a.dH, W, M, W, O, s);
   for (int l = 2; l >= 1; --l) {  // hidden layers 3 and 2
     hipLaunchKernelGGL(act_bwd_kernel, dim3(grid1((int64_t)M * W)), dim3(256), 0, s, a.dH,
                        a.Z[l], M, W, a.dZ[l], a.dZT[l], (float*)nullptr);
     gemm(a.dZT[l], M, a.HT[l - 1], M, a.gW[l], W, W, W, M, s);
-    colsum_bf16(a.dZ[l], M, W, a.gb[l], s);
+    colsum_bf16(a.dZ[l], M, W, a.part, a.gb[l], s);
     gemm(a.dZ[l], W, S.wk[l], W, a.dH, W, M, W, W, s);
   }
   hipLaunchKernelGGL(act_bwd_kernel, dim3(grid1((int64_t)M * W)), dim3(256), 0, s, a.dH, a.Z[0],
                      M, W, (bf16*)nullptr, (bf16*)nullptr, a.dZ1);
-  hipLaunchKernelGGL(layer1_wgrad_kernel, dim3(W / 64), dim3(256), 0, s, a.X0, a.dZ1, M,
+  hipLaunchKernelGGL(layer1_wgrad_kernel, dim3(W / 64, M / 64), dim3(256), 0, s, a.X0, a.dZ1, M,
+                     a.part);
+  hipLaunchKernelGGL(layer1_sum_kernel, dim3((5 * W + 255) / 256), dim3(256), 0, s, a.part, M / 64,
                      a.gW[0], a.gb[0]);
 }
 
@@ -901,6 +934,9 @@ void free_surrogate(rt_ctx c) {
   dfree(S.d_exact);
   for (auto& e : S.ev)
     if (e) (void)hipEventDestroy(e);
+  if (S.fork) (void)hipEventDestroy(S.fork);
+  if (S.join) (void)hipEventDestroy(S.join);
+  if (S.side) (void)hipStreamDestroy(S.side);
   delete c->surrogate;
   c->surrogate = nullptr;
 }
@@ -909,11 +945,12 @@ bool surrogate_ready(rt_ctx c) {
   return c->surrogate && c->surrogate->trained && c->surrogate->n_nu == c->n_nu;
 }
 
-// Learned kappa into c->kappa, four stream-ordered launches with every
-// decision taken on the device (no host round trip):
+// Learned kappa into c->kappa, stream-ordered launches with every decision
+// taken on the device (no host round trip):
 //   1. the fused network writes kappa and marks cells outside the training
 //      box (and their line-sum groups) with this call's epoch;
-//   2. exact rows of the sampled cells;
+//   2. exact rows of the sampled cells, on the side stream beside step 1
+//      (forked after the handle's stream's earlier work, joined before 3);
 //   3. the checked error per chunk (marked cells left out);
 //   4. the line sum over every tile that touches a chunk over tolerance or a
 //      marked group of cells.
@@ -963,6 +1000,14 @@ rt_status surrogate_kappa(rt_ctx c) {
   }
   for (auto& e : S.ev)
     if (!e && hipEventCreate(&e) != hipSuccess) return sfail(c, RT_EDEVICE, "surrogate: event");
+  if (!S.side) {
+    if (hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S.join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return sfail(c, RT_EDEVICE, "surrogate: side stream");
+    }
+  }
 
   if (S.pick_epoch != c->grid_epoch && n_check > 0) {
     // sampled cells: the coldest and the hottest (where the network is least
@@ -998,11 +1043,10 @@ rt_status surrogate_kappa(rt_ctx c) {
   t.col_end = c->ld;
   const int tiles_all = (int)((c->ld + dev::kKappaTilePoints - 1) / dev::kKappaTilePoints);
 
-  (void)hipEventRecord(S.ev[0], s);
-  launch_fused(c, S, rows, nullptr, nullptr, true, s);
-  ok = ok && chk(hipGetLastError());
-  (void)hipEventRecord(S.ev[1], s);
+  // the exact rows of the sampled cells do not depend on the network: they
+  // are summed on the side stream while the network runs
   if (ok && n_check > 0) {
+    ok = chk(hipEventRecord(S.fork, s)) && chk(hipStreamWaitEvent(S.side, S.fork, 0));
     dev::KappaTile te = t;
     te.cell_list = S.d_check;
     te.n_cells = n_check;
@@ -1010,13 +1054,22 @@ rt_status surrogate_kappa(rt_ctx c) {
     te.compact_rows = 1;
     const int parts = check_parts(c, n_check);
     const int64_t part_stride = (int64_t)n_check * c->ld;
-    ok = chk(launch_kappa_tiles(c, te, (n_check + dev::kKappaCells - 1) / dev::kKappaCells, 0,
-                                tiles_all, false, s, dev::TileGate(), parts, part_stride));
+    ok = ok && chk(launch_kappa_tiles(c, te, (n_check + dev::kKappaCells - 1) / dev::kKappaCells,
+                                      0, tiles_all, false, S.side, dev::TileGate(), parts,
+                                      part_stride));
     if (ok && parts > 1)
-      hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)grid1(part_stride)), dim3(256), 0, s,
-                         S.d_exact, part_stride, parts, part_stride);
+      hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)grid1(part_stride)), dim3(256), 0,
+                         S.side, S.d_exact, part_stride, parts, part_stride);
+    ok = ok && chk(hipGetLastError()) && chk(hipEventRecord(S.join, S.side));
+  }
+  (void)hipEventRecord(S.ev[0], s);
+  launch_fused(c, S, rows, nullptr, nullptr, true, s);
+  ok = ok && chk(hipGetLastError());
+  (void)hipEventRecord(S.ev[1], s);
+  if (ok && n_check > 0) {
+    ok = chk(hipStreamWaitEvent(s, S.join, 0));
     if (ok)
-      hipLaunchKernelGGL(check_kernel, dim3(S.n_chunks), dim3(256), 0, s, c->kappa, c->ld,
+      hipLaunchKernelGGL(check_kernel, dim3(S.n_chunks), dim3(kCheckThreads), 0, s, c->kappa, c->ld,
                          S.d_exact, c->ld, S.d_check, n_check, c->n_nu,
                          (float)(c->cell_m * 100.0), S.d_cell_flag, S.epoch, S.d_err);
   } else if (ok) {
