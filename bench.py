@@ -232,18 +232,25 @@ def form_precision(rtlbl, I):
 
 def form_batched(rtlbl, I):
     """Batched form: 64 receiver cases (16^3-48^3 cells, 2^14-2^18 rays, 5,000
-    lines, 20,000 points) in one persistent, graph-captured launch, with the
+    lines, 20,000 points) in one graph launch, with the launch shape and
     tuning looked up in (or written to) the autotuner's cache."""
     import numpy as np
     import torch
     cases = I.batched_cases(64)
     t = rtlbl.Tracer(0)
     t.setup_lines(cases[0].lines)
+    # room for the largest trial of either launch shape
     big = rtlbl.Tracer.default_tuning()
     big.chunk_points = 4 * rtlbl.MARCH_CHUNK
     big.blocks_per_cu = 4
     big.slots = 8
-    ws = torch.empty(t.batch_workspace_size(cases, big), dtype=torch.uint8, device="cuda")
+    big.mode = rtlbl.BATCH_PERSISTENT
+    nbytes = t.batch_workspace_size(cases, big)
+    big.mode = rtlbl.BATCH_CHUNKED  # one slab of 3072 points for every cell
+    big.chunk_points = 2 * rtlbl.MARCH_CHUNK
+    big.slots = 1
+    nbytes = max(nbytes, t.batch_workspace_size(cases, big))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     t0 = time.perf_counter()
     best = t.batch_autotune(cases, rtlbl.KAPPA_PLAIN, ws, TUNING_CACHE)
     tune_s = time.perf_counter() - t0

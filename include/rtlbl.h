@@ -305,11 +305,21 @@ rt_status rt_get_stats(rt_ctx ctx, rt_stats* out);
 /* ------------------------------------------------------------------------
  * Batched form: many independent receiver cases (each its own grid, wall
  * temperature, ray count and seed) sharing the line list and spectral grid
- * of rt_setup_lines, run as one persistent work-queue kernel captured in a
- * HIP graph.  The line sum and the march are fused per (case, spectral
- * chunk): the chunk's kappa is built into one of `slots` slabs and marched
- * at once, so no full kappa table is ever stored.  Plain-form march
- * (rt_tally_prec RT_TALLY_F32); kappa_mode as rt_compute_kappa.
+ * of rt_setup_lines, run as one HIP graph launch.  The line sum and the
+ * march are fused per spectral chunk: a chunk's kappa is built into a slab
+ * and marched at once, so no full kappa table is ever stored.  Two launch
+ * shapes give the same tallies bit for bit:
+ *   RT_BATCH_CHUNKED    per chunk, one line-sum launch over the cells of
+ *                       every case into a slab of all cells, then one march
+ *                       launch over the rays of every case; with slots > 1
+ *                       the line sums run on a second stream, up to
+ *                       slots - 1 chunks ahead of the marches
+ *                       (kappa_groups, march_rays, blocks_per_cu unused);
+ *   RT_BATCH_PERSISTENT one persistent work-queue kernel over (case, chunk)
+ *                       pairs, each pair's kappa in one of `slots` slabs of
+ *                       the largest case (less memory).
+ * Plain-form march (rt_tally_prec RT_TALLY_F32); kappa_mode as
+ * rt_compute_kappa.
  * ---------------------------------------------------------------------- */
 typedef struct {
   int nx, ny, nz;        /* as rt_setup_grid                                */
@@ -322,20 +332,27 @@ typedef struct {
   uint64_t n_rays;       /* >= 1                                            */
 } rt_case;
 
+enum { RT_BATCH_CHUNKED = 0, RT_BATCH_PERSISTENT = 1 };
+
 typedef struct {
-  int chunk_points;   /* nu points per (case, chunk) pair, multiple of 1536 */
-  int kappa_groups;   /* groups of 8 cells per line-sum work item, >= 1     */
-  int march_rays;     /* rays per march work item, multiple of 4            */
-  int blocks_per_cu;  /* persistent blocks per compute unit, 1..8           */
-  int slots;          /* kappa slabs in flight, 2..8                        */
+  int chunk_points;   /* nu points per spectral chunk, multiple of
+                         rt_march_chunk() (1536)                            */
+  int kappa_groups;   /* persistent: groups of 8 cells per line-sum item    */
+  int march_rays;     /* persistent: rays per march item, multiple of 4     */
+  int blocks_per_cu;  /* persistent: blocks per compute unit, 1..8          */
+  int slots;          /* kappa slabs in flight: persistent 2..8, chunked
+                         1..8                                               */
+  int mode;           /* RT_BATCH_CHUNKED or RT_BATCH_PERSISTENT            */
 } rt_batch_tuning;
 
-/* A tuning that is valid for any batch (2048, 16, 64, 2, 3). */
+/* A tuning that is valid for any batch: chunked, 3072 points per chunk,
+ * one slab (persistent fields 16, 64, 2; the queue needs slots >= 2). */
 rt_status rt_batch_default_tuning(rt_batch_tuning* out);
 
 /* Device workspace the batch needs with this tuning (tuning NULL: default):
- * segments of every ray, `slots` kappa slabs of the largest case, per-case
- * tables, accumulators and the work plan. */
+ * segments of every ray, `slots` kappa slabs (chunked: chunk_points for
+ * every cell of every case; persistent: for the largest case),
+ * per-case tables, accumulators and the work plan. */
 rt_status rt_batch_workspace_size(rt_ctx ctx, int n_cases, const rt_case* cases,
                                   const rt_batch_tuning* tuning, int64_t* bytes);
 
@@ -348,8 +365,8 @@ rt_status rt_batch_prepare(rt_ctx ctx, int n_cases, const rt_case* cases,
                            void* workspace_dev, int64_t workspace_bytes);
 
 /* One launch of the prepared graph on the handle's stream (asynchronous):
- * clears the accumulators, runs the persistent kernel over all cases and
- * reduces the per-case balances.  May be repeated. */
+ * clears the accumulators, traces all cases and reduces the per-case
+ * balances.  May be repeated. */
 rt_status rt_batch_launch(rt_ctx ctx);
 
 /* Synchronises and copies the results of the last launch: absorbed_W and
@@ -370,7 +387,7 @@ rt_status rt_batch_run(rt_ctx ctx, int n_cases, const rt_case* cases, int kappa_
                        const rt_batch_tuning* tuning, double* absorbed_W, double* emitted_W,
                        double* balance);
 
-/* Picks chunk_points, kappa_groups, march_rays, blocks_per_cu and slots by timing
+/* Picks the mode, chunk_points, kappa_groups, march_rays, blocks_per_cu and slots by timing
  * launches restricted to the first spectral chunks of every case (a sweep
  * one parameter at a time from the default), and remembers the winner in a
  * JSON file keyed by device architecture and a bucket of the batch shape

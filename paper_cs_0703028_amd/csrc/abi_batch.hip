@@ -38,7 +38,8 @@ rt_batch_tuning default_tuning() {
   t.kappa_groups = 16;
   t.march_rays = 64;
   t.blocks_per_cu = 2;
-  t.slots = 3;
+  t.slots = 1;
+  t.mode = RT_BATCH_CHUNKED;
   return t;
 }
 
@@ -46,6 +47,12 @@ rt_status check_tuning(rt_ctx c, const rt_batch_tuning& t) {
   if (t.chunk_points < kChunk || t.chunk_points % kChunk != 0 || t.chunk_points > (1 << 20))
     return bfail(c, RT_EINVAL, "rt_batch: chunk_points must be a positive multiple of " +
                                    std::to_string(kChunk));
+  if (t.mode != RT_BATCH_CHUNKED && t.mode != RT_BATCH_PERSISTENT)
+    return bfail(c, RT_EINVAL, "rt_batch: mode must be RT_BATCH_CHUNKED or RT_BATCH_PERSISTENT");
+  if (t.mode == RT_BATCH_CHUNKED) {  // kappa_groups, march_rays, blocks_per_cu unused
+    if (t.slots < 1 || t.slots > 8) return bfail(c, RT_EINVAL, "rt_batch: slots must be in 1..8");
+    return RT_OK;
+  }
   if (t.kappa_groups < 1 || t.kappa_groups > (1 << 20))
     return bfail(c, RT_EINVAL, "rt_batch: kappa_groups must be >= 1");
   if (t.march_rays < 4 || t.march_rays % 4 != 0 || t.march_rays > (1 << 20))
@@ -88,12 +95,13 @@ int64_t align_up(int64_t v) { return (v + 255) / 256 * 256; }
 rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch_tuning& t,
                      int64_t limit_points, BatchPlan& pl, int64_t* bytes) {
   pl.tuning = t;
+  pl.chunked = t.mode == RT_BATCH_CHUNKED;
   pl.n_cases = n_cases;
   const int64_t n_nu = limit_points > 0 ? std::min<int64_t>(limit_points, c->n_nu) : c->n_nu;
   pl.n_chunks = (int)((n_nu + t.chunk_points - 1) / t.chunk_points);
   pl.bwall_ld = (int64_t)pl.n_chunks * t.chunk_points;
   pl.cases.assign(n_cases, BatchCase());
-  int64_t cell_off = 0, seg_off = 0, ray_off = 0, max_cells = 0;
+  int64_t cell_off = 0, seg_off = 0, ray_off = 0, blk_off = 0, max_cells = 0;
   double evals = 0;
   double T_min = INFINITY, T_max = 0;
   for (int k = 0; k < n_cases; ++k) {
@@ -113,6 +121,7 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
       return bfail(c, RT_EINVAL, "rt_batch: n_rays x spectral chunks of a case must be <= 2^35");
     b.seg_off = seg_off;
     b.ray_off = ray_off;
+    b.blk_off = blk_off;
     b.seed = q.seed;
     const double h = q.cell_m;
     const double area = 2.0 * h * h * ((double)q.nx * q.ny + (double)q.ny * q.nz + (double)q.nz * q.nx);
@@ -128,18 +137,25 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
     cell_off += b.n_cells;
     seg_off += b.n_rays * b.max_segs;
     ray_off += b.n_rays;
+    // march blocks of 4 rays, an eighth per XCD, for each kChunk part
+    blk_off += (int64_t)(t.chunk_points / kChunk) * (((b.n_rays + 3) / 4 + 7) / 8);
     max_cells = std::max(max_cells, b.n_cells);
     evals += c->line_evals_per_cell * (double)b.n_cells;
   }
   pl.total_cells = cell_off;
   pl.total_rays = ray_off;
+  pl.ray_blocks = blk_off;
+  if (pl.chunked && 8 * blk_off > 0x7fffffffLL)
+    return bfail(c, RT_EINVAL, "rt_batch: too many rays for one chunked march launch "
+                               "(use RT_BATCH_PERSISTENT or fewer chunk_points)");
   pl.planck_quad = planck_needs_quadratic(T_min, T_max, c->nu0, c->dnu, c->n_nu);
   pl.max_cells = max_cells;
   pl.line_evals = limit_points > 0 ? 0.0 : evals;
-  pl.slab_stride = max_cells * t.chunk_points;
+  pl.slab_stride = (pl.chunked ? cell_off : max_cells) * t.chunk_points;
+  const int n_slabs = t.slots;
   pl.n_pairs = n_cases * pl.n_chunks;
 
-  // stages
+  // stages of the persistent queue
   pl.stages.clear();
   std::vector<int> rg_stage(n_cases), k_stage(pl.n_pairs), m_stage(pl.n_pairs);
   const int tiles = t.chunk_points / dev::kKappaTilePoints;
@@ -152,7 +168,9 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
     pl.stages.push_back(s);
     return (int)pl.stages.size() - 1;
   };
-  for (int k = 0; k < n_cases; ++k) rg_stage[k] = add(kStageRaygen, k, 0, -1, (pl.cases[k].n_rays + 255) / 256);
+  if (!pl.chunked)
+    for (int k = 0; k < n_cases; ++k)
+      rg_stage[k] = add(kStageRaygen, k, 0, -1, (pl.cases[k].n_rays + 255) / 256);
   auto pair_case = [&](int p) { return p / pl.n_chunks; };
   auto pair_chunk = [&](int p) { return p % pl.n_chunks; };
   auto add_k = [&](int p) {
@@ -169,6 +187,7 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   // ahead of the march, K(0) .. K(L-1), then K(p + L) M(p) for every p, with
   // L = slots - 1; K(p + L) reuses the slab of M(p - 1), which precedes it
   const int L = std::max(1, t.slots - 1);
+  if (pl.chunked) pl.n_pairs = 0;  // no queue
   for (int p = 0; p < std::min(L, pl.n_pairs); ++p) add_k(p);
   for (int p = 0; p < pl.n_pairs; ++p) {
     if (p + L < pl.n_pairs) add_k(p + L);
@@ -203,7 +222,7 @@ rt_status build_plan(rt_ctx c, int n_cases, const rt_case* cases, const rt_batch
   int64_t o_segs = take(seg_off * 8), o_cnt = take(ray_off * 4);
   int64_t o_keys = take(ray_off * 4), o_perm = take(ray_off * 4);
   int64_t o_hist = take((int64_t)n_cases * kOrderBuckets * 4);
-  int64_t o_slab = take((int64_t)t.slots * pl.slab_stride * 4);
+  int64_t o_slab = take((int64_t)n_slabs * pl.slab_stride * 4);
   int64_t o_ctr = take(pl.n_counters * 4);
   int64_t o_st = take((int64_t)pl.n_stages * sizeof(BatchStage));
   int64_t o_cases = take((int64_t)n_cases * sizeof(BatchCase));
@@ -255,6 +274,8 @@ void release_plan(rt_ctx c) {
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
+  if (pl->side_stream) (void)hipStreamDestroy(pl->side_stream);
+  for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
   delete pl;
   c->batch = nullptr;
 }
@@ -287,6 +308,14 @@ rt_status materialize(rt_ctx c, int n_cases, const rt_case* cases, BatchPlan& pl
   RT_BHIP(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
   pl.grid_blocks = (int64_t)pl.tuning.blocks_per_cu * cus;
   RT_BHIP(c, hipStreamCreateWithFlags(&pl.capture_stream, hipStreamNonBlocking));
+  if (pl.chunked && pl.tuning.slots > 1) {
+    // line sums on a second stream (default priority), ordered against the
+    // marches by events: one fork, then per chunk "line sum done" and
+    // "march done"
+    RT_BHIP(c, hipStreamCreateWithFlags(&pl.side_stream, hipStreamNonBlocking));
+    pl.events.assign(1 + 2 * (size_t)pl.n_chunks, nullptr);
+    for (auto& e : pl.events) RT_BHIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   RT_BHIP(c, hipStreamBeginCapture(pl.capture_stream, hipStreamCaptureModeRelaxed));
   hipError_t le = launch_batch(c, pl, pl.capture_stream);
   hipError_t ce = hipStreamEndCapture(pl.capture_stream, &pl.graph);
@@ -329,15 +358,15 @@ std::string shape_key(rt_ctx c, int n_cases, const rt_case* cases) {
     rays += (double)cases[k].n_rays;
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "v5|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
+  std::snprintf(buf, sizeof(buf), "v6|%s|cases=%d|log2cells=%d|log2rays=%d|nu=%d|log2lines=%d",
                 arch_name(c).c_str(), n_cases, (int)std::lround(std::log2(cells)),
                 (int)std::lround(std::log2(rays)), c->n_nu,
                 (int)std::lround(std::log2((double)std::max(1, c->lines.n))));
   return buf;
 }
 
-// cache file: one line per entry, "<key> <chunk> <groups> <rays> <bpc> <slots>",
-// wrapped as a JSON object {"<key>": [chunk, groups, rays, bpc, slots], ...}
+// cache file: one line per entry, wrapped as a JSON object
+// {"<key>": [chunk, groups, rays, bpc, slots, mode], ...}
 bool cache_lookup(const char* path, const std::string& key, rt_batch_tuning* t) {
   if (!path) return false;
   std::ifstream f(path);
@@ -349,8 +378,8 @@ bool cache_lookup(const char* path, const std::string& key, rt_batch_tuning* t) 
     if (q == std::string::npos || q2 == std::string::npos) continue;
     if (line.substr(q + 1, q2 - q - 1) != key) continue;
     rt_batch_tuning v;
-    if (std::sscanf(line.c_str() + q2 + 1, " : [%d, %d, %d, %d, %d]", &v.chunk_points,
-                    &v.kappa_groups, &v.march_rays, &v.blocks_per_cu, &v.slots) == 5) {
+    if (std::sscanf(line.c_str() + q2 + 1, " : [%d, %d, %d, %d, %d, %d]", &v.chunk_points,
+                    &v.kappa_groups, &v.march_rays, &v.blocks_per_cu, &v.slots, &v.mode) == 6) {
       *t = v;
       return true;
     }
@@ -375,8 +404,8 @@ void cache_store(const char* path, const std::string& key, const rt_batch_tuning
     }
   }
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "\"%s\": [%d, %d, %d, %d, %d]", key.c_str(), t.chunk_points,
-                t.kappa_groups, t.march_rays, t.blocks_per_cu, t.slots);
+  std::snprintf(buf, sizeof(buf), "\"%s\": [%d, %d, %d, %d, %d, %d]", key.c_str(),
+                t.chunk_points, t.kappa_groups, t.march_rays, t.blocks_per_cu, t.slots, t.mode);
   entries.push_back(buf);
   std::ofstream o(path, std::ios::trunc);
   o << "{\n";
@@ -527,25 +556,30 @@ rt_status rt_batch_autotune(rt_ctx c, int n_cases, const rt_case* cases, int kap
   if (cur_ms < 0) return bfail(c, RT_EINVAL, "rt_batch_autotune: workspace too small for the default tuning");
   // coordinate descent, repeated while a pass improves (at most 3 passes):
   // the best value of one parameter moves when the others change
+  // (the persistent kernel's own parameters are swept only in its mode)
+  const int modes[] = {RT_BATCH_CHUNKED, RT_BATCH_PERSISTENT};
   const int chunks[] = {kChunk, 2 * kChunk, 4 * kChunk};
   const int groups[] = {16, 32, 64, 128};
   const int rays[] = {16, 64, 256};
   const int bpc[] = {2, 4, 5, 8};
-  const int slots[] = {2, 4, 8};
-  const int* values[5] = {chunks, groups, rays, bpc, slots};
-  const int n_values[5] = {3, 4, 3, 4, 3};
+  const int slots[] = {1, 2, 4, 8};
+  const int* values[6] = {modes, chunks, groups, rays, bpc, slots};
+  const int n_values[6] = {2, 3, 4, 3, 4, 4};
   for (int pass = 0; pass < 3; ++pass) {
     bool improved = false;
-    for (int param = 0; param < 5; ++param) {
+    for (int param = 0; param < 6; ++param) {
+      if (param >= 2 && param <= 4 && cur.mode == RT_BATCH_CHUNKED) continue;
       for (int v = 0; v < n_values[param]; ++v) {
         rt_batch_tuning t = cur;
         const int x = values[param][v];
-        if (param == 0) t.chunk_points = x;
-        if (param == 1) t.kappa_groups = x;
-        if (param == 2) t.march_rays = x;
-        if (param == 3) t.blocks_per_cu = x;
-        if (param == 4) t.slots = x;
+        if (param == 0) t.mode = x;
+        if (param == 1) t.chunk_points = x;
+        if (param == 2) t.kappa_groups = x;
+        if (param == 3) t.march_rays = x;
+        if (param == 4) t.blocks_per_cu = x;
+        if (param == 5) t.slots = x;
         if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
+        if (check_tuning(c, t) != RT_OK) continue;  // e.g. one slab for the queue
         double ms = -1;
         if (rt_status s = trial(t, &ms)) return s;
         if (ms > 0 && ms < cur_ms) { cur = t; cur_ms = ms; improved = true; }

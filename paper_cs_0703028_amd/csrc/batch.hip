@@ -1,7 +1,16 @@
-// batch.hip -- many independent receiver cases in one persistent launch.
+// batch.hip -- many independent receiver cases in one graph launch, in one
+// of two shapes that give the same tallies bit for bit.
 //
-// Work is a queue of items in a fixed order; every block pops the next item
-// with one atomic and runs it:
+// Chunked: the rays of every case are generated and traversed in one
+// launch; then, chunk after chunk of the spectrum, one line-sum launch
+// fills a slab with the chunk's kappa for the cells of every case, and one
+// march launch takes the rays of every case through it.  Each launch fills
+// the GPU however small the cases, and the kernels are the single-case ones
+// with a case lookup per block.  With several slabs the line sums run on a
+// second stream, overlapping the march of the previous chunk.
+//
+// Persistent: work is a queue of items in a fixed order; every block pops
+// the next item with one atomic and runs it:
 //   RAYGEN (case, 256 rays)            rays and exact traversal -> segments
 //   KAPPA  (case, chunk, tile, groups) line sum of a spectral chunk for a
 //                                      range of cells into a kappa slab
@@ -346,6 +355,93 @@ __global__ void batch_order_scatter_kernel(const BatchCase* __restrict__ cases, 
   perm[off + pos] = (uint32_t)(i - off);
 }
 
+// Chunked mode, rays: slot r of case k holds ray perm[ray_off + r] of the
+// case (its coherent order), traversed into the case's segment lists.
+__global__ void batch_raygen_kernel(const BatchCase* __restrict__ cases, int n_cases,
+                                    int64_t total_rays, const uint32_t* __restrict__ perm,
+                                    int2* segs, int32_t* counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total_rays) return;
+  const BatchCase cs = cases[case_of_ray(cases, n_cases, i)];
+  const int64_t r = i - cs.ray_off;
+  int64_t O[3], D[3];
+  sample_ray(cs.seed, (uint64_t)perm[i], cs.nx, cs.ny, cs.nz, O, D);
+  counts[i] = traverse(cs.nx, cs.ny, cs.nz, cs.unit_cm, O, D, cs.max_segs,
+                       segs + cs.seg_off + r * cs.max_segs);
+}
+
+struct ChunkMarchArgs {
+  const BatchCase* cases;
+  int n_cases;
+  const float* slab;     // the chunk's slab: [total cells][chunk_points]
+  int chunk_points;
+  int64_t col0;          // first point of the chunk
+  const double* theta;   // packed over the cases
+  const float* bwall;    // [case][bwall_ld]
+  int64_t bwall_ld;
+  double nu0, dnu, c1;
+  const int2* segs;
+  const int32_t* counts;
+  unsigned long long* acc;
+  unsigned* ovf;
+};
+
+// last case whose first block row is <= local
+__device__ __forceinline__ int case_of_block(const BatchCase* cases, int n_cases, int64_t local) {
+  int lo = 0, hi = n_cases - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cases[mid].blk_off <= local) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Chunked mode, march: block = 4 wavefronts = 4 consecutive slots of one
+// case on one kChunk-point part of the chunk.  Workgroups go to the 8 XCDs
+// round-robin (block b runs on XCD b % 8); the rows of 8 blocks (b / 8) run
+// case after case, and within a case each XCD takes a contiguous eighth of
+// its ray blocks, part-major: the single-case kernel's order, so that all
+// XCDs work on one case's slab rows at a time and its working set stays in
+// the last-level cache.  Each wavefront adds to the same accumulator rows as
+// the persistent kernel's march items.
+template <bool QUAD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void chunk_march_kernel(
+    ChunkMarchArgs a) {
+  __shared__ float stage[4][TallyStage<false>::kEntries];
+  const int64_t b = blockIdx.x;
+  const int64_t xcd = b & 7, local = b >> 3;
+  const int k = case_of_block(a.cases, a.n_cases, local);
+  const BatchCase& cs = a.cases[k];
+  const int64_t nb = (cs.n_rays + 3) / 4, rbx = (nb + 7) / 8;
+  const int64_t idx = local - cs.blk_off;
+  const int part = (int)(idx / rbx);
+  const int64_t rb = xcd * rbx + idx % rbx;
+  if (rb >= nb) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t r = rb * 4 + wave;
+  if (r >= cs.n_rays) return;
+  MarchWave w;
+  w.kappa = a.slab + cs.cell_off * a.chunk_points;
+  w.planck = nullptr;
+  w.ld = a.chunk_points;
+  w.col0 = a.col0;
+  w.theta = a.theta + cs.cell_off;
+  w.bwall = a.bwall + (int64_t)k * a.bwall_ld;
+  w.nu0 = a.nu0;
+  w.dnu = a.dnu;
+  w.c1 = a.c1;
+  w.weight = cs.weight;
+  w.acc = a.acc;
+  w.row0 = cs.cell_off + (int64_t)k * kCaseBalRows;
+  w.bal_row0 = w.row0 + cs.n_cells;
+  w.bal_mask = kCaseBalRows - 1;
+  w.ovf = a.ovf;
+  const int64_t j = a.col0 + (int64_t)part * kChunk + lane * kQ;
+  march_wave<false, false, QUAD>(w, a.segs + cs.seg_off + r * cs.max_segs,
+                                 a.counts[cs.ray_off + r], j, lane, nullptr, stage[wave], r);
+}
+
 __global__ void fill_u32_kernel(unsigned* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -403,6 +499,82 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
                      pl.n_cases, pl.total_rays, pl.d_keys, pl.d_hist, pl.d_perm);
   const int64_t acc_words = (pl.total_cells + (int64_t)pl.n_cases * kCaseBalRows) * kAccRow;
   fill_d(reinterpret_cast<double*>(pl.d_acc), acc_words + 1);  // + overflow flag
+  unsigned* ovf = reinterpret_cast<unsigned*>(pl.d_acc + acc_words);
+  const int64_t groups = acc_words / kAccDigits;
+  auto finish = [&]() {
+    hipLaunchKernelGGL(batch_acc_normalize_kernel, dim3((unsigned)((groups + 255) / 256)),
+                       dim3(256), 0, s, pl.d_acc, groups);
+    hipLaunchKernelGGL(case_tally_kernel, dim3((unsigned)pl.n_cases), dim3(256), 0, s,
+                       pl.d_cases, pl.d_acc, pl.d_abs, pl.d_emi, pl.d_balance);
+    return hipGetLastError();
+  };
+  if (pl.chunked) {
+    hipLaunchKernelGGL(batch_raygen_kernel, dim3(ray_blocks), dim3(256), 0, s, pl.d_cases,
+                       pl.n_cases, pl.total_rays, pl.d_perm, pl.d_segs, pl.d_counts);
+    const int cp = pl.tuning.chunk_points;
+    const int tiles = cp / dev::kKappaTilePoints;
+    KappaTile t;
+    t.L = c->lines;
+    t.C = pl.cells;
+    t.n_cells = pl.total_cells;
+    t.n_nu = c->n_nu;
+    t.K = c->K;
+    t.have_E = c->have_E ? 1 : 0;
+    t.out = pl.d_slabs;
+    t.ld_out = cp;
+    ChunkMarchArgs m;
+    m.cases = pl.d_cases;
+    m.n_cases = pl.n_cases;
+    m.slab = pl.d_slabs;
+    m.chunk_points = cp;
+    m.theta = pl.cells.theta;
+    m.bwall = pl.d_bwall;
+    m.bwall_ld = pl.bwall_ld;
+    m.nu0 = c->nu0;
+    m.dnu = c->dnu;
+    m.c1 = first_radiation_wavenumber();
+    m.segs = pl.d_segs;
+    m.counts = pl.d_counts;
+    m.acc = pl.d_acc;
+    m.ovf = ovf;
+    const int64_t march_blocks = 8 * pl.ray_blocks;
+    if (march_blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int64_t n_groups = (pl.total_cells + kKappaCells - 1) / kKappaCells;
+    // chunk ch uses slab ch % slots.  With one slab everything runs in
+    // order on s.  With more, the line sums run on the side stream, ahead
+    // of the marches by up to slots - 1 chunks (the line sum of a chunk
+    // overlaps the march of the previous one): march ch waits for line sum
+    // ch, and line sum ch waits for the march that last read its slab.
+    const int slots = pl.tuning.slots;
+    const bool two = slots > 1;
+    hipStream_t ks = two ? pl.side_stream : s;
+    hipEvent_t* ev = two ? const_cast<hipEvent_t*>(pl.events.data()) : nullptr;
+    hipError_t e = hipSuccess;
+    if (two) {
+      e = hipEventRecord(ev[0], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ks, ev[0], 0);
+    }
+    for (int ch = 0; ch < pl.n_chunks && e == hipSuccess; ++ch) {
+      float* slab = pl.d_slabs + (int64_t)(ch % slots) * pl.slab_stride;
+      t.out = slab;
+      t.col0 = (int64_t)ch * cp;
+      t.col_end = t.col0 + cp;
+      if (two && ch >= slots) e = hipStreamWaitEvent(ks, ev[1 + pl.n_chunks + ch - slots], 0);
+      if (e == hipSuccess) e = launch_kappa_tiles(c, t, n_groups, ch * tiles, tiles, pl.comp, ks);
+      if (two && e == hipSuccess) e = hipEventRecord(ev[1 + ch], ks);
+      if (two && e == hipSuccess) e = hipStreamWaitEvent(s, ev[1 + ch], 0);
+      if (e != hipSuccess) break;
+      m.slab = slab;
+      m.col0 = t.col0;
+      if (pl.planck_quad)
+        hipLaunchKernelGGL(chunk_march_kernel<true>, dim3((unsigned)march_blocks), dim3(256), 0, s, m);
+      else
+        hipLaunchKernelGGL(chunk_march_kernel<false>, dim3((unsigned)march_blocks), dim3(256), 0, s, m);
+      if (two) e = hipEventRecord(ev[1 + pl.n_chunks + ch], s);
+    }
+    if (e != hipSuccess) return e;
+    return finish();
+  }
   BatchArgs a;
   a.stages = pl.d_stages;
   a.n_stages = pl.n_stages;
@@ -427,7 +599,7 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
   a.bwall = pl.d_bwall;
   a.bwall_ld = pl.bwall_ld;
   a.acc = pl.d_acc;
-  a.ovf = reinterpret_cast<unsigned*>(pl.d_acc + acc_words);
+  a.ovf = ovf;
   a.nu0 = c->nu0;
   a.dnu = c->dnu;
   a.c1 = first_radiation_wavenumber();
@@ -441,12 +613,7 @@ hipError_t launch_batch(rt_ctx c, const BatchPlan& pl, hipStream_t s) {
     hipLaunchKernelGGL(batch_kernel<true>, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(batch_kernel<false>, dim3((unsigned)pl.grid_blocks), dim3(256), 0, s, a);
-  const int64_t groups = acc_words / kAccDigits;
-  hipLaunchKernelGGL(batch_acc_normalize_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256),
-                     0, s, pl.d_acc, groups);
-  hipLaunchKernelGGL(case_tally_kernel, dim3((unsigned)pl.n_cases), dim3(256), 0, s, pl.d_cases,
-                     pl.d_acc, pl.d_abs, pl.d_emi, pl.d_balance);
-  return hipGetLastError();
+  return finish();
 }
 
 }  // namespace rt

@@ -1,4 +1,5 @@
-// batch_plan.h -- work plan of the persistent batched launch (host + device).
+// batch_plan.h -- work plan of the batched launch (host + device): either
+// per-chunk launches over all cases or one persistent work-queue kernel.
 #pragma once
 
 #include "rt_internal.h"
@@ -26,6 +27,7 @@ struct BatchStage {
 struct BatchCase {
   int nx, ny, nz, max_segs;
   int64_t n_cells, cell_off, n_rays, seg_off, ray_off;
+  int64_t blk_off;  // chunked mode: first row of 8 march blocks of the case
   uint64_t seed;
   double weight, unit_cm;
   float2 theta_wall;  // c2 / T_wall as an FP32 pair (0: cold walls)
@@ -34,9 +36,11 @@ struct BatchCase {
 struct BatchPlan {
   rt_batch_tuning tuning;
   bool comp = false;
+  bool chunked = true;      // tuning.mode == RT_BATCH_CHUNKED
   bool planck_quad = true;  // second-order Planck expansion in the march
   int n_cases = 0, n_chunks = 0, n_pairs = 0, n_stages = 0;
   int64_t total_items = 0, total_cells = 0, total_rays = 0, max_cells = 0;
+  int64_t ray_blocks = 0;  // chunked mode: rows of 8 march blocks over all cases
   int64_t grid_blocks = 0;
   int64_t bwall_ld = 0, slab_stride = 0;
   int64_t n_counters = 0;
@@ -64,6 +68,11 @@ struct BatchPlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture_stream = nullptr;
+  // chunked mode with several slabs: the line sums' stream and the events
+  // ordering it against the marches (fork, line sum done per chunk, march
+  // done per chunk)
+  hipStream_t side_stream = nullptr;
+  std::vector<hipEvent_t> events;
 };
 
 hipError_t launch_batch_prep(rt_ctx c, const BatchPlan& pl, hipStream_t s);

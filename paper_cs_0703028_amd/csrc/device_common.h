@@ -876,4 +876,12 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
 }
 
 }  // namespace dev
+
+// Line-sum tiles [tile_begin, tile_begin + n_tiles) for n_cell_groups groups
+// of kKappaCells cells (kappa.hip).
+hipError_t launch_kappa_tiles(rt_ctx c, const dev::KappaTile& t, int64_t n_cell_groups,
+                              int tile_begin, int n_tiles, bool comp, hipStream_t s,
+                              const dev::TileGate& gate = dev::TileGate(), int parts = 1,
+                              int64_t part_stride = 0);
+
 }  // namespace rt

@@ -30,10 +30,6 @@
 
 namespace rt {
 
-hipError_t launch_kappa_tiles(rt_ctx c, const dev::KappaTile& t, int64_t n_cell_groups,
-                              int tile_begin, int n_tiles, bool comp, hipStream_t s,
-                              const dev::TileGate& gate = dev::TileGate(), int parts = 1,
-                              int64_t part_stride = 0);
 hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const double* x,
                                  const double* p, const CellSet& cells, hipStream_t s);
 

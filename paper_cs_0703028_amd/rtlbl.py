@@ -26,6 +26,7 @@ RT_NO_DEVICE = -1    # rt_create: a host-only handle (argument and call-order ch
  KAPPA_ADAPTIVE_WINGS) = 0, 1, 2, 3, 4, 5
 ADAPTIVE_GROUP = 8   # RT_ADAPTIVE_GROUP: cells sharing one line window
 TALLY_F32, TALLY_F64 = 0, 1
+BATCH_CHUNKED, BATCH_PERSISTENT = 0, 1  # rt_batch_tuning.mode
 # rt_arith_op: name -> (code, operands read)
 ARITH_OPS = {
     "copy": (0, 1), "add": (1, 2), "sub": (2, 2), "mul": (3, 2), "fma": (4, 3),
@@ -60,7 +61,7 @@ class RtCase(C.Structure):
 
 class BatchTuning(C.Structure):
     _fields_ = [(n, C.c_int) for n in ("chunk_points", "kappa_groups", "march_rays",
-                                        "blocks_per_cu", "slots")]
+                                        "blocks_per_cu", "slots", "mode")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -225,6 +225,26 @@ def test_host_only_batch_checks(rt, host):
     tun = rt.Tracer.default_tuning()
     tun.chunk_points = 1000                     # not a multiple of the march chunk
     assert _status(rt, lambda: host.batch_workspace_size(cases, tun)) == rt.RT_EINVAL
+    tun = rt.Tracer.default_tuning()
+    tun.mode = 2                                # no such launch shape
+    assert _status(rt, lambda: host.batch_workspace_size(cases, tun)) == rt.RT_EINVAL
+    tun = rt.Tracer.default_tuning()
+    tun.slots = 1                               # the persistent queue needs two slabs
+    tun.slots = 9
+    assert _status(rt, lambda: host.batch_workspace_size(cases, tun)) == rt.RT_EINVAL
+    tun.slots = 1
+    assert tun.mode == rt.BATCH_CHUNKED and host.batch_workspace_size(cases, tun) > 0
+    tun.mode = rt.BATCH_PERSISTENT
+    assert _status(rt, lambda: host.batch_workspace_size(cases, tun)) == rt.RT_EINVAL
+    # two slabs each, chunked: over the cells of every case; persistent: of
+    # the largest case
+    ch, pe = rt.Tracer.default_tuning(), rt.Tracer.default_tuning()
+    ch.slots = 2
+    pe.mode, pe.slots = rt.BATCH_PERSISTENT, 2
+    cells = [c.grid.n_cells for c in cases]
+    grow = 2 * (sum(cells) - max(cells)) * ch.chunk_points * 4
+    diff = host.batch_workspace_size(cases, ch) - host.batch_workspace_size(cases, pe)
+    assert abs(diff - grow) < 1 << 16, (diff, grow)
     bad = replace(cases[1], n_rays=0)
     assert _status(rt, lambda: host.batch_workspace_size([cases[0], bad])) == rt.RT_EINVAL
     g = I.hot_spot_grid(16, 1.0, seed=3)

@@ -1,8 +1,9 @@
-"""GPU tests of the batched form: many receiver cases in one persistent,
-graph-captured launch.
+"""GPU tests of the batched form: many receiver cases in one graph launch,
+either per-chunk launches over all cases or one persistent work-queue kernel.
 
-* every case equals its own single-case run bit for bit (same kernels, and
-  the tallies are exact fixed-point sums whatever the order of additions);
+* every case equals its own single-case run bit for bit, in both launch
+  shapes (same arithmetic, and the tallies are exact fixed-point sums
+  whatever the order of additions);
 * every case matches the FP64 oracle: 1e-5 relative per cell, exact zeros;
 * graph replays with host work in between reproduce the first launch;
 * the autotuner returns a valid tuning, stores it and serves it from the
@@ -60,16 +61,19 @@ def _single(rt, w):
     return res
 
 
-def test_batch_matches_single_runs_and_oracle(rt):
+@pytest.mark.parametrize("mode", ["chunked", "chunked_one_slab", "persistent"])
+def test_batch_matches_single_runs_and_oracle(rt, mode):
     from oracle import oracle as O
     cases = _cases()
     t = rt.Tracer(0)
     t.setup_lines(cases[0].lines)
     tun = rt.Tracer.default_tuning()
+    tun.mode = rt.BATCH_PERSISTENT if mode == "persistent" else rt.BATCH_CHUNKED
+    tun.slots = 1 if mode == "chunked_one_slab" else 2
     tun.chunk_points = rt.MARCH_CHUNK
     tun.kappa_groups = 2
     tun.march_rays = 16
-    print("batch prepare", [c.name for c in cases], flush=True)
+    print("batch prepare", mode, [c.name for c in cases], flush=True)
     ws = t.batch_prepare(cases, rt.KAPPA_PLAIN, tun)
     t.batch_launch()
     out = t.batch_results()
@@ -125,7 +129,8 @@ def _committed_tuning(rt):
     cache = os.path.join(os.path.dirname(here), "paper_cs_0703028_amd", "tuning", "batch_tune.json")
     vals = list(json.load(open(cache)).values())[0]
     tun = rt.Tracer.default_tuning()
-    (tun.chunk_points, tun.kappa_groups, tun.march_rays, tun.blocks_per_cu, tun.slots) = vals
+    for (name, _), v in zip(tun._fields_, vals):
+        setattr(tun, name, int(v))
     return tun, vals
 
 
@@ -161,11 +166,15 @@ def test_64_case_extremes_match_oracle(rt):
         assert ra.max() <= 1e-5 and re_.max() <= 1e-5 and rb.max() <= 1e-5
 
 
-def test_batch_graph_replays(rt):
+@pytest.mark.parametrize("mode", ["chunked", "persistent"])
+def test_batch_graph_replays(rt, mode):
     cases = _cases()[:3]
     t = rt.Tracer(0)
     t.setup_lines(cases[0].lines)
-    ws = t.batch_prepare(cases)
+    tun = rt.Tracer.default_tuning()
+    tun.mode = rt.BATCH_CHUNKED if mode == "chunked" else rt.BATCH_PERSISTENT
+    tun.slots = 2
+    ws = t.batch_prepare(cases, rt.KAPPA_PLAIN, tun)
     t.batch_launch()
     first = t.batch_results()
     for rep in range(3):
@@ -230,7 +239,9 @@ def test_batch_autotune_and_cache(rt, tmp_path):
     print("autotune", flush=True)
     best = t.batch_autotune(cases, rt.KAPPA_PLAIN, ws, path)
     d = best.as_dict()
-    assert d["chunk_points"] % rt.MARCH_CHUNK == 0 and d["march_rays"] % 4 == 0 and d["slots"] >= 2
+    assert d["chunk_points"] % rt.MARCH_CHUNK == 0 and d["march_rays"] % 4 == 0
+    assert d["mode"] in (rt.BATCH_CHUNKED, rt.BATCH_PERSISTENT)
+    assert d["slots"] >= (2 if d["mode"] == rt.BATCH_PERSISTENT else 1)
     assert os.path.exists(path) and '"' in open(path).read()
     best2 = t.batch_autotune(cases, rt.KAPPA_PLAIN, ws, path)
     assert best2.as_dict() == d
@@ -252,6 +263,11 @@ def test_batch_errors(rt):
     t.setup_lines(cases[0].lines)
     bad = rt.Tracer.default_tuning()
     bad.chunk_points = 1000
+    with pytest.raises(rt.RtError) as e:
+        t.batch_workspace_size(cases, bad)
+    assert e.value.status == rt.RT_EINVAL
+    bad = rt.Tracer.default_tuning()
+    bad.mode = 2
     with pytest.raises(rt.RtError) as e:
         t.batch_workspace_size(cases, bad)
     assert e.value.status == rt.RT_EINVAL

@@ -84,10 +84,11 @@ def test_coherent_order_tallies_repeat_bit_for_bit(rt):
     t.close()
 
 
-def test_batched_tallies_repeat_bit_for_bit(rt):
-    """Two launches of one prepared batch (persistent queue, blocks taking
-    march items in whatever order they reach the queue) give the same
-    tallies bit for bit."""
+@pytest.mark.parametrize("mode", ["chunked", "persistent"])
+def test_batched_tallies_repeat_bit_for_bit(rt, mode):
+    """Two launches of one prepared batch give the same tallies bit for bit
+    (persistent queue: blocks take march items in whatever order they reach
+    the queue), and both launch shapes give the same tallies."""
     L = I.small_ragged().lines
     cases = []
     for (nx, ny, nz), h, nr, Tw, seed in (((5, 6, 7), 0.1, 700, 0.0, 3),
@@ -98,12 +99,23 @@ def test_batched_tallies_repeat_bit_for_bit(rt):
         cases.append(I.Workload(f"case_{nx}x{ny}x{nz}", g, L, nr, seed))
     t = rt.Tracer(0)
     t.setup_lines(cases[0].lines)
-    ws = t.batch_prepare(cases)
+    tun = rt.Tracer.default_tuning()
+    other = rt.Tracer.default_tuning()
+    tun.mode = rt.BATCH_CHUNKED if mode == "chunked" else rt.BATCH_PERSISTENT
+    tun.slots = 2
+    other.mode = rt.BATCH_PERSISTENT if mode == "chunked" else rt.BATCH_CHUNKED
+    other.slots = 2
+    ws = t.batch_prepare(cases, rt.KAPPA_PLAIN, tun)
     res = []
     for _ in range(2):
         t.batch_launch()
         res.append(t.batch_results())
-    for (a1, e1, b1), (a2, e2, b2) in zip(*res):
-        assert np.array_equal(a1, a2) and np.array_equal(e1, e2) and np.array_equal(b1, b2)
+    del ws
+    ws = t.batch_prepare(cases, rt.KAPPA_PLAIN, other)
+    t.batch_launch()
+    res.append(t.batch_results())
+    for other_res in res[1:]:
+        for (a1, e1, b1), (a2, e2, b2) in zip(res[0], other_res):
+            assert np.array_equal(a1, a2) and np.array_equal(e1, e2) and np.array_equal(b1, b2)
     del ws
     t.close()
