@@ -569,6 +569,25 @@ def form_arith(rtlbl, I):
     }
 
 
+def run_forms(rtlbl, I, args):
+    out = {}
+    ep = args.learned_epochs
+    for name, fn in (("precision", form_precision), ("batched", form_batched),
+                     ("learned", lambda r, i: form_learned(r, i, epochs=ep)),
+                     ("learned_dense_lines",
+                      lambda r, i: form_learned(r, i, epochs=ep, n_lines=20000)),
+                     ("two_gases", form_two_gases), ("table16", form_table16),
+                     ("adaptive", form_adaptive), ("arith", form_arith)):
+        if name not in args.forms.split(","):
+            continue
+        try:
+            out[name] = fn(rtlbl, I)
+        except Exception as exc:  # a failing form must not hide the headline
+            out[name] = {"error": repr(exc)}
+        print(f"# form {name} done", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -580,6 +599,10 @@ def main():
                                        "adaptive,arith",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--workload", default="plain_32cube")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="run only the forms (for profiling one form); no headline record")
+    ap.add_argument("--learned-epochs", type=int, default=40,
+                    help="training epochs of the learned forms")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device once (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -601,6 +624,11 @@ def main():
 
     from paper_cs_0703028_amd import inputs as I
     from paper_cs_0703028_amd import rtlbl
+
+    if args.no_headline:
+        rec = {"forms": run_forms(rtlbl, I, args)}
+        print(json.dumps(rec), flush=True)
+        return
 
     w = getattr(I, args.workload)()
     t = rtlbl.Tracer(0)
@@ -697,19 +725,7 @@ def main():
         },
     }
     if not args.no_forms:
-        rec["forms"] = {}
-        for name, fn in (("precision", form_precision), ("batched", form_batched),
-                         ("learned", form_learned),
-                         ("learned_dense_lines", lambda r, i: form_learned(r, i, n_lines=20000)),
-                         ("two_gases", form_two_gases), ("table16", form_table16),
-                         ("adaptive", form_adaptive), ("arith", form_arith)):
-            if name not in args.forms.split(","):
-                continue
-            try:
-                rec["forms"][name] = fn(rtlbl, I)
-            except Exception as exc:  # a failing form must not hide the headline
-                rec["forms"][name] = {"error": repr(exc)}
-            print(f"# form {name} done", file=sys.stderr, flush=True)
+        rec["forms"] = run_forms(rtlbl, I, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
