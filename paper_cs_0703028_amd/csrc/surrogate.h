@@ -50,6 +50,7 @@ struct Surrogate {
   int inf_check = 0, inf_chunks = 0;
   unsigned* d_cell_flag = nullptr;   // = epoch: cell outside the training box
   unsigned* d_group_flag = nullptr;  // = epoch: its line-sum group of cells
+  float4* d_cell_feat = nullptr;     // per cell: the three state features and u
   unsigned epoch = 0;                // inference calls so far
   float* d_err = nullptr;            // checked error per chunk
   int32_t* d_check = nullptr;   // sampled cells

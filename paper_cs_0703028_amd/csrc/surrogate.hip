@@ -275,12 +275,16 @@ __global__ void pack_fragments_kernel(const bf16* __restrict__ wt, int N, bf16* 
 // to linear in 1/T (Boltzmann factor of Eq. (1)) and in ln p (half widths).
 struct Box { float T0, Ts, x0, xs, p0, ps; int n_chunks; };
 
+__device__ __forceinline__ float chunk_feature(const Box& bx, int k) {
+  return bx.n_chunks > 1 ? 2.0f * k / (float)(bx.n_chunks - 1) - 1.0f : 0.0f;
+}
+
 __device__ __forceinline__ void features(const Box& bx, double T, double x, double p, int k,
                                          float* f) {
   f[0] = ((float)(1.0 / T) - bx.T0) * bx.Ts;
   f[1] = ((float)x - bx.x0) * bx.xs;
   f[2] = ((float)log(p) - bx.p0) * bx.ps;
-  f[3] = bx.n_chunks > 1 ? 2.0f * k / (float)(bx.n_chunks - 1) - 1.0f : 0.0f;
+  f[3] = chunk_feature(bx, k);
 }
 
 // Training batch: rows perm[step*M .. +M) of the (sample, chunk) table.
@@ -320,6 +324,26 @@ __global__ void infer_features_kernel(const double* __restrict__ T, const double
 
 __device__ __forceinline__ double gas_density(double T, double x, double p) {
   return x * p * kAtm / (kBoltzmann * T) * 1e-6;
+}
+
+// Per cell, once per inference: the three state features and u (the
+// network's rows of one cell share them), and the marks of a cell outside
+// the training box and of its line-sum group.
+__global__ void cell_features_kernel(const double* __restrict__ T, const double* __restrict__ x,
+                                     const double* __restrict__ p, int64_t n_cells, Box bx,
+                                     double T_lo, double T_hi, double x_lo, double x_hi,
+                                     double p_lo, double p_hi, unsigned epoch,
+                                     unsigned* cell_flag, unsigned* group_flag, float4* feat) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= n_cells) return;
+  const double t = T[cell], xc = x[cell], pc = p[cell];
+  float f[4];
+  features(bx, t, xc, pc, 0, f);
+  feat[cell] = make_float4(f[0], f[1], f[2], (float)gas_density(t, xc, pc));
+  if (!(t >= T_lo && t <= T_hi && xc >= x_lo && xc <= x_hi && pc >= p_lo && pc <= p_hi)) {
+    cell_flag[cell] = epoch;
+    group_flag[cell / dev::kKappaCells] = epoch;
+  }
 }
 
 // kappa[cell][k*256 + i] = u exp(mean + std * y), 0 beyond n_nu.
@@ -370,9 +394,7 @@ struct FusedArgs {
   const float* b4;
   int64_t rows;
   const float* X0;  // [rows][4] features
-  const double* T;
-  const double* x;
-  const double* p;
+  const float4* cell_feat;  // per cell: three state features and u
   Box bx;
   float* P;         // [rows][256]
   const float* mean;
@@ -380,10 +402,6 @@ struct FusedArgs {
   float* kappa;
   int64_t ld;
   int n_nu;
-  double T_lo, T_hi, x_lo, x_hi, p_lo, p_hi;  // training box
-  unsigned epoch;
-  unsigned* cell_flag;   // marked with epoch when outside the box
-  unsigned* group_flag;  // and the cell's line-sum group
 };
 
 // C += A W over K = 512 for RT row tiles x NT column tiles: A from LDS, W in
@@ -421,6 +439,7 @@ __device__ __forceinline__ void mfma_layer(const bf16* __restrict__ H, const bf1
     for (int ct = 0; ct < NT; ++ct) bq[d][ct] = *reinterpret_cast<const bf16x8*>(wrow[ct] + d * 512);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) aq[0][rt] = *reinterpret_cast<const bf16x8*>(hrow[rt]);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int st = 0; st < kSteps; ++st) {
     if (st + 1 < kSteps)
@@ -437,6 +456,10 @@ __device__ __forceinline__ void mfma_layer(const bf16* __restrict__ H, const bf1
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct)
         bq[st % kPrefetch][ct] = *reinterpret_cast<const bf16x8*>(wrow[ct] + (st + kPrefetch) * 512);
+    // keep each step's loads in its step: left free, the scheduler sinks
+    // the weight loads to just before their MFMAs (to save registers), and
+    // every k-step then waits a full L2 round trip
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -446,7 +469,7 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
   __shared__ bf16 H[kFuseRows * kLdsRow];  // also holds the FP32 outputs
   static_assert(kFuseRows * kLdsRow * sizeof(bf16) >= kFuseRows * kMlpWidth * sizeof(float),
                 "LDS buffer too small for the output layer");
-  __shared__ float F[kFuseRows][4];
+  __shared__ __align__(16) float F[kFuseRows][4];
   __shared__ float U[kFuseRows];
   __shared__ int64_t RowBase[kFuseRows];  // kappa offset of the row's chunk (-1: no row)
   __shared__ int RowJ[kFuseRows];         // first wavenumber index of the row's chunk
@@ -465,15 +488,13 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
       if (FROM_STATE) {
         const int64_t cell = row / n_chunks;
         k = (int)(row - cell * n_chunks);
-        const double T = a.T[cell], x = a.x[cell], p = a.p[cell];
-        features(a.bx, T, x, p, k, f);
-        u = (float)gas_density(T, x, p);
+        const float4 cf = a.cell_feat[cell];
+        f[0] = cf.x;
+        f[1] = cf.y;
+        f[2] = cf.z;
+        f[3] = chunk_feature(a.bx, k);
+        u = cf.w;
         base = cell * a.ld + (int64_t)k * kMlpWidth;
-        if (k == 0 && !(T >= a.T_lo && T <= a.T_hi && x >= a.x_lo && x <= a.x_hi &&
-                        p >= a.p_lo && p <= a.p_hi)) {
-          a.cell_flag[cell] = a.epoch;
-          a.group_flag[cell / dev::kKappaCells] = a.epoch;
-        }
       } else {
         for (int q = 0; q < 4; ++q) f[q] = a.X0[4 * row + q];
         base = row * kMlpWidth;
@@ -493,11 +514,21 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) w1[k] = (float)a.W1k[k * kHidden + n];
     const float b1 = a.b1[n];
-    for (int r = 0; r < kFuseRows; ++r) {
-      float z = b1;
+    // eight rows at a time, each step over all eight before the next, so
+    // that the exponentials and reciprocals of independent rows interleave
+    for (int r0 = 0; r0 < kFuseRows; r0 += 8) {
+      float z[8], e[8];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) z = fmaf(F[r][k], w1[k], z);
-      H[r * kLdsRow + n] = (bf16)(z * sigmoid(z));
+      for (int q = 0; q < 8; ++q) {
+        const float4 f = *reinterpret_cast<const float4*>(F[r0 + q]);
+        z[q] = fmaf(f.w, w1[3], fmaf(f.z, w1[2], fmaf(f.y, w1[1], fmaf(f.x, w1[0], b1))));
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_exp2f(-1.4426950408889634f * z[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_rcpf(1.0f + e[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) H[(r0 + q) * kLdsRow + n] = (bf16)(z[q] * e[q]);
     }
   }
   __syncthreads();
@@ -509,17 +540,30 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
     f32x16 acc[RT][2];
     mfma_layer<RT, 2>(H, wt, n_base, lane, acc);
     __syncthreads();  // every wavefront has read the layer input
+    // SiLU(z) = z sigmoid(z), eight values at a time as in layer 1
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
+      for (int ct = 0; ct < 2; ++ct) {
+        const int col = n_base + ct * 32 + (lane & 31);
+        const float bc = b[col];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int row = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-          const int col = n_base + ct * 32 + (lane & 31);
-          const float z = acc[rt][ct][i] + b[col];
-          H[row * kLdsRow + col] = (bf16)(z * sigmoid(z));
+        for (int h = 0; h < 16; h += 8) {
+          float z[8], e[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) z[q] = acc[rt][ct][h + q] + bc;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_exp2f(-1.4426950408889634f * z[q]);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_rcpf(1.0f + e[q]);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int i = h + q;
+            const int row = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+            H[row * kLdsRow + col] = (bf16)(z[q] * e[q]);
+          }
         }
+      }
     __syncthreads();
   }
   // output layer (wavefront w: columns [32 w, 32 w + 32)); accumulators to
@@ -541,24 +585,54 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
       }
     __syncthreads();
   }
+  // Each thread takes groups of kGroup float4 runs of a row, loads all of a
+  // group's inputs before any of its outputs is stored (one memory latency
+  // per group), then writes them.  Rows, tables and kappa row offsets are
+  // multiples of 4 floats.
   const float* Z = reinterpret_cast<const float*>(H);
-  static_assert(kMlpWidth == 256, "row = i >> 8 below");
-  for (int i = tid; i < kFuseRows * kMlpWidth; i += kFuseThreads) {
-    const int row = i >> 8, col = i & (kMlpWidth - 1);
-    const int64_t base = RowBase[row];
-    if (base < 0) break;
-    const float z = Z[i];
-    if (!TO_KAPPA) {
-      a.P[base + col] = z;
-    } else {
-      const int j = RowJ[row] + col;
-      const int k = RowK[row];
-      float v = 0.f;
-      if (j < a.n_nu) {  // exp to ~1e-6 relative, far inside the network's own error
-        const float y = a.mean[k * kMlpWidth + col] + a.stdv[k * kMlpWidth + col] * z;
-        v = U[row] * __builtin_amdgcn_exp2f(1.4426950408889634f * y);
+  constexpr int kRuns = kMlpWidth / 4;                      // float4 runs per row
+  constexpr int kPer = kFuseRows * kRuns / kFuseThreads;    // runs per thread
+  constexpr int kGroup = 4;
+  static_assert(kFuseRows * kRuns % kFuseThreads == 0 && kPer % kGroup == 0, "output tiling");
+  const float* __restrict__ mean = a.mean;
+  const float* __restrict__ stdv = a.stdv;
+#pragma unroll
+  for (int g = 0; g < kPer; g += kGroup) {
+    float4 z[kGroup], m[kGroup], sd[kGroup];
+    int64_t base[kGroup];
+    int col[kGroup], row[kGroup];
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+      const int i4 = (g + q) * kFuseThreads + tid;
+      row[q] = i4 / kRuns;
+      col[q] = (i4 % kRuns) * 4;
+      base[q] = RowBase[row[q]];
+      z[q] = *reinterpret_cast<const float4*>(Z + row[q] * kMlpWidth + col[q]);
+      if (TO_KAPPA && base[q] >= 0) {
+        const int t4 = RowK[row[q]] * kMlpWidth + col[q];
+        m[q] = *reinterpret_cast<const float4*>(mean + t4);
+        sd[q] = *reinterpret_cast<const float4*>(stdv + t4);
       }
-      if (j < a.ld) a.kappa[base + col] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+      if (base[q] < 0) continue;
+      if (!TO_KAPPA) {
+        *reinterpret_cast<float4*>(a.P + base[q] + col[q]) = z[q];
+        continue;
+      }
+      // exp to ~1e-6 relative, far inside the network's own error
+      const int j = RowJ[row[q]] + col[q];
+      const float u = U[row[q]];
+      const float zz[4] = {z[q].x, z[q].y, z[q].z, z[q].w};
+      const float mm[4] = {m[q].x, m[q].y, m[q].z, m[q].w};
+      const float ss[4] = {sd[q].x, sd[q].y, sd[q].z, sd[q].w};
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        v[e] = j + e < a.n_nu ? u * __builtin_amdgcn_exp2f(1.4426950408889634f * (mm[e] + ss[e] * zz[e]))
+                              : 0.f;
+      if (j < a.ld) *reinterpret_cast<float4*>(a.kappa + base[q] + col[q]) = make_float4(v[0], v[1], v[2], v[3]);
     }
   }
   if (TO_KAPPA) {  // pitch columns past the last chunk
@@ -882,16 +956,11 @@ void launch_fused(rt_ctx c, const Surrogate& S, int64_t rows, const float* X0, f
   a.wt4 = S.wf[3]; a.b4 = S.b[3];
   a.rows = rows;
   a.X0 = X0;
-  a.T = c->d_T; a.x = c->d_x; a.p = c->d_p;
+  a.cell_feat = S.d_cell_feat;
   a.bx = make_box(S);
   a.P = P;
   a.mean = S.mean; a.stdv = S.stdv;
   a.kappa = c->kappa; a.ld = c->ld; a.n_nu = c->n_nu;
-  a.T_lo = S.T_min; a.T_hi = S.T_max; a.x_lo = S.x_min; a.x_hi = S.x_max;
-  a.p_lo = S.p_min; a.p_hi = S.p_max;
-  a.epoch = S.epoch;
-  a.cell_flag = S.d_cell_flag;
-  a.group_flag = S.d_group_flag;
   // rows per block 32 RT: 64 rows fit two blocks per CU, 96 one; pick the
   // size with the least work on the busiest CU (on a tie, the fewest weight
   // reads)
@@ -927,7 +996,7 @@ void free_surrogate(rt_ctx c) {
   }
   dfree(S.mean); dfree(S.stdv);
   dfree(S.d_cell_flag); dfree(S.d_group_flag); dfree(S.d_err); dfree(S.d_check);
-  dfree(S.d_exact);
+  dfree(S.d_exact); dfree(S.d_cell_feat);
   for (auto& e : S.ev)
     if (e) (void)hipEventDestroy(e);
   if (S.fork) (void)hipEventDestroy(S.fork);
@@ -980,8 +1049,9 @@ rt_status surrogate_kappa(rt_ctx c) {
   if (S.inf_cells != n_cells || S.inf_ld != c->ld || S.inf_check != n_check ||
       S.inf_chunks != S.n_chunks || !S.d_cell_flag) {
     dfree(S.d_cell_flag); dfree(S.d_group_flag); dfree(S.d_err); dfree(S.d_check);
-    dfree(S.d_exact);
+    dfree(S.d_exact); dfree(S.d_cell_feat);
     ok = chk(dalloc(&S.d_cell_flag, n_cells)) && chk(dalloc(&S.d_group_flag, groups_all)) &&
+         chk(dalloc(&S.d_cell_feat, n_cells)) &&
          chk(dalloc(&S.d_err, S.n_chunks)) && chk(dalloc(&S.d_check, std::max(1, n_check))) &&
          chk(dalloc(&S.d_exact, std::max<int64_t>(1, (int64_t)check_parts(c, n_check) * n_check * c->ld)));
     // marks start at 0, which no call uses as its epoch
@@ -1059,6 +1129,11 @@ rt_status surrogate_kappa(rt_ctx c) {
     ok = ok && chk(hipGetLastError()) && chk(hipEventRecord(S.join, S.side));
   }
   (void)hipEventRecord(S.ev[0], s);
+  if (n_cells > 0)
+    hipLaunchKernelGGL(cell_features_kernel, dim3((unsigned)grid1(n_cells)), dim3(256), 0, s,
+                       c->d_T, c->d_x, c->d_p, n_cells, make_box(S), S.T_min, S.T_max, S.x_min,
+                       S.x_max, S.p_min, S.p_max, S.epoch, S.d_cell_flag, S.d_group_flag,
+                       S.d_cell_feat);
   launch_fused(c, S, rows, nullptr, nullptr, true, s);
   ok = ok && chk(hipGetLastError());
   (void)hipEventRecord(S.ev[1], s);
