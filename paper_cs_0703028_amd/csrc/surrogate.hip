@@ -107,11 +107,13 @@ __global__ void bias_kernel(float* __restrict__ C, const float* __restrict__ b, 
   C[i] += b[i % N];
 }
 
-// dP = 2 (P - Y) / (M 256) on valid outputs (0 beyond n_nu); squared error
-// accumulated in FP64.
+// dP = 2 (P - Y) / (M 256) on valid outputs (0 beyond n_nu); the squared
+// error of each block, summed in FP64 in a fixed tree, is added into a
+// fixed-point accumulator (sse: kAccDigits words, then an overflow word), so
+// the reported loss does not depend on the order the blocks finish in.
 __global__ void loss_grad_kernel(const float* __restrict__ P, const float* __restrict__ Y,
                                  const int32_t* __restrict__ row_chunk, int M, int n_nu,
-                                 bf16* dP, bf16* dPT, double* sse) {
+                                 bf16* dP, bf16* dPT, unsigned long long* sse) {
   __shared__ double red[256];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double e2 = 0;
@@ -130,7 +132,14 @@ __global__ void loss_grad_kernel(const float* __restrict__ P, const float* __res
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) unsafeAtomicAdd(sse, red[0]);
+  if (threadIdx.x == 0)
+    dev::acc_add(sse, red[0], reinterpret_cast<unsigned*>(sse + kAccDigits));
+}
+
+// The loss accumulator as one FP64 value (carries propagated first).
+__global__ void sse_value_kernel(unsigned long long* sse, double* out) {
+  dev::acc_normalize(sse);
+  *out = dev::acc_value(sse);
 }
 
 // dZ = dH * SiLU'(Z); BF16 (and transposed) or FP32 output.
@@ -811,14 +820,15 @@ struct Acts {
   float *gW[kMlpLayers] = {}, *gb[kMlpLayers] = {};
   float* part = nullptr;  // column-sum partials: [M / 64][5][512]
   int32_t* row_chunk = nullptr;
-  double* sse = nullptr;
+  unsigned long long* sse = nullptr;  // kAccDigits + 1 words (see loss_grad_kernel)
+  double* sse_value = nullptr;
   int* step = nullptr;
   void release() {
     dfree(X0); dfree(P); dfree(Y); dfree(dH); dfree(dZ1); dfree(dP); dfree(dPT);
     for (int l = 0; l < 3; ++l) { dfree(Z[l]); dfree(H[l]); dfree(HT[l]); dfree(dZ[l]); dfree(dZT[l]); }
     for (int l = 0; l < kMlpLayers; ++l) { dfree(gW[l]); dfree(gb[l]); }
     dfree(part);
-    dfree(row_chunk); dfree(sse); dfree(step);
+    dfree(row_chunk); dfree(sse); dfree(sse_value); dfree(step);
   }
 };
 
@@ -848,7 +858,8 @@ rt_status alloc_acts(rt_ctx c, Acts& a, int M, bool train) {
     RT_SHIP(c, dalloc(&a.gb[l], kMlpDims[l + 1]));
   }
   RT_SHIP(c, dalloc(&a.row_chunk, M));
-  RT_SHIP(c, dalloc(&a.sse, 1));
+  RT_SHIP(c, dalloc(&a.sse, kAccDigits + 1));
+  RT_SHIP(c, dalloc(&a.sse_value, 1));
   RT_SHIP(c, dalloc(&a.step, 1));
   return RT_OK;
 }
@@ -1343,12 +1354,17 @@ rt_status rt_surrogate_train(rt_ctx c, const rt_surrogate_cfg* cfg, double* fina
     const int64_t span = steps_per_epoch * M;
     for (int64_t q = 0; q < span; ++q) rolled[(base + q) % span] = perm[q];
     re = hipMemcpyAsync(perm_d, rolled.data(), rolled.size() * 4, hipMemcpyHostToDevice, s);
-    if (re == hipSuccess) re = hipMemsetAsync(a.sse, 0, sizeof(double), s);
+    if (re == hipSuccess)
+      re = hipMemsetAsync(a.sse, 0, (kAccDigits + 1) * sizeof(unsigned long long), s);
     if (re == hipSuccess) re = hipStreamSynchronize(s);
     for (int64_t st = 0; st < steps_per_epoch && re == hipSuccess; ++st)
       re = hipGraphLaunch(exec, s);
+    if (re == hipSuccess) {
+      hipLaunchKernelGGL(sse_value_kernel, dim3(1), dim3(1), 0, s, a.sse, a.sse_value);
+      re = hipGetLastError();
+    }
     if (re == hipSuccess)
-      re = hipMemcpyAsync(&last_sse, a.sse, sizeof(double), hipMemcpyDeviceToHost, s);
+      re = hipMemcpyAsync(&last_sse, a.sse_value, sizeof(double), hipMemcpyDeviceToHost, s);
     if (re == hipSuccess) re = hipStreamSynchronize(s);
   }
   (void)hipGraphExecDestroy(exec);

@@ -137,18 +137,20 @@ def test_trained_network_drives_the_march(rt, bench_trained):
 
 def test_training_repeats_bit_for_bit(rt, bench_trained):
     """A second training from the same seed and states gives the same
-    weights (fixed-order gradient sums, seeded shuffles)."""
+    weights and the same reported loss (fixed-order gradient sums, seeded
+    shuffles, the loss summed as an exact integer)."""
     t, w = bench_trained
     u = rt.Tracer(0)
     u.setup_grid(w.grid)
     u.setup_lines(w.lines)
     T, x, p = I.surrogate_samples(4096, seed=5)
-    runs = []
+    runs, losses = [], []
     for _ in range(2):
-        u.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=2, batch=1024, lr=1e-3, seed=7,
-                          check_cells=8, tolerance=5e-4)
+        losses.append(u.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=2, batch=1024, lr=1e-3,
+                                        seed=7, check_cells=8, tolerance=5e-4))
         runs.append(u.surrogate_weights())
     u.close()
+    assert losses[0] == losses[1] and np.isfinite(losses[0]) and losses[0] > 0
     for (W0, b0), (W1, b1) in zip(*runs):
         assert np.array_equal(W0, W1) and np.array_equal(b0, b1)
 
