@@ -98,8 +98,8 @@ typedef enum {
  * same rays give the same tallies bit for bit, however they are split over
  * calls.  Each added value is rounded to 29 significant bits first.
  *   RT_TALLY_F32: plain form.  Planck values evaluated in registers (FP32),
- *     1 - exp(-tau) from the hardware exponential with a degree-4 series
- *     below tau = 1/16, per-wavefront partial sums in FP32.
+ *     1 - exp(-tau) from the hardware exponential with a degree-3 series
+ *     below tau = 1/32, per-wavefront partial sums in FP32.
  *   RT_TALLY_F64: precision form.  Planck values read from the table of
  *     rt_compute_kappa (required), degree-5 series below tau = 1/4, all in
  *     FP32; FP64 only in the tally (per-lane partial sums and the weighted

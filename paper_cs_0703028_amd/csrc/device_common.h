@@ -559,10 +559,10 @@ __device__ __forceinline__ double dpp_f64(double v) {
 // a = 1 - e^{-tau} for tau >= 0, two accuracy levels.
 //   precision form: degree-5 Taylor polynomial of (1 - e^{-tau})/tau below
 //     tau = 1/4 (truncation < 5e-8), 1 - 2^{-tau log2 e} above (<= 5e-7);
-//   plain form (in march_wave): the same series to tau^4 below tau = 1/16
-//     (truncation < 1.3e-7), written in the exponent argument, and
-//     1 - 2^{-tau log2 e} above (<= 2e-6 just above the switch, falling as
-//     1/tau); the series is skipped by the whole wavefront when no lane
+//   plain form (in march_wave): the same series to tau^3 below tau = 1/32
+//     (truncation < 1.3e-6), written in the exponent argument, and
+//     1 - 2^{-tau log2 e} above (<= 1.5e-6 just above the switch, falling
+//     as 1/tau); the series is skipped by the whole wavefront when no lane
 //     needs it.
 // The exponent is folded into base 2 per segment, as the paper's listing
 // folds 1/ln 2 into the per-volume scalar.
@@ -823,17 +823,19 @@ __device__ __forceinline__ void march_wave(const MarchWave& a, const int2* sg, i
         av[q] = 1.0f - __builtin_amdgcn_exp2f(kv[q] * xs);
         kmin = fminf(kmin, kv[q]);
       }
-      if (__ballot(kmin * l < 0.0625f)) {
-        // some lane has tau < 1/16: there a = tau - tau^2/2 + tau^3/6 -
-        // tau^4/24 written in x = -tau log2(e), i.e. a = -sum_k (x ln 2)^k / k!,
-        // k = 1..4 (truncation below 1.3e-7 relative)
+      if (__ballot(kmin * l < 0.03125f)) {
+        // some lane has tau < 1/32: there a = tau - tau^2/2 + tau^3/6 written
+        // in x = -tau log2(e), i.e. a = -sum_k (x ln 2)^k / k!, k = 1..3
+        // (truncation below tau^3/24 = 1.3e-6 relative); at tau >= 1/32 the
+        // error of 1 - 2^x, about one unit in the last place of 2^x, is
+        // below 1.5e-6 relative to a
         constexpr float L1 = -0.69314718055994531f, L2 = -0.24022650695910071f,
-                        L3 = -0.055504108664821576f, L4 = -0.0096181291076284772f;
-        constexpr float xlim = -0.0625f * 1.4426950408889634f;
+                        L3 = -0.055504108664821576f;
+        constexpr float xlim = -0.03125f * 1.4426950408889634f;
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
           const float x = kv[q] * xs;
-          const float ser = x * fmaf(x, fmaf(x, fmaf(x, L4, L3), L2), L1);
+          const float ser = x * fmaf(x, fmaf(x, L3, L2), L1);
           av[q] = x > xlim ? ser : av[q];
         }
       }
