@@ -96,16 +96,28 @@ def test_batch_matches_single_runs_and_oracle(rt, mode):
     del ws
 
 
-def test_full_64_case_batch_sampled_cases(rt):
+_SINGLE = {}
+
+
+@pytest.mark.parametrize("shape", ["committed", "persistent"])
+def test_full_64_case_batch_sampled_cases(rt, shape):
     """The 64-case workload (16^3-48^3 cells, 2^14-2^18 rays, 5,000 lines,
     20,000 points) in the launch configuration bench times (the committed
-    tuning): the smallest, the largest and one more case against the
-    single-case path, which is itself checked against the oracle."""
+    tuning), and in the persistent launch shape with its own tuning (1,536
+    points, 32 groups, 16 rays, 5 blocks per CU, 8 slabs): the smallest, the
+    largest and one more case against the single-case path, which is itself
+    checked against the oracle."""
     import torch
     cases = I.batched_cases(64)
     t = rt.Tracer(0)
     t.setup_lines(cases[0].lines)
     tun, vals = _committed_tuning(rt)
+    if shape == "persistent":
+        tun = rt.Tracer.default_tuning()
+        (tun.chunk_points, tun.kappa_groups, tun.march_rays, tun.blocks_per_cu, tun.slots) = (
+            rt.MARCH_CHUNK, 32, 16, 5, 8)
+        tun.mode = rt.BATCH_PERSISTENT
+        vals = tun.as_dict()
     print("64-case batch, tuning", vals, flush=True)
     ws = t.batch_prepare(cases, rt.KAPPA_PLAIN, tun)
     t.batch_launch()
@@ -118,7 +130,9 @@ def test_full_64_case_batch_sampled_cases(rt):
     for k in pick:
         w = cases[k]
         print(f"  case {k}: {w.grid.nx}^3 cells, {w.n_rays} rays", flush=True)
-        sa, se, sb = _single(rt, w)
+        if k not in _SINGLE:
+            _SINGLE[k] = _single(rt, w)
+        sa, se, sb = _SINGLE[k]
         a, e, b = out[k]
         assert np.array_equal(a, sa) and np.array_equal(e, se) and np.array_equal(b, sb)
 
