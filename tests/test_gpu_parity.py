@@ -244,6 +244,39 @@ def test_full_size_32cube_sampled(rt, O):
     t.close()
 
 
+@pytest.mark.slow
+def test_full_size_32cube_precision_form_sampled(rt, O):
+    """The precision form at the 32^3 workload's full size: the compensated
+    line sum and the FP32 Planck table of 64 sampled cells (every point), and
+    a ray range traced with the precision march (FP64 tally partials), all
+    against the oracle."""
+    w = I.plain_32cube()
+    t = _tracer(rt, w)
+    _say("full-size 32^3 compute_kappa (compensated, with the Planck table)")
+    kap, B = t.compute_kappa(rt.KAPPA_COMPENSATED)
+    assert B is not None
+    rng = np.random.default_rng(12)
+    cells = np.sort(rng.choice(w.grid.n_cells, 64, replace=False)).astype(np.int32)
+    nz = w.lines.n_nu
+    kg = kap[cells.tolist()].cpu().numpy()[:, :nz]
+    bg = B[cells.tolist()].cpu().numpy()[:, :nz]
+    rk = _rel(kg, O.kappa(w.grid, w.lines, cells))
+    rb = _rel(bg, O.planck_rows(w.grid, w.lines, cells))
+    _say(f"  kappa sampled max rel {rk.max():.3e}, planck {rb.max():.3e}")
+    assert rk.max() <= REL and rb.max() <= 1e-6
+    begin, count = 333_333, 6
+    _say(f"full-size 32^3 precision march, rays [{begin}, {begin + count}) of 2^20")
+    t.trace_rays(w.seed, w.n_rays, begin, count, rt.TALLY_F64)
+    ag, eg, bg_ = t.tally()
+    res = O.run(w.grid, w.lines, w.n_rays, seed=w.seed, begin=begin, count=count,
+                cells_needed_only=True)
+    ra, re = _rel(ag, res["absorbed"]), _rel(eg, res["emitted"])
+    rbal = _rel(bg_, res["balance"])
+    _say(f"  absorbed max rel {ra.max():.3e}, emitted {re.max():.3e}, balance {rbal.max():.3e}")
+    assert ra.max() <= REL and re.max() <= REL and rbal.max() <= REL
+    t.close()
+
+
 def _check_tallies(tag, got, ref):
     ag, eg, bg = got
     ra = _rel(ag, ref["absorbed"])
