@@ -271,8 +271,11 @@ struct TileGate {
 };
 
 // F32: line records from line_cell_params_f32 (the precision form).
+// active (uniform over the wavefront): false leaves this wavefront's points
+// untouched; it still stages line records with the others.
 template <bool COMP, bool F32 = false>
-__device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds) {
+__device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds,
+                           bool active = true) {
   constexpr int C = kKappaCells, P = kKappaPoints;
   constexpr int REC = kLineRec;
   const int tid = threadIdx.x;
@@ -356,6 +359,7 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
     }
     __syncthreads();
 
+    if (!active) continue;
     const int lb = max(base, w_first), le = min(base + nt, w_end);
     // lines [f_first, f_end) cover all of the wave's points: no membership test
     const int fb = min(le, max(lb, f_first)), fe = max(fb, min(le, f_end));
@@ -363,6 +367,7 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
     sum_lines(std::true_type(), base, fb, fe);
     sum_lines(std::false_type(), base, fe, le);
   }
+  if (!active) return;
 
 #pragma unroll
   for (int c = 0; c < C; ++c) {

@@ -76,12 +76,24 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs 
   const int tile = (int)(tb % a.n_tiles);
   const int64_t cg = tb / a.n_tiles;
   const int j0 = (a.tile_begin + tile) * kKappaTilePoints;
+  bool wave_on = true;
   if (a.gate.group_flag || a.gate.chunk_err) {
-    bool need = a.gate.group_flag && a.gate.group_flag[cg] == a.gate.epoch;
+    const bool marked = a.gate.group_flag && a.gate.group_flag[cg] == a.gate.epoch;
+    bool need = marked;
     if (a.gate.chunk_err) {
       const int c0 = j0 / a.gate.chunk_w;
       const int c1 = min(a.gate.n_chunks - 1, (j0 + kKappaTilePoints - 1) / a.gate.chunk_w);
       for (int k = c0; k <= c1; ++k) need = need || a.gate.chunk_err[k] > a.gate.tol;
+      // a wavefront's 64 kKappaPoints points lie in one chunk when chunks
+      // are a multiple of that span: then only the wavefronts of chunks
+      // over tolerance (or of marked cells) evaluate and write; the others
+      // only help stage the line records
+      constexpr int kSpan = 64 * kKappaPoints;
+      if (!marked && a.gate.chunk_w % kSpan == 0) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int k = (j0 + wave * kSpan) / a.gate.chunk_w;
+        wave_on = k < a.gate.n_chunks && a.gate.chunk_err[k] > a.gate.tol;
+      }
     }
     if (!need) return;
   }
@@ -90,10 +102,10 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs 
     t.line_parts = a.parts;
     t.line_part = part;
     t.out += part * a.part_stride;
-    kappa_tile<COMP, F32>(t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
+    kappa_tile<COMP, F32>(t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4), wave_on);
     return;
   }
-  kappa_tile<COMP, F32>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4));
+  kappa_tile<COMP, F32>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4), wave_on);
 }
 
 // Planck table: one block per (cell, 256-point segment of the row).
