@@ -6,7 +6,8 @@
 // ln(kappa / u) on chunk k, each output normalised by its mean and standard
 // deviation over the training spectra; kappa = u exp(mean + std * y).
 // Weights are BF16, products accumulate in FP32 on MFMA
-// (v_mfma_f32_32x32x16_bf16); the first layer (K = 4) runs on the VALU.
+// (v_mfma_f32_32x32x16_bf16); in training the first layer (K = 4) runs on
+// the VALU, in inference on MFMA with exact BF16 splits of its inputs.
 // Training data are spectra of the exact line sum (the same kernel as
 // rt_compute_kappa) for caller-supplied gas states; training is plain Adam
 // on the mean squared error of the normalised outputs, one training step
@@ -36,6 +37,7 @@ hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const dou
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ------------------------------------------------------------------ GEMM
@@ -375,15 +377,21 @@ __global__ void infer_kappa_kernel(const float* __restrict__ P, const float* __r
 }
 
 // ------------------------------------------------------------ fused inference
-// One block of 8 wavefronts takes 64 rows through all four layers.  The
-// hidden activations stay in LDS as BF16 (64 x 512, each row padded by 8
+// One block of 8 wavefronts takes 32 RT rows (RT = 2 or 3) through all four
+// layers.  The hidden activations stay in LDS as BF16 (each row padded by 8
 // elements so that the fragment reads of 32 consecutive rows spread over the
-// banks).  Each wavefront computes a 64-column slice of a hidden layer (32 of
-// the output layer) as 2 x 2 (2 x 1) tiles of 32 x 32 MFMA with FP32
-// accumulators; its weight fragments are read from L2, where the 1.3 MB of
-// BF16 weights stay.
-// The arithmetic is that of the layer-by-layer kernels (the same MFMA
-// sequence over k, the same bias and SiLU), so both give identical values.
+// banks).  Each wavefront computes a 64-column slice of a layer (32 of the
+// output layer) as RT x 2 (RT x 1) tiles of 32 x 32 MFMA with FP32
+// accumulators, layer 1 included (its K = 4 padded to one K = 16 step with
+// exact BF16 splits of the inputs and bias); its weight fragments are read
+// from L2, where the 1.3 MB of BF16 weights stay.  The layers are computed
+// transposed (see mfma_layer), so that each lane's results are runs of
+// contiguous features of one row: the epilogues write 8-byte runs to LDS,
+// and the output layer writes kappa straight from its accumulators.
+// Layers 2-4 are the layer-by-layer kernels' arithmetic (the same products
+// summed in the same k order, the same bias and SiLU); layer 1 sums its
+// exact products in the MFMA instead of an FMA chain, which moves z by an
+// FP32 rounding at most.
 // Inputs are either given features (FROM_STATE false) or gas states and the
 // chunk index of each row (row = cell * n_chunks + k); the output is either
 // the raw last layer or kappa = u exp(mean + std * y), written straight into
@@ -413,12 +421,17 @@ struct FusedArgs {
   int n_nu;
 };
 
-// C += A W over K = 512 for RT row tiles x NT column tiles: A from LDS, W in
-// fragment order from L2.  The weight fragments are loaded kPrefetch k-steps
-// ahead through a ring of registers (the k loop is unrolled so that every
-// ring index is static), which covers the L2 latency behind the MFMAs; the
-// activation fragments come from LDS one step ahead.  Two row tiles keep the
-// ring at 6 steps so that two blocks fit a CU's registers.
+// The transposed product of one layer, Z^T += W^T H^T over K = 512, for RT
+// row tiles x NT column tiles: the weights are the MFMA's A operand, the
+// activations (rows of H) its B operand, so lane l of a 32 x 32 result tile
+// holds row l % 32 and the 16 features 8 g + 4 (l / 32) + m (g, m < 4):
+// four runs of four contiguous features of one row, which the epilogues
+// store as whole runs.  Weights come in fragment order from L2, loaded
+// kPrefetch k-steps ahead through a ring of registers (the k loop is
+// unrolled so that every ring index is static), which covers the L2
+// latency behind the MFMAs; activation fragments come from LDS one step
+// ahead.  Two row tiles keep the ring at 6 steps so that two blocks fit a
+// CU's registers.
 template <int RT>
 constexpr int prefetch_steps() { return RT == 2 ? 6 : 8; }
 
@@ -459,7 +472,7 @@ __device__ __forceinline__ void mfma_layer(const bf16* __restrict__ H, const bf1
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct)
-        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[st & 1][rt], bq[st % kPrefetch][ct],
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bq[st % kPrefetch][ct], aq[st & 1][rt],
                                                                acc[rt][ct], 0, 0, 0);
     if (st + kPrefetch < kSteps)
 #pragma unroll
@@ -472,12 +485,65 @@ __device__ __forceinline__ void mfma_layer(const bf16* __restrict__ H, const bf1
   }
 }
 
+__device__ __forceinline__ float f4_at(const float4& v, int m) {
+  return m == 0 ? v.x : m == 1 ? v.y : m == 2 ? v.z : v.w;
+}
+
+// z (+ bias) -> SiLU(z) = z sigmoid(z) of a wavefront's transposed tiles
+// into H as BF16: per row tile, column tile and g, one 8-byte run of four
+// features.  Eight values at a time, so that the exponentials and
+// reciprocals of independent values interleave.
+template <int RT, int NT, bool BIAS>
+__device__ __forceinline__ void silu_to_lds(const f32x16 (&acc)[RT][NT], const float* __restrict__ b,
+                                            bf16* H, int n_base, int lane) {
+  const int h = lane >> 5;
+  float4 bb[NT][4];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      bb[ct][g] = BIAS ? *reinterpret_cast<const float4*>(b + n_base + 32 * ct + 8 * g + 4 * h)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    bf16* hrow = H + (rt * 32 + (lane & 31)) * kLdsRow + n_base + 4 * h;
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int g2 = 0; g2 < 4; g2 += 2) {
+        float z[8], e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          z[q] = acc[rt][ct][4 * g2 + q] + (BIAS ? f4_at(bb[ct][g2 + q / 4], q % 4) : 0.f);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_exp2f(-1.4426950408889634f * z[q]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_rcpf(1.0f + e[q]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          bf16x4 v;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) v[m] = (bf16)(z[4 * u + m] * e[4 * u + m]);
+          *reinterpret_cast<bf16x4*>(hrow + 32 * ct + 8 * (g2 + u)) = v;
+        }
+      }
+  }
+}
+
+// x = hi + mid + lo in BF16 parts: hi and mid exact roundings of x and of
+// x - hi (both differences are exact in FP32), lo the rounding of the rest
+// (below 2^-26 |x|)
+__device__ __forceinline__ void split3(float x, bf16& hi, bf16& mid, bf16& lo) {
+  hi = (bf16)x;
+  const float r = x - (float)hi;
+  mid = (bf16)r;
+  lo = (bf16)(r - (float)mid);
+}
+
 template <int RT, bool FROM_STATE, bool TO_KAPPA>
 __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
   constexpr int kFuseRows = 32 * RT;
-  __shared__ bf16 H[kFuseRows * kLdsRow];  // also holds the FP32 outputs
-  static_assert(kFuseRows * kLdsRow * sizeof(bf16) >= kFuseRows * kMlpWidth * sizeof(float),
-                "LDS buffer too small for the output layer");
+  __shared__ bf16 H[kFuseRows * kLdsRow];
   __shared__ __align__(16) float F[kFuseRows][4];
   __shared__ float U[kFuseRows];
   __shared__ int64_t RowBase[kFuseRows];  // kappa offset of the row's chunk (-1: no row)
@@ -487,6 +553,7 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = (int64_t)blockIdx.x * kFuseRows;
   const int n_chunks = a.bx.n_chunks;
+  const int h = lane >> 5;
   if (tid < kFuseRows) {
     const int64_t row = row0 + tid;
     float f[4] = {0.f, 0.f, 0.f, 0.f};
@@ -516,29 +583,48 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
     RowJ[tid] = k * kMlpWidth;
   }
   __syncthreads();
-  // layer 1 (K = 4) on the VALU: thread t owns column t
+  // layer 1 (K = 4) as one K = 16 MFMA per tile, exact to FP32 rounding:
+  //   k       0-3      4-7       8-11     12-14                15
+  //   input   x_hi     x_mid     x_lo     1, 1, 1              0
+  //   weight  W1       W1        W1       b_hi, b_mid, b_lo    0
+  // (W1 is BF16 already; the bias is split like the inputs).  Wavefront w
+  // computes columns [64 w, 64 w + 64).
   {
-    const int n = tid;
-    float w1[4];
+    const int n_base = wave * 64;
+    bf16x8 wq[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w1[k] = (float)a.W1k[k * kHidden + n];
-    const float b1 = a.b1[n];
-    // eight rows at a time, each step over all eight before the next, so
-    // that the exponentials and reciprocals of independent rows interleave
-    for (int r0 = 0; r0 < kFuseRows; r0 += 8) {
-      float z[8], e[8];
+    for (int ct = 0; ct < 2; ++ct) {
+      const int n = n_base + 32 * ct + (lane & 31);
+      bf16 w[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float4 f = *reinterpret_cast<const float4*>(F[r0 + q]);
-        z[q] = fmaf(f.w, w1[3], fmaf(f.z, w1[2], fmaf(f.y, w1[1], fmaf(f.x, w1[0], b1))));
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_exp2f(-1.4426950408889634f * z[q]);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_rcpf(1.0f + e[q]);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) H[(r0 + q) * kLdsRow + n] = (bf16)(z[q] * e[q]);
+      for (int k = 0; k < 4; ++k) w[k] = a.W1k[k * kHidden + n];
+      bf16 bh, bm, bl;
+      split3(a.b1[n], bh, bm, bl);
+      const bf16 zero = (bf16)0.f;
+      wq[ct] = h == 0 ? bf16x8{w[0], w[1], w[2], w[3], w[0], w[1], w[2], w[3]}
+                      : bf16x8{w[0], w[1], w[2], w[3], bh, bm, bl, zero};
     }
+    f32x16 acc[RT][2];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const float4 f = *reinterpret_cast<const float4*>(F[rt * 32 + (lane & 31)]);
+      bf16 p[3][4];
+      split3(f.x, p[0][0], p[1][0], p[2][0]);
+      split3(f.y, p[0][1], p[1][1], p[2][1]);
+      split3(f.z, p[0][2], p[1][2], p[2][2]);
+      split3(f.w, p[0][3], p[1][3], p[2][3]);
+      const bf16 one = (bf16)1.f, zero = (bf16)0.f;
+      const bf16x8 xq = h == 0 ? bf16x8{p[0][0], p[0][1], p[0][2], p[0][3],
+                                        p[1][0], p[1][1], p[1][2], p[1][3]}
+                               : bf16x8{p[2][0], p[2][1], p[2][2], p[2][3], one, one, one, zero};
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[rt][ct][i] = 0.f;
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq[ct], xq, acc[rt][ct], 0, 0, 0);
+      }
+    }
+    silu_to_lds<RT, 2, false>(acc, nullptr, H, n_base, lane);
   }
   __syncthreads();
   // layers 2 and 3: wavefront w computes columns [64 w, 64 w + 64)
@@ -549,108 +635,85 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
     f32x16 acc[RT][2];
     mfma_layer<RT, 2>(H, wt, n_base, lane, acc);
     __syncthreads();  // every wavefront has read the layer input
-    // SiLU(z) = z sigmoid(z), eight values at a time as in layer 1
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        const int col = n_base + ct * 32 + (lane & 31);
-        const float bc = b[col];
-#pragma unroll
-        for (int h = 0; h < 16; h += 8) {
-          float z[8], e[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) z[q] = acc[rt][ct][h + q] + bc;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_exp2f(-1.4426950408889634f * z[q]);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) e[q] = __builtin_amdgcn_rcpf(1.0f + e[q]);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int i = h + q;
-            const int row = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-            H[row * kLdsRow + col] = (bf16)(z[q] * e[q]);
-          }
-        }
-      }
+    silu_to_lds<RT, 2, true>(acc, b, H, n_base, lane);
     __syncthreads();
   }
-  // output layer (wavefront w: columns [32 w, 32 w + 32)); accumulators to
-  // LDS as FP32 over the activation buffer, then a row-major pass with
-  // coalesced stores
+  // output layer (wavefront w: columns [32 w, 32 w + 32)), written straight
+  // from the accumulators: per row tile and g, one 16-byte run of a row
+  // (nothing is written to LDS any more, so no barrier follows)
   {
     const int n_base = wave * 32;
     f32x16 acc[RT][1];
     mfma_layer<RT, 1>(H, a.wt4, n_base, lane, acc);
-    __syncthreads();  // every wavefront has read the last hidden layer
-    float* Z = reinterpret_cast<float*>(H);
+    const float* __restrict__ mean = a.mean;
+    const float* __restrict__ stdv = a.stdv;
+    float4 bb[4];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int g = 0; g < 4; ++g) bb[g] = *reinterpret_cast<const float4*>(a.b4 + n_base + 8 * g + 4 * h);
+    if (!TO_KAPPA) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int row = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const int col = n_base + (lane & 31);
-        Z[row * kMlpWidth + col] = acc[rt][0][i] + a.b4[col];
+      for (int rt = 0; rt < RT; ++rt) {
+        const int64_t base = RowBase[rt * 32 + (lane & 31)];
+        if (base < 0) continue;
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          *reinterpret_cast<float4*>(a.P + base + n_base + 8 * g + 4 * h) =
+              make_float4(acc[rt][0][4 * g] + bb[g].x, acc[rt][0][4 * g + 1] + bb[g].y,
+                          acc[rt][0][4 * g + 2] + bb[g].z, acc[rt][0][4 * g + 3] + bb[g].w);
       }
-    __syncthreads();
-  }
-  // Each thread takes groups of kGroup float4 runs of a row, loads all of a
-  // group's inputs before any of its outputs is stored (one memory latency
-  // per group), then writes them.  Rows, tables and kappa row offsets are
-  // multiples of 4 floats.
-  const float* Z = reinterpret_cast<const float*>(H);
-  constexpr int kRuns = kMlpWidth / 4;                      // float4 runs per row
-  constexpr int kPer = kFuseRows * kRuns / kFuseThreads;    // runs per thread
-  constexpr int kGroup = 4;
-  static_assert(kFuseRows * kRuns % kFuseThreads == 0 && kPer % kGroup == 0, "output tiling");
-  const float* __restrict__ mean = a.mean;
-  const float* __restrict__ stdv = a.stdv;
+    } else {
+      // kappa = u exp(mean + std y), to ~1e-6 relative, far inside the
+      // network's own error; zeros past n_nu.  The normalisation of every
+      // row tile is loaded before any of it is used (one L2 round trip;
+      // a missing row reads chunk 0's and stores nothing).
+      float4 m[RT][4], sd[RT][4];
 #pragma unroll
-  for (int g = 0; g < kPer; g += kGroup) {
-    float4 z[kGroup], m[kGroup], sd[kGroup];
-    int64_t base[kGroup];
-    int col[kGroup], row[kGroup];
+      for (int rt = 0; rt < RT; ++rt) {
+        const int t0 = RowK[rt * 32 + (lane & 31)] * kMlpWidth + n_base + 4 * h;
 #pragma unroll
-    for (int q = 0; q < kGroup; ++q) {
-      const int i4 = (g + q) * kFuseThreads + tid;
-      row[q] = i4 / kRuns;
-      col[q] = (i4 % kRuns) * 4;
-      base[q] = RowBase[row[q]];
-      z[q] = *reinterpret_cast<const float4*>(Z + row[q] * kMlpWidth + col[q]);
-      if (TO_KAPPA && base[q] >= 0) {
-        const int t4 = RowK[row[q]] * kMlpWidth + col[q];
-        m[q] = *reinterpret_cast<const float4*>(mean + t4);
-        sd[q] = *reinterpret_cast<const float4*>(stdv + t4);
+        for (int g = 0; g < 4; ++g) {
+          m[rt][g] = *reinterpret_cast<const float4*>(mean + t0 + 8 * g);
+          sd[rt][g] = *reinterpret_cast<const float4*>(stdv + t0 + 8 * g);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int row = rt * 32 + (lane & 31);
+        const int64_t base = RowBase[row];
+        const float u = U[row];
+        const int j0 = RowJ[row] + n_base + 4 * h;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int j = j0 + 8 * g;
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float y = acc[rt][0][4 * g + e] + f4_at(bb[g], e);
+            v[e] = j + e < a.n_nu
+                       ? u * __builtin_amdgcn_exp2f(1.4426950408889634f *
+                                                    fmaf(f4_at(sd[rt][g], e), y, f4_at(m[rt][g], e)))
+                       : 0.f;
+          }
+          if (base >= 0 && j < a.ld)
+            *reinterpret_cast<float4*>(a.kappa + base + n_base + 8 * g + 4 * h) =
+                make_float4(v[0], v[1], v[2], v[3]);
+        }
       }
     }
-#pragma unroll
-    for (int q = 0; q < kGroup; ++q) {
-      if (base[q] < 0) continue;
-      if (!TO_KAPPA) {
-        *reinterpret_cast<float4*>(a.P + base[q] + col[q]) = z[q];
-        continue;
-      }
-      // exp to ~1e-6 relative, far inside the network's own error
-      const int j = RowJ[row[q]] + col[q];
-      const float u = U[row[q]];
-      const float zz[4] = {z[q].x, z[q].y, z[q].z, z[q].w};
-      const float mm[4] = {m[q].x, m[q].y, m[q].z, m[q].w};
-      const float ss[4] = {sd[q].x, sd[q].y, sd[q].z, sd[q].w};
-      float v[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        v[e] = j + e < a.n_nu ? u * __builtin_amdgcn_exp2f(1.4426950408889634f * (mm[e] + ss[e] * zz[e]))
-                              : 0.f;
-      if (j < a.ld) *reinterpret_cast<float4*>(a.kappa + base[q] + col[q]) = make_float4(v[0], v[1], v[2], v[3]);
-    }
   }
-  if (TO_KAPPA) {  // pitch columns past the last chunk
-    const int pad0 = n_chunks * kMlpWidth;
-    for (int r = 0; r < kFuseRows; ++r) {
-      if (RowBase[r] < 0) break;
-      if (RowK[r] != n_chunks - 1) continue;
-      const int64_t rowbase = RowBase[r] - (int64_t)RowJ[r];
-      for (int64_t j = pad0 + tid; j < a.ld; j += kFuseThreads) a.kappa[rowbase + j] = 0.f;
+  // pitch columns past the last chunk: wavefront w finds the rows of its
+  // 64-row slice that hold a cell's last chunk with one ballot, then zeroes
+  // those cells' columns [n_chunks 256, ld) with all its lanes
+  const int pad0 = n_chunks * kMlpWidth;
+  if (TO_KAPPA && pad0 < a.ld && wave * 64 < kFuseRows) {
+    const int r = wave * 64 + lane;
+    const bool last = r < kFuseRows && RowBase[r] >= 0 && RowK[r] == n_chunks - 1;
+    uint64_t m = __ballot(last);
+    while (m) {
+      const int rr = wave * 64 + __builtin_ctzll(m);
+      m &= m - 1;
+      const int64_t rowbase = RowBase[rr] - (int64_t)RowJ[rr];
+      for (int64_t j = pad0 + lane; j < a.ld; j += 64) a.kappa[rowbase + j] = 0.f;
     }
   }
 }
