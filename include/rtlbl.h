@@ -433,10 +433,13 @@ typedef struct {
   int fallback_chunks;        /* chunks recomputed with the line sum         */
   int fallback_cells;         /* out-of-range cells recomputed               */
   int n_chunks;
-  double infer_ms, check_ms, fallback_ms;  /* device times, last inference:
-                                 the network; from its end to the end of the
-                                 check (whose exact line sum runs beside the
-                                 network on a second stream); the fallback  */
+  double infer_ms, check_ms, fallback_ms;  /* device times of the last
+                                 inference when it ran with phase timing on
+                                 (rt_surrogate_time_phases), else 0: the
+                                 network; from the network's end to the end
+                                 of the check (whose exact line
+                                 sum runs beside the network on a second
+                                 stream); the fallback                       */
   double train_loss;          /* mean squared normalised error, last epoch   */
   double param_count;
 } rt_surrogate_stats;
@@ -458,6 +461,15 @@ rt_status rt_surrogate_forward(rt_ctx ctx, int n_rows, const float* inputs, floa
 rt_status rt_surrogate_weights(rt_ctx ctx, float* out, int64_t n);
 
 rt_status rt_surrogate_get_stats(rt_ctx ctx, rt_surrogate_stats* out);
+
+/* Phase timing of the learned form's inference.  With on != 0, each later
+ * rt_compute_kappa call in RT_KAPPA_SURROGATE mode records timing events
+ * between its kernels (before and after the network, after the check and
+ * after the fallback), which rt_surrogate_get_stats
+ * reports; off (the default), it records none and reports the phase times
+ * as 0.  The events cost the call several microseconds.  Needs no device
+ * and no trained surrogate; RT_EINVAL for a NULL handle. */
+rt_status rt_surrogate_time_phases(rt_ctx ctx, int on);
 
 /* ------------------------------------------------------------------------
  * FP32 arithmetic characterisation of the device (the paper's Section 2

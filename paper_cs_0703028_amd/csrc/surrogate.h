@@ -63,6 +63,8 @@ struct Surrogate {
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   bool stats_pending = false;   // counts of the last inference not read yet
+  bool time_phases = false;     // attach timing events to the inference kernels
+  bool timed_last = false;      // the last inference carried them
 };
 
 

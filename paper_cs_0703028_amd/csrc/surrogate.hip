@@ -1184,9 +1184,30 @@ rt_status surrogate_kappa(rt_ctx c) {
   const int tiles_all = (int)((c->ld + dev::kKappaTilePoints - 1) / dev::kKappaTilePoints);
 
   // the exact rows of the sampled cells do not depend on the network: they
-  // are summed on the side stream while the network runs
+  // are summed on the side stream while the network runs.  The fork is
+  // recorded first, but the side stream's launches are issued after the
+  // network's, so that the handle's stream starts at once (issuing them
+  // takes the host longer than the side stream's work takes the GPU)
+  // Phase times, when asked for, come from events recorded between the
+  // kernels (before and after the network, after the check and after the
+  // fallback); each costs the call several microseconds, so by default none
+  // are recorded.
+  S.timed_last = S.time_phases;
+  auto mark = [&](int i) {
+    if (S.time_phases) (void)hipEventRecord(S.ev[i], s);
+  };
+  if (ok && n_check > 0) ok = chk(hipEventRecord(S.fork, s));
+  if (n_cells > 0)
+    hipLaunchKernelGGL(cell_features_kernel, dim3((unsigned)grid1(n_cells)), dim3(256), 0, s,
+                       c->d_T, c->d_x, c->d_p, n_cells, make_box(S), S.T_min, S.T_max, S.x_min,
+                       S.x_max, S.p_min, S.p_max, S.epoch, S.d_cell_flag, S.d_group_flag,
+                       S.d_cell_feat);
+  mark(0);
+  launch_fused(c, S, rows, nullptr, nullptr, true, s);
+  mark(1);
+  ok = ok && chk(hipGetLastError());
   if (ok && n_check > 0) {
-    ok = chk(hipEventRecord(S.fork, s)) && chk(hipStreamWaitEvent(S.side, S.fork, 0));
+    ok = chk(hipStreamWaitEvent(S.side, S.fork, 0));
     dev::KappaTile te = t;
     te.cell_list = S.d_check;
     te.n_cells = n_check;
@@ -1202,15 +1223,6 @@ rt_status surrogate_kappa(rt_ctx c) {
                          S.side, S.d_exact, part_stride, parts, part_stride);
     ok = ok && chk(hipGetLastError()) && chk(hipEventRecord(S.join, S.side));
   }
-  (void)hipEventRecord(S.ev[0], s);
-  if (n_cells > 0)
-    hipLaunchKernelGGL(cell_features_kernel, dim3((unsigned)grid1(n_cells)), dim3(256), 0, s,
-                       c->d_T, c->d_x, c->d_p, n_cells, make_box(S), S.T_min, S.T_max, S.x_min,
-                       S.x_max, S.p_min, S.p_max, S.epoch, S.d_cell_flag, S.d_group_flag,
-                       S.d_cell_feat);
-  launch_fused(c, S, rows, nullptr, nullptr, true, s);
-  ok = ok && chk(hipGetLastError());
-  (void)hipEventRecord(S.ev[1], s);
   if (ok && n_check > 0) {
     ok = chk(hipStreamWaitEvent(s, S.join, 0));
     if (ok)
@@ -1221,7 +1233,7 @@ rt_status surrogate_kappa(rt_ctx c) {
     hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(S.n_chunks)), dim3(256), 0, s, S.d_err,
                        (int64_t)S.n_chunks);
   }
-  (void)hipEventRecord(S.ev[2], s);
+  mark(2);
   if (ok) {
     dev::TileGate gate;
     gate.group_flag = S.d_group_flag;
@@ -1232,7 +1244,7 @@ rt_status surrogate_kappa(rt_ctx c) {
     gate.n_chunks = S.n_chunks;
     ok = chk(launch_kappa_tiles(c, t, groups_all, 0, tiles_all, false, s, gate));
   }
-  (void)hipEventRecord(S.ev[3], s);
+  mark(3);
   ok = ok && chk(hipGetLastError());
   S.stats_pending = true;
   if (!ok) return sfail(c, RT_EDEVICE, "surrogate inference: a HIP call failed");
@@ -1259,9 +1271,11 @@ rt_status surrogate_finish_stats(rt_ctx c) {
   }
   S.fallback_cells = (int)std::count(flag.begin(), flag.end(), S.epoch);
   float f1 = 0, f2 = 0, f3 = 0;
-  (void)hipEventElapsedTime(&f1, S.ev[0], S.ev[1]);
-  (void)hipEventElapsedTime(&f2, S.ev[1], S.ev[2]);
-  (void)hipEventElapsedTime(&f3, S.ev[2], S.ev[3]);
+  if (S.timed_last) {
+    (void)hipEventElapsedTime(&f1, S.ev[0], S.ev[1]);
+    (void)hipEventElapsedTime(&f2, S.ev[1], S.ev[2]);
+    (void)hipEventElapsedTime(&f3, S.ev[2], S.ev[3]);
+  }
   S.infer_ms = f1;
   S.check_ms = f2;
   S.fallback_ms = f3;
@@ -1293,8 +1307,10 @@ rt_status rt_surrogate_train(rt_ctx c, const rt_surrogate_cfg* cfg, double* fina
       return sfail(c, RT_EINVAL, "rt_surrogate_train: invalid sample state");
   if (c->device < 0) return sfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_SHIP(c, hipSetDevice(c->device));
+  const bool timed = c->surrogate && c->surrogate->time_phases;  // kept across a new network
   free_surrogate(c);
   Surrogate& S = surrogate(c);
+  S.time_phases = timed;
   S.n_nu = c->n_nu;
   S.n_chunks = (c->n_nu + kMlpWidth - 1) / kMlpWidth;
   S.T_min = cfg->T_min; S.T_max = cfg->T_max;
@@ -1483,6 +1499,12 @@ rt_status rt_surrogate_weights(rt_ctx c, float* out, int64_t n) {
   return RT_OK;
 }
 
+rt_status rt_surrogate_time_phases(rt_ctx c, int on) {
+  if (!c) return RT_EINVAL;
+  surrogate(c).time_phases = on != 0;
+  return RT_OK;
+}
+
 rt_status rt_surrogate_get_stats(rt_ctx c, rt_surrogate_stats* out) {
   if (!c || !out) return RT_EINVAL;
   if (!c->surrogate || !c->surrogate->trained) return sfail(c, RT_ESTATE, "rt_surrogate_get_stats: no surrogate");
@@ -1564,8 +1586,10 @@ rt_status rt_surrogate_load(rt_ctx c, const char* path) {
   if ((int64_t)blob.size() != (int64_t)off + need + 8) return sfail(c, RT_EINVAL, "rt_surrogate_load: size mismatch");
   if (c->device < 0) return sfail(c, RT_EUNSUPPORTED, "host-only handle (RT_NO_DEVICE): the call needs a device");
   RT_SHIP(c, hipSetDevice(c->device));
+  const bool timed = c->surrogate && c->surrogate->time_phases;  // kept across a new network
   free_surrogate(c);
   Surrogate& S = surrogate(c);
+  S.time_phases = timed;
   S.n_nu = hdr[1]; S.n_chunks = hdr[2]; S.check_cells = hdr[3];
   S.T_min = box[0]; S.T_max = box[1]; S.x_min = box[2]; S.x_max = box[3];
   S.p_min = box[4]; S.p_max = box[5]; S.tolerance = box[6];

@@ -132,10 +132,12 @@ def _load():
     L.rt_surrogate_forward.argtypes = [vp, C.c_int, _f32p, _f32p]
     L.rt_surrogate_weights.argtypes = [vp, _f32p, C.c_int64]
     L.rt_surrogate_get_stats.argtypes = [vp, C.POINTER(SurrogateStats)]
+    L.rt_surrogate_time_phases.argtypes = [vp, C.c_int]
     L.rt_arith_eval.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int64]
     L.rt_setup_gas.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp, vp, vp, vp]
     for f in ("rt_surrogate_train", "rt_surrogate_save", "rt_surrogate_load",
-              "rt_surrogate_forward", "rt_surrogate_weights", "rt_surrogate_get_stats"):
+              "rt_surrogate_forward", "rt_surrogate_weights", "rt_surrogate_get_stats",
+              "rt_surrogate_time_phases"):
         getattr(L, f).restype = C.c_int
     for f in ("rt_create", "rt_destroy", "rt_setup_grid", "rt_setup_lines", "rt_compute_kappa",
               "rt_trace_rays", "rt_trace_rays_noalloc", "rt_trace_explicit", "rt_tally", "rt_reset_tally",
@@ -486,6 +488,12 @@ class Tracer:
             off += d[i + 1]
             out.append((W.copy(), b.copy()))
         return out
+
+    def surrogate_time_phases(self, on=True):
+        """Timing events between the inference phases (reported by
+        surrogate_stats) on or off; off by default, since they cost each
+        call several microseconds."""
+        self._check(lib.rt_surrogate_time_phases(self._h, 1 if on else 0))
 
     def surrogate_stats(self):
         st = SurrogateStats()

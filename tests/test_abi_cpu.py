@@ -215,6 +215,25 @@ def test_host_only_call_order(rt, host):
     assert lib.rt_reset_tally(h) == rt.RT_EUNSUPPORTED
 
 
+def test_host_only_surrogate_calls(rt, host):
+    """Phase timing is a host-side switch (no device, no trained network
+    needed); the other learned-form calls still report what they lack."""
+    from paper_cs_0703028_amd import inputs as I
+    lib = rt.lib
+    h = host._h
+    assert lib.rt_surrogate_time_phases(None, 1) == rt.RT_EINVAL
+    assert lib.rt_surrogate_time_phases(h, 1) == rt.RT_OK
+    assert lib.rt_surrogate_time_phases(h, 0) == rt.RT_OK
+    st = rt.SurrogateStats()
+    assert lib.rt_surrogate_get_stats(h, ctypes.byref(st)) == rt.RT_ESTATE   # nothing trained
+    w = I.small_ragged()
+    host.setup_grid(w.grid)
+    host.setup_lines(w.lines)
+    ld = host.required_pitch()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.rt_compute_kappa(h, rt.KAPPA_SURROGATE, fake, None, ld) == rt.RT_ESTATE
+
+
 def test_host_only_batch_checks(rt, host):
     from dataclasses import replace
     from paper_cs_0703028_amd import inputs as I

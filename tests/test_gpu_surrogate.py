@@ -246,6 +246,28 @@ def test_out_of_range_cells_get_exact_kappa(rt, trained):
     t.setup_grid(w.grid)
 
 
+def test_phase_timing_is_opt_in(rt, trained):
+    """Inference takes no phase timestamps unless asked (they cost the call
+    several microseconds); asked, the network, check and fallback times are
+    positive and the kappa table is the same bit for bit."""
+    t, w = trained
+    kap, _ = t.alloc_tables()
+    t.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
+    k0 = kap.cpu().numpy().copy()
+    st = t.surrogate_stats()
+    assert st["infer_ms"] == 0 and st["check_ms"] == 0 and st["fallback_ms"] == 0
+    t.surrogate_time_phases(True)
+    try:
+        t.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
+        st = t.surrogate_stats()
+    finally:
+        t.surrogate_time_phases(False)
+    print(f"phases: network {st['infer_ms']:.4f} ms, check {st['check_ms']:.4f} ms, "
+          f"fallback {st['fallback_ms']:.4f} ms", flush=True)
+    assert st["infer_ms"] > 0 and st["check_ms"] > 0 and st["fallback_ms"] > 0
+    assert np.array_equal(kap.cpu().numpy(), k0)
+
+
 def test_save_load_roundtrip(rt, trained, tmp_path):
     t, w = trained
     path = str(tmp_path / "mlp.bin")
