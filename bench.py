@@ -579,6 +579,53 @@ def form_arith(rtlbl, I):
     }
 
 
+def form_spectral_shard(rtlbl, I, n_shards=8, steps=3):
+    """One GPU's share of the 32^3 workload split by wavenumber over n_shards
+    GPUs (shard boundaries on march chunks; the shard keeps only the lines
+    that reach its range): the largest shard with all 2^20 rays, timed as the
+    headline step.  The split run would take about the slowest shard's time
+    plus one all-reduce of 0.5 MB of tallies, which is not measured here."""
+    import torch
+    w = I.plain_32cube()
+    bounds = I.spectral_shard_bounds(w.lines.n_nu, n_shards, rtlbl.lib.rt_march_chunk())
+    lo, hi = max(bounds, key=lambda b: b[1] - b[0])
+    s = I.spectral_shard(w, lo, hi)
+    t = rtlbl.Tracer(0)
+    t.setup_grid(s.grid)
+    t.setup_lines(s.lines)
+    kap = torch.empty((s.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
+
+    def step():
+        t.reset_tally()
+        t.compute_kappa(rtlbl.KAPPA_PLAIN, kap, None)
+        t.trace_rays(s.seed, s.n_rays, 0, s.n_rays, rtlbl.TALLY_F32)
+        return t.tally()
+
+    step()
+    torch.cuda.synchronize()
+    t.stats()
+    kappa_ms = march_ms = updates = evals = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        st = t.stats()
+        kappa_ms += st["kappa_ms"]
+        march_ms += st["march_ms"]
+        updates += st["updates"]
+        evals += st["line_evals"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    t.close()
+    del kap
+    torch.cuda.empty_cache()
+    return {"workload": s.name, "n_shards": n_shards, "shard_points": hi - lo,
+            "shard_bounds": bounds, "lines": int(len(s.lines.nu)), "rays": s.n_rays,
+            "ms_per_step": dt * 1e3, "updates_per_s": updates / steps / dt,
+            "kappa_ms_per_step": kappa_ms / steps, "march_ms_per_step": march_ms / steps,
+            "march_updates_per_s": updates / (march_ms * 1e-3),
+            "line_evals_per_s": evals / (kappa_ms * 1e-3)}
+
+
 def run_forms(rtlbl, I, args):
     out = {}
     ep = args.learned_epochs
@@ -587,6 +634,7 @@ def run_forms(rtlbl, I, args):
                      ("learned_dense_lines",
                       lambda r, i: form_learned(r, i, epochs=ep, n_lines=20000)),
                      ("two_gases", form_two_gases), ("table16", form_table16),
+                     ("spectral_shard", form_spectral_shard),
                      ("adaptive", form_adaptive), ("arith", form_arith)):
         if name not in args.forms.split(","):
             continue
@@ -606,7 +654,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--forms", default="precision,batched,learned,learned_dense_lines,two_gases,table16,"
-                                       "adaptive,arith",
+                                       "spectral_shard,adaptive,arith",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--workload", default="plain_32cube")
     ap.add_argument("--no-headline", action="store_true",

@@ -202,6 +202,30 @@ def with_lines(w: Workload, **kw) -> Workload:
     return replace(w, lines=replace(w.lines, **kw))
 
 
+def spectral_shard_bounds(n_nu: int, n_shards: int, align: int) -> list:
+    """Point ranges [lo, hi) of n_shards contiguous spectral shards, their
+    boundaries on multiples of `align` points (the march chunk), so that no
+    shard pads a chunk it shares with a neighbour."""
+    units = -(-n_nu // align)
+    cuts = [min(n_nu, (units * g // n_shards) * align) for g in range(n_shards + 1)]
+    return [(cuts[g], cuts[g + 1]) for g in range(n_shards)]
+
+
+def spectral_shard(w: Workload, lo: int, hi: int) -> Workload:
+    """The workload on spectral points [lo, hi) of its grid only: the grid
+    starts at point lo, and only the lines whose cutoff window can reach the
+    range are kept (one GPU's share when a run is split by wavenumber)."""
+    L = w.lines
+    nu_lo = L.nu0 + lo * L.dnu
+    nu_hi = L.nu0 + (hi - 1) * L.dnu
+    margin = L.cutoff + L.dnu
+    keep = (L.nu >= nu_lo - margin) & (L.nu <= nu_hi + margin)
+    sub = replace(L, nu=L.nu[keep], S=L.S[keep], gamma=L.gamma[keep], n_T=L.n_T[keep],
+                  E_lower=None if L.E_lower is None else L.E_lower[keep],
+                  nu0=nu_lo, n_nu=hi - lo)
+    return replace(w, name=f"{w.name}_points_{lo}_{hi}", lines=sub)
+
+
 # A second, CO2-like absorber beside the first (H2O-like) one: its own line
 # list drawn by the same laws from other streams (seed offset), weaker median
 # strength and a steeper half-width temperature exponent, and its own mole

@@ -116,3 +116,29 @@ def test_thin_medium_emission_and_ray_weight():
     # the same rays with a known weight give a deterministic scale check
     w = O.ray_weight(g, L, N)
     assert w == pytest.approx(math.pi * 6 * (n * h) ** 2 * L.dnu / N, rel=1e-15)
+
+
+def test_spectral_shards_add_up_in_the_oracle():
+    """No step couples two wavenumbers (Eqs. (2)-(4) act point by point), so
+    runs over disjoint spectral ranges, each with only the lines that can
+    reach its range, add up to the full run: per-cell absorbed and emitted
+    power and the balance, to FP64 rounding.  This is the property the
+    spectral split of the path over several GPUs rests on; a shard whose
+    grid or line selection were off by a point or a window would break it."""
+    w = I.small_ragged()
+    w.grid.T_wall = 1250.0
+    n = 64
+    full = O.run(w.grid, w.lines, w.n_rays, seed=w.seed, count=n)
+    bounds = I.spectral_shard_bounds(w.lines.n_nu, 3, 256)
+    assert bounds[0][0] == 0 and bounds[-1][1] == w.lines.n_nu
+    assert all(b[0] % 256 == 0 and b[0] < b[1] for b in bounds)
+    assert all(bounds[k][1] == bounds[k + 1][0] for k in range(len(bounds) - 1))
+    tot = {k: np.zeros_like(full[k]) for k in ("absorbed", "emitted", "balance")}
+    for lo, hi in bounds:
+        s = I.spectral_shard(w, lo, hi)
+        assert len(s.lines.nu) < len(w.lines.nu)
+        part = O.run(s.grid, s.lines, w.n_rays, seed=w.seed, count=n)
+        for k in tot:
+            tot[k] += part[k]
+    for k in tot:
+        assert np.allclose(tot[k], full[k], rtol=1e-12, atol=0), k
