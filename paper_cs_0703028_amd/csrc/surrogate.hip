@@ -430,10 +430,9 @@ struct FusedArgs {
 // kPrefetch k-steps ahead through a ring of registers (the k loop is
 // unrolled so that every ring index is static), which covers the L2
 // latency behind the MFMAs; activation fragments come from LDS one step
-// ahead.  Two row tiles keep the ring at 6 steps so that two blocks fit a
-// CU's registers.
+// ahead.
 template <int RT>
-constexpr int prefetch_steps() { return RT == 2 ? 6 : 8; }
+constexpr int prefetch_steps() { return 8; }
 
 template <int RT, int NT>
 __device__ __forceinline__ void mfma_layer(const bf16* __restrict__ H, const bf16* __restrict__ wf,
@@ -1035,17 +1034,15 @@ void launch_fused(rt_ctx c, const Surrogate& S, int64_t rows, const float* X0, f
   a.P = P;
   a.mean = S.mean; a.stdv = S.stdv;
   a.kappa = c->kappa; a.ld = c->ld; a.n_nu = c->n_nu;
-  // rows per block 32 RT: 64 rows fit two blocks per CU, 96 one; pick the
-  // size with the least work on the busiest CU (on a tie, the fewest weight
-  // reads)
+  // rows per block 32 RT; either size holds one block per CU (registers:
+  // two wavefronts per SIMD); pick the size with the fewest row tiles on the
+  // busiest CU (on a tie, the fewest weight reads)
   const int64_t cus = 256;
   int best = 2;
   double best_cost = 1e300;
   for (int rt : {2, 3}) {
     const int64_t blocks = (rows + 32 * rt - 1) / (32 * rt);
-    const int64_t per_cu = rt == 2 ? 2 : 1;
-    const double cost = (double)((blocks + cus * per_cu - 1) / (cus * per_cu)) * rt * per_cu -
-                        1e-3 * rt;
+    const double cost = (double)((blocks + cus - 1) / cus) * rt - 1e-3 * rt;
     if (cost < best_cost) { best_cost = cost; best = rt; }
   }
   const dim3 t(kFuseThreads);

@@ -82,12 +82,13 @@ def _bf16(a):
     return torch.as_tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float32)
 
 
-def test_forward_matches_torch(rt, trained):
+@pytest.mark.parametrize("n_rows", [200, 20000])   # blocks of 64 and of 96 rows
+def test_forward_matches_torch(rt, trained, n_rows):
     import torch
     t, _ = trained
     params = t.surrogate_weights()
     rng = np.random.default_rng(0)
-    X = rng.uniform(-1, 1, (200, 4)).astype(np.float32)
+    X = rng.uniform(-1, 1, (n_rows, 4)).astype(np.float32)
     got = t.surrogate_forward(X)
     h = torch.as_tensor(X)
     for i, (W, b) in enumerate(params):
@@ -97,12 +98,19 @@ def test_forward_matches_torch(rt, trained):
         else:
             h = z
     ref = h.numpy()
-    err = np.abs(got - ref).max()
+    err = np.abs(got - ref)
     scale = 1.0 + np.abs(ref).max()
-    print(f"forward max abs err {err:.3e} (scale {scale:.3e})", flush=True)
-    # FP32 sums in another order can move a hidden activation across a BF16
-    # rounding boundary (2^-8 relative) now and then
-    assert err <= 5e-4 * scale
+    q = np.quantile(err, [0.5, 0.99])
+    flipped = float((err.max(axis=1) > 1e-3 * scale).mean())
+    print(f"forward abs err median {q[0]:.3e}, 99% {q[1]:.3e}, max {err.max():.3e} "
+          f"(scale {scale:.3e}); rows over 1e-3 scale: {flipped:.2%}", flush=True)
+    # the bulk agrees to FP32 rounding of the sums; FP32 sums in another
+    # order move a hidden activation across a BF16 rounding boundary (2^-8
+    # relative) now and then, and such a row's outputs move by up to about
+    # 1e-2 of the scale (measured over 20,000 rows: 0.2% of the rows over
+    # 1e-3 of it, the worst at 2.7e-3)
+    assert q[0] <= 1e-5 * scale and q[1] <= 1e-4 * scale
+    assert flipped <= 0.01 and err.max() <= 1e-2 * scale
 
 
 def test_trained_network_drives_the_march(rt, bench_trained):
@@ -244,6 +252,48 @@ def test_out_of_range_cells_get_exact_kappa(rt, trained):
         np.testing.assert_array_equal(kap[c].cpu().numpy(), k_ref[c].cpu().numpy())
     r.close()
     t.setup_grid(w.grid)
+
+
+def _blob_with_tolerance(rt, t, path, tol):
+    """The saved model with its check tolerance replaced (checksum redone)."""
+    import struct
+    t.surrogate_save(path)
+    blob = bytearray(open(path, "rb").read())
+    struct.pack_into("<d", blob, 8 + 16 + 6 * 8, tol)   # the box's seventh double
+    blob[-8:] = struct.pack("<Q", _fnv1a64(bytes(blob[:-8])))
+    open(path, "wb").write(bytes(blob))
+
+
+def test_kappa_rows_do_not_depend_on_the_block_grouping(rt, trained, tmp_path):
+    """A (cell, chunk) row's kappa is the same bit for bit whichever block
+    of the fused network computes it: 64 cells of the 8^3 grid (20,480 rows,
+    blocks of 96 rows) copied into a 4^3 grid (2,560 rows, blocks of 64),
+    with the check disabled so that no chunk falls back on either grid."""
+    from dataclasses import replace
+    t, w = trained
+    path = str(tmp_path / "mlp_nocheck.bin")
+    _blob_with_tolerance(rt, t, path, 1e30)
+    big = rt.Tracer(0)
+    big.setup_grid(w.grid)
+    big.setup_lines(w.lines)
+    big.surrogate_load(path)
+    k8, _ = big.alloc_tables()
+    big.compute_kappa(rt.KAPPA_SURROGATE, k8, None)
+    assert big.surrogate_stats()["fallback_chunks"] == 0
+    pick = np.random.default_rng(4).choice(w.grid.n_cells, 64, replace=False)
+    g4 = replace(w.grid, nx=4, ny=4, nz=4, T=w.grid.T[pick].copy(), x=w.grid.x[pick].copy(),
+                 p=w.grid.p[pick].copy())
+    small = rt.Tracer(0)
+    small.setup_grid(g4)
+    small.setup_lines(w.lines)
+    small.surrogate_load(path)
+    k4, _ = small.alloc_tables()
+    small.compute_kappa(rt.KAPPA_SURROGATE, k4, None)
+    st = small.surrogate_stats()
+    assert st["fallback_chunks"] == 0 and st["fallback_cells"] == 0
+    np.testing.assert_array_equal(k4.cpu().numpy(), k8.cpu().numpy()[pick])
+    big.close()
+    small.close()
 
 
 def test_phase_timing_is_opt_in(rt, trained):
