@@ -121,3 +121,27 @@ def test_gas_removal_and_refusals(rt):
     assert e.value.status == rt.RT_EUNSUPPORTED
     for h in (t, ref, fresh):
         h.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_two_gas_full_size_32cube_sampled_rows(rt, O, mode):
+    """The 32^3 workload with its second gas (20,000 + 10,000 lines, 50,000
+    points), the whole table on the GPU as bench computes it; 64 seeded
+    cells' rows against the oracle's sum of the two line sums."""
+    import torch
+    w = I.plain_32cube_two_gases()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    print(f"two-gas kappa 32^3 mode {mode}", flush=True)
+    kap, _ = t.compute_kappa(mode)
+    cells = np.sort(np.random.default_rng(11).choice(w.grid.n_cells, 64, replace=False))
+    kg = kap[torch.as_tensor(cells, device=kap.device)].cpu().numpy()
+    t.close()
+    del kap
+    torch.cuda.empty_cache()
+    n_nu = w.lines.n_nu
+    ko = O.kappa_gases(w.grid, w.lines, w.gases, cells.astype(np.int32))
+    assert (kg[:, n_nu:] == 0).all()
+    r = _rel(kg[:, :n_nu], ko)
+    print(f"  kappa rel err max {r.max():.3e} median {np.median(r):.3e}", flush=True)
+    assert r.max() <= REL

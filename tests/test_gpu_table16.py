@@ -83,3 +83,25 @@ def test_table16_needs_eight_point_cutoff(rt):
         t.compute_kappa(rt.KAPPA_TABLE16)
     assert e.value.status == rt.RT_EUNSUPPORTED
     t.close()
+
+
+def test_table16_full_size_32cube_sampled_rows(rt, O):
+    """The 16-point kappa of the whole 32^3 table (20,000 lines, 50,000
+    points), as bench computes it; 64 seeded cells' rows against the oracle."""
+    import torch
+    w = I.plain_32cube()
+    t = rt.Tracer(0)
+    t.setup_workload(w)
+    kap, _ = t.compute_kappa(rt.KAPPA_TABLE16)
+    cells = np.sort(np.random.default_rng(12).choice(w.grid.n_cells, 64, replace=False))
+    kg = kap[torch.as_tensor(cells, device=kap.device)].cpu().numpy().astype(np.float64)
+    t.close()
+    del kap
+    torch.cuda.empty_cache()
+    n_nu = w.lines.n_nu
+    ko = O.kappa_table16(w.grid, w.lines, cells.astype(np.int32))
+    assert (kg[:, n_nu:] == 0).all()
+    r = _rel(kg[:, :n_nu], ko)
+    print(f"table16 32^3 sampled rows: rel err max {r.max():.3e} median {np.median(r):.3e}",
+          flush=True)
+    assert r.max() <= REL
