@@ -129,11 +129,13 @@ void free_lineset(rt::LineSet& L) {
   dev_free(L.m); dev_free(L.phi); dev_free(L.wlo); dev_free(L.whi); dev_free(L.S);
   dev_free(L.E2); dev_free(L.nu); dev_free(L.gamma); dev_free(L.nexp); dev_free(L.prof16);
   dev_free(L.tile16);
+  dev_free(L.span4);
   dev_free(L.r64); dev_free(L.S64); dev_free(L.g64); dev_free(L.n64);
   dev_free(L.aE); dev_free(L.rN);
   dev_free(L.E2p); dev_free(L.nup);
   L.n = 0;
   L.n_tiles16 = 0;
+  L.n_spans = 0;
 }
 
 void free_lines(rt_ctx c) { free_lineset(c->lines); }
@@ -516,6 +518,23 @@ rt_status build_lines(rt_ctx c, const char* who, int n_lines, const double* nu, 
   RT_HIP(c, dev_alloc(&L.tile16, (size_t)n_t16));
   RT_HIP(c, hipMemcpy(L.tile16, ht16.data(), (size_t)n_t16 * sizeof(int2), hipMemcpyHostToDevice));
   L.n_tiles16 = n_t16;
+  // per 64-point span, the four line-range bounds of LineSet::span4 (the
+  // window bounds are non-decreasing along the sorted list)
+  const int n_sp = (nl > 0 ? std::max(0, hwhi[nl - 1]) : 0) / 64 + 2;
+  std::vector<int4> hsp(n_sp);
+  for (int b = 0; b < n_sp; ++b) {
+    const int v0 = 64 * b, v1 = 64 * b + 63;
+    auto ge = [&](const std::vector<int32_t>& a, int v) {
+      return (int)(std::lower_bound(a.begin(), a.end(), v) - a.begin());
+    };
+    auto gt = [&](const std::vector<int32_t>& a, int v) {
+      return (int)(std::upper_bound(a.begin(), a.end(), v) - a.begin());
+    };
+    hsp[b] = make_int4(ge(hwhi, v0), gt(hwlo, v1), ge(hwhi, v1), gt(hwlo, v0));
+  }
+  RT_HIP(c, dev_alloc(&L.span4, (size_t)n_sp));
+  RT_HIP(c, hipMemcpy(L.span4, hsp.data(), (size_t)n_sp * sizeof(int4), hipMemcpyHostToDevice));
+  L.n_spans = n_sp;
   if (nl > 0) {
     RT_HIP(c, hipMemcpy(L.prof16, hprof.data(), (size_t)nl * 16 * sizeof(float), hipMemcpyHostToDevice));
     RT_HIP(c, hipMemcpy(L.m, hm.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice));

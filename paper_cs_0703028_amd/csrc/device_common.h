@@ -272,11 +272,13 @@ struct TileGate {
 
 // F32: line records from line_cell_params_f32 (the precision form).
 // active (uniform over the wavefront): false leaves this wavefront's points
-// untouched; it still stages line records with the others.
-template <bool COMP, bool F32 = false>
+// untouched; it still stages line records with the others.  P: points per
+// lane (the tile is 256 P points); every point's sum runs over the same
+// lines in the same order whatever P is, so the values do not depend on it.
+template <bool COMP, bool F32 = false, int P = kKappaPoints>
 __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds,
                            bool active = true) {
-  constexpr int C = kKappaCells, P = kKappaPoints;
+  constexpr int C = kKappaCells;
   constexpr int REC = kLineRec;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -285,15 +287,21 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
   const int wj0 = j0 + wave * span;
 
   const int nl = a.L.n;
-  int blk_first = first_ge(a.L.whi, nl, j0);
-  int blk_end = first_gt(a.L.wlo, nl, j0 + kKappaTilePoints - 1);
+  // line ranges of the block's points and of the wavefront's (both start
+  // and end on 64-point spans)
+  auto bound = [&](int b, int k) {  // field k of span b (all n past the table)
+    return b < a.L.n_spans ? reinterpret_cast<const int*>(a.L.span4)[4 * b + k] : nl;
+  };
+  int blk_first = bound(j0 / 64, 0);
+  int blk_end = bound((j0 + kKappaThreads * P - 1) / 64, 1);
   if (a.line_parts > 1) {
     const int share = (blk_end - blk_first + a.line_parts - 1) / a.line_parts;
     blk_first = min(blk_end, blk_first + a.line_part * share);
     blk_end = min(blk_end, blk_first + share);
   }
-  const int w_first = first_ge(a.L.whi, nl, wj0);
-  const int w_end = first_gt(a.L.wlo, nl, wj0 + span - 1);
+  const int wb0 = wj0 / 64, wb1 = (wj0 + span - 1) / 64;
+  const int w_first = bound(wb0, 0);
+  const int w_end = bound(wb1, 1);
 
   float jf[P];
 #pragma unroll
@@ -301,8 +309,8 @@ __device__ void kappa_tile(const KappaTile& a, int j0, int64_t cell0, float* lds
 
   // windows are non-decreasing along the sorted list, so the lines whose
   // window covers [wj0, wj0 + span) are the contiguous range [f_first, f_end)
-  const int f_first = first_ge(a.L.whi, nl, wj0 + span - 1);
-  const int f_end = first_gt(a.L.wlo, nl, wj0);
+  const int f_first = bound(wb1, 2);
+  const int f_end = bound(wb0, 3);
 
   float acc[P][C];
   float cmp[P][C];

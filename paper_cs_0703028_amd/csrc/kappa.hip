@@ -68,27 +68,31 @@ struct KappaArgs {
   int64_t part_stride = 0;   // floats between the shares' outputs
 };
 
-template <bool COMP, bool F32 = false>
-__global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs a) {
+// The plain sum is held to 64 registers (eight wavefronts per SIMD), the
+// compensated one needs more.
+template <bool COMP, bool F32 = false, int P = kKappaPoints>
+__global__ __launch_bounds__(kKappaThreads)
+__attribute__((amdgpu_waves_per_eu(COMP ? 1 : 8))) void kappa_linesum_kernel(KappaArgs a) {
   __shared__ float4 lds4[kLineTile * (4 + 2 * kKappaCells) / 4];
   const int part = (int)(blockIdx.x % (unsigned)a.parts);
   const int64_t tb = blockIdx.x / (unsigned)a.parts;
   const int tile = (int)(tb % a.n_tiles);
   const int64_t cg = tb / a.n_tiles;
-  const int j0 = (a.tile_begin + tile) * kKappaTilePoints;
+  constexpr int kTilePoints = kKappaThreads * P;
+  const int j0 = (a.tile_begin + tile) * kTilePoints;
   bool wave_on = true;
   if (a.gate.group_flag || a.gate.chunk_err) {
     const bool marked = a.gate.group_flag && a.gate.group_flag[cg] == a.gate.epoch;
     bool need = marked;
     if (a.gate.chunk_err) {
       const int c0 = j0 / a.gate.chunk_w;
-      const int c1 = min(a.gate.n_chunks - 1, (j0 + kKappaTilePoints - 1) / a.gate.chunk_w);
+      const int c1 = min(a.gate.n_chunks - 1, (j0 + kTilePoints - 1) / a.gate.chunk_w);
       for (int k = c0; k <= c1; ++k) need = need || a.gate.chunk_err[k] > a.gate.tol;
-      // a wavefront's 64 kKappaPoints points lie in one chunk when chunks
-      // are a multiple of that span: then only the wavefronts of chunks
-      // over tolerance (or of marked cells) evaluate and write; the others
-      // only help stage the line records
-      constexpr int kSpan = 64 * kKappaPoints;
+      // a wavefront's 64 P points lie in one chunk when chunks are a
+      // multiple of that span: then only the wavefronts of chunks over
+      // tolerance (or of marked cells) evaluate and write; the others only
+      // help stage the line records
+      constexpr int kSpan = 64 * P;
       if (!marked && a.gate.chunk_w % kSpan == 0) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int k = (j0 + wave * kSpan) / a.gate.chunk_w;
@@ -102,10 +106,10 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_linesum_kernel(KappaArgs 
     t.line_parts = a.parts;
     t.line_part = part;
     t.out += part * a.part_stride;
-    kappa_tile<COMP, F32>(t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4), wave_on);
+    kappa_tile<COMP, F32, P>(t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4), wave_on);
     return;
   }
-  kappa_tile<COMP, F32>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4), wave_on);
+  kappa_tile<COMP, F32, P>(a.t, j0, cg * kKappaCells, reinterpret_cast<float*>(lds4), wave_on);
 }
 
 // Planck table: one block per (cell, 256-point segment of the row).
@@ -338,6 +342,26 @@ hipError_t launch_kappa_tiles(rt_ctx c, const KappaTile& t, int64_t n_cell_group
   else
     hipLaunchKernelGGL((kappa_linesum_kernel<false>), dim3((unsigned)blocks), dim3(kKappaThreads),
                        0, s, a);
+  return hipGetLastError();
+}
+
+// The plain line sum in 256-point tiles of one point per lane: twice the
+// blocks of launch_kappa_tiles, each with half its work, for launches that
+// cover only part of the table (the learned form's fallback), where the
+// latency of one block rather than the total work sets the time.  The
+// values are the same bit for bit.
+hipError_t launch_kappa_tiles_fine(rt_ctx c, const KappaTile& t, int64_t n_cell_groups,
+                                   int n_tiles, hipStream_t s, const TileGate& gate) {
+  KappaArgs a;
+  a.t = t;
+  a.gate = gate;
+  a.n_tiles = n_tiles;
+  a.tile_begin = 0;
+  const int64_t blocks = n_cell_groups * n_tiles;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((kappa_linesum_kernel<false, false, 1>), dim3((unsigned)blocks),
+                     dim3(kKappaThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -50,6 +50,15 @@ struct LineSet {
   // sorted list, int2 per tile (t = 0 .. n_tiles16 - 1)
   int2* tile16 = nullptr;
   int n_tiles16 = 0;
+  // per 64-point span b of the grid (points 64 b .. 64 b + 63), indices into
+  // the sorted list: x the first line whose window reaches point 64 b or
+  // beyond (whi >= 64 b), y the first starting beyond point 64 b + 63
+  // (wlo > 64 b + 63), z the first with whi >= 64 b + 63, w the first with
+  // wlo > 64 b.  The line sum's blocks and wavefronts start and end on
+  // spans, so their line ranges are table reads instead of binary searches.
+  // Spans from n_spans on lie past every window: (n, n, n, n).
+  int4* span4 = nullptr;
+  int n_spans = 0;
   // binary64 line data for the adaptive windows: r = (nu - nu0)/dnu,
   // S_ref, gamma_ref, n_T, a = -c2 E and 1/expm1(-c2 nu / T_ref)
   double* r64 = nullptr;

@@ -33,6 +33,9 @@ namespace rt {
 
 hipError_t launch_cell_params_on(rt_ctx c, int64_t n, const double* T, const double* x,
                                  const double* p, const CellSet& cells, hipStream_t s);
+// the plain line sum in 256-point tiles (kappa.hip)
+hipError_t launch_kappa_tiles_fine(rt_ctx c, const dev::KappaTile& t, int64_t n_cell_groups,
+                                   int n_tiles, hipStream_t s, const dev::TileGate& gate);
 
 namespace {
 
@@ -1239,7 +1242,8 @@ rt_status surrogate_kappa(rt_ctx c) {
     gate.tol = (float)S.tolerance;
     gate.chunk_w = kMlpWidth;
     gate.n_chunks = S.n_chunks;
-    ok = chk(launch_kappa_tiles(c, t, groups_all, 0, tiles_all, false, s, gate));
+    const int tiles_fine = (int)((c->ld + dev::kKappaThreads - 1) / dev::kKappaThreads);
+    ok = chk(launch_kappa_tiles_fine(c, t, groups_all, tiles_fine, s, gate));
   }
   mark(3);
   ok = ok && chk(hipGetLastError());
