@@ -322,20 +322,6 @@ __global__ void gather_kernel(const int32_t* __restrict__ perm, const int* step,
   }
 }
 
-// Inference rows: row = cell * n_chunks + k.
-__global__ void infer_features_kernel(const double* __restrict__ T, const double* __restrict__ x,
-                                      const double* __restrict__ p, int64_t n_cells, Box bx,
-                                      int M, float* X0) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= M) return;
-  float f[4] = {0, 0, 0, 0};
-  if (row < n_cells * bx.n_chunks) {
-    const int64_t cell = row / bx.n_chunks;
-    features(bx, T[cell], x[cell], p[cell], (int)(row % bx.n_chunks), f);
-  }
-  for (int q = 0; q < 4; ++q) X0[4 * row + q] = f[q];
-}
-
 __device__ __forceinline__ double gas_density(double T, double x, double p) {
   return x * p * kAtm / (kBoltzmann * T) * 1e-6;
 }
@@ -360,25 +346,6 @@ __global__ void cell_features_kernel(const double* __restrict__ T, const double*
   }
 }
 
-// kappa[cell][k*256 + i] = u exp(mean + std * y), 0 beyond n_nu.
-__global__ void infer_kappa_kernel(const float* __restrict__ P, const float* __restrict__ mean,
-                                   const float* __restrict__ stdv, const double* __restrict__ T,
-                                   const double* __restrict__ x, const double* __restrict__ p,
-                                   int64_t n_cells, int n_chunks, int n_nu, int64_t ld,
-                                   float* kappa) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_cells * ld) return;
-  const int64_t cell = i / ld, j = i % ld;
-  float v = 0.f;
-  if (j < n_nu) {
-    const int k = (int)(j / kMlpWidth), o = (int)(j % kMlpWidth);
-    const int64_t row = cell * n_chunks + k;
-    const float y = mean[k * kMlpWidth + o] + stdv[k * kMlpWidth + o] * P[row * kMlpWidth + o];
-    v = (float)(gas_density(T[cell], x[cell], p[cell]) * exp((double)y));
-  }
-  kappa[i] = v;
-}
-
 // ------------------------------------------------------------ fused inference
 // One block of 8 wavefronts takes 32 RT rows (RT = 2 or 3) through all four
 // layers.  The hidden activations stay in LDS as BF16 (each row padded by 8
@@ -396,7 +363,9 @@ __global__ void infer_kappa_kernel(const float* __restrict__ P, const float* __r
 // exact products in the MFMA instead of an FMA chain, which moves z by an
 // FP32 rounding at most.
 // Inputs are either given features (FROM_STATE false) or gas states and the
-// chunk index of each row (row = cell * n_chunks + k); the output is either
+// chunk index of each row, chunk-major (row = k * n_cells + cell, so that the
+// rows of a wavefront mostly share their chunk's output normalisation, read
+// once per wavefront instead of gathered row by row); the output is either
 // the raw last layer or kappa = u exp(mean + std * y), written straight into
 // the table with zeros beyond n_nu.
 constexpr int kFuseThreads = 512;  // 8 wavefronts
@@ -413,6 +382,7 @@ struct FusedArgs {
   const bf16* wt4;
   const float* b4;
   int64_t rows;
+  int64_t n_cells;  // FROM_STATE: rows = n_chunks x n_cells
   const float* X0;  // [rows][4] features
   const float4* cell_feat;  // per cell: three state features and u
   Box bx;
@@ -556,6 +526,16 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * kFuseRows;
   const int n_chunks = a.bx.n_chunks;
   const int h = lane >> 5;
+  if (TO_KAPPA) {
+    // the pitch columns [n_chunks 256, ld) of every cell are zero: each block
+    // clears those of an equal share of the cells (no block is left with
+    // more than a few rows of them)
+    const int64_t pad0 = (int64_t)n_chunks * kMlpWidth;
+    const int64_t share = (a.n_cells + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * share, c1 = min(a.n_cells, c0 + share);
+    for (int64_t c = c0; c < c1; ++c)
+      for (int64_t j = pad0 + tid; j < a.ld; j += kFuseThreads) a.kappa[c * a.ld + j] = 0.f;
+  }
   if (tid < kFuseRows) {
     const int64_t row = row0 + tid;
     float f[4] = {0.f, 0.f, 0.f, 0.f};
@@ -564,8 +544,8 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
     int k = 0;
     if (row < a.rows) {
       if (FROM_STATE) {
-        const int64_t cell = row / n_chunks;
-        k = (int)(row - cell * n_chunks);
+        k = (int)(row / a.n_cells);
+        const int64_t cell = row - (int64_t)k * a.n_cells;
         const float4 cf = a.cell_feat[cell];
         f[0] = cf.x;
         f[1] = cf.y;
@@ -701,21 +681,6 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
                 make_float4(v[0], v[1], v[2], v[3]);
         }
       }
-    }
-  }
-  // pitch columns past the last chunk: wavefront w finds the rows of its
-  // 64-row slice that hold a cell's last chunk with one ballot, then zeroes
-  // those cells' columns [n_chunks 256, ld) with all its lanes
-  const int pad0 = n_chunks * kMlpWidth;
-  if (TO_KAPPA && pad0 < a.ld && wave * 64 < kFuseRows) {
-    const int r = wave * 64 + lane;
-    const bool last = r < kFuseRows && RowBase[r] >= 0 && RowK[r] == n_chunks - 1;
-    uint64_t m = __ballot(last);
-    while (m) {
-      const int rr = wave * 64 + __builtin_ctzll(m);
-      m &= m - 1;
-      const int64_t rowbase = RowBase[rr] - (int64_t)RowJ[rr];
-      for (int64_t j = pad0 + lane; j < a.ld; j += 64) a.kappa[rowbase + j] = 0.f;
     }
   }
 }
@@ -1031,6 +996,7 @@ void launch_fused(rt_ctx c, const Surrogate& S, int64_t rows, const float* X0, f
   a.wt3 = S.wf[2]; a.b3 = S.b[2];
   a.wt4 = S.wf[3]; a.b4 = S.b[3];
   a.rows = rows;
+  a.n_cells = S.n_chunks > 0 ? rows / S.n_chunks : 0;
   a.X0 = X0;
   a.cell_feat = S.d_cell_feat;
   a.bx = make_box(S);
