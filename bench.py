@@ -318,13 +318,15 @@ def form_batched(rtlbl, I):
     }
 
 
-def form_learned(rtlbl, I, epochs=40, n_lines=None):
+def form_learned(rtlbl, I, epochs=40, n_lines=None, model_path=None):
     """Learned form on the 8^3 workload: train the MLP on 2^16 line-sum
     spectra, then take kappa from it (range check, sampled check, line-sum
     fallback) for the plain march; error and speed-up against the line sum.
     n_lines replaces the 500-line list by a denser one over the same
     1000-1100 cm^-1 (the line sum's cost grows with it, the network's does
-    not)."""
+    not).  model_path: load the network from there if the file exists,
+    otherwise train and save it there (so that a profiled run need not
+    train)."""
     import numpy as np
     import torch
     w = I.plain_8cube()
@@ -335,11 +337,17 @@ def form_learned(rtlbl, I, epochs=40, n_lines=None):
     t = rtlbl.Tracer(0)
     t.setup_grid(w.grid)
     t.setup_lines(w.lines)
-    T, x, p = I.surrogate_samples(1 << 16, seed=0)
     t0 = time.perf_counter()
-    loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=epochs, batch=1024, lr=1e-3,
-                             seed=0, check_cells=32, tolerance=5e-4)
-    train_s = time.perf_counter() - t0
+    if model_path and os.path.exists(model_path):
+        t.surrogate_load(model_path)
+        loss = None
+    else:
+        T, x, p = I.surrogate_samples(1 << 16, seed=0)
+        loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=epochs, batch=1024, lr=1e-3,
+                                 seed=0, check_cells=32, tolerance=5e-4)
+        if model_path:
+            t.surrogate_save(model_path)
+    train_s = time.perf_counter() - t0 if loss is not None else None
     kap = torch.empty((w.grid.n_cells, t.required_pitch()), dtype=torch.float32, device="cuda")
 
     def run(mode, reps=5):
@@ -375,7 +383,7 @@ def form_learned(rtlbl, I, epochs=40, n_lines=None):
         "workload": w.name,
         "train_s": train_s,
         "train_samples": 1 << 16,
-        "epochs": epochs,
+        "epochs": epochs if loss is not None else None,
         "train_mse_normalised": loss,
         "kappa_ms_surrogate": t_sur * 1e3,
         "kappa_ms_plain_line_sum": t_plain * 1e3,
@@ -630,7 +638,8 @@ def run_forms(rtlbl, I, args):
     out = {}
     ep = args.learned_epochs
     for name, fn in (("precision", form_precision), ("batched", form_batched),
-                     ("learned", lambda r, i: form_learned(r, i, epochs=ep)),
+                     ("learned", lambda r, i: form_learned(r, i, epochs=ep,
+                                                           model_path=args.learned_model)),
                      ("learned_dense_lines",
                       lambda r, i: form_learned(r, i, epochs=ep, n_lines=20000)),
                      ("two_gases", form_two_gases), ("table16", form_table16),
@@ -661,6 +670,9 @@ def main():
                     help="run only the forms (for profiling one form); no headline record")
     ap.add_argument("--learned-epochs", type=int, default=40,
                     help="training epochs of the learned forms")
+    ap.add_argument("--learned-model", default=None,
+                    help="the 8^3 learned form's network: loaded from this file if it "
+                         "exists, else trained and saved there (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device once (calibrates HBM byte counters)")
     args = ap.parse_args()
