@@ -483,8 +483,12 @@ __global__ __launch_bounds__(kKappaThreads) __attribute__((amdgpu_waves_per_eu(6
   const int span = ROW * P;                         // points of one pass
   const int wj0 = j0 + wave * 64 * kKappaPoints;
   const int nl = a.L.n;
-  const int blk_first = first_ge(a.L.whi, nl, j0);
-  const int blk_end = first_gt(a.L.wlo, nl, j0 + kKappaTilePoints - 1);
+  // the block's line range from the per-span table (tiles start and end on
+  // 64-point spans)
+  const int b0 = j0 / 64, b1 = (j0 + kKappaTilePoints - 1) / 64;
+  const int* sp = reinterpret_cast<const int*>(a.L.span4);
+  const int blk_first = b0 < a.L.n_spans ? sp[4 * b0] : nl;
+  const int blk_end = b1 < a.L.n_spans ? sp[4 * b1 + 1] : nl;
   const uint32_t* wrow = win + run * (int64_t)nl;
 
   float jf[NQ][P];
