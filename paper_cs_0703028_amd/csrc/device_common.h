@@ -127,23 +127,6 @@ __device__ __forceinline__ float planck_f32(Pair nu, Pair theta, float c1) {
   return c1 * v * v * v / em1;
 }
 
-__device__ __forceinline__ int first_ge(const int32_t* a, int n, int v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (a[mid] >= v) hi = mid; else lo = mid + 1;
-  }
-  return lo;
-}
-__device__ __forceinline__ int first_gt(const int32_t* a, int n, int v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (a[mid] > v) hi = mid; else lo = mid + 1;
-  }
-  return lo;
-}
-
 // Knuth's TwoSum: s + x = s' + err exactly.
 __device__ __forceinline__ void two_sum_acc(float& s, float& comp, float x) {
   float t = s + x;
