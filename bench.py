@@ -318,7 +318,13 @@ def form_batched(rtlbl, I):
     }
 
 
-def form_learned(rtlbl, I, epochs=40, n_lines=None, model_path=None):
+# the learned form's training: 2^16 states, batch 1024, Adam with a cosine
+# decay from this initial step
+LEARNED_EPOCHS = 80
+LEARNED_LR = 2e-3
+
+
+def form_learned(rtlbl, I, epochs=LEARNED_EPOCHS, n_lines=None, model_path=None):
     """Learned form on the 8^3 workload: train the MLP on 2^16 line-sum
     spectra, then take kappa from it (range check, sampled check, line-sum
     fallback) for the plain march; error and speed-up against the line sum.
@@ -343,8 +349,8 @@ def form_learned(rtlbl, I, epochs=40, n_lines=None, model_path=None):
         loss = None
     else:
         T, x, p = I.surrogate_samples(1 << 16, seed=0)
-        loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=epochs, batch=1024, lr=1e-3,
-                                 seed=0, check_cells=32, tolerance=5e-4)
+        loss = t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=epochs, batch=1024,
+                                 lr=LEARNED_LR, seed=0, check_cells=32, tolerance=5e-4)
         if model_path:
             t.surrogate_save(model_path)
     train_s = time.perf_counter() - t0 if loss is not None else None
@@ -668,7 +674,7 @@ def main():
     ap.add_argument("--workload", default="plain_32cube")
     ap.add_argument("--no-headline", action="store_true",
                     help="run only the forms (for profiling one form); no headline record")
-    ap.add_argument("--learned-epochs", type=int, default=40,
+    ap.add_argument("--learned-epochs", type=int, default=LEARNED_EPOCHS,
                     help="training epochs of the learned forms")
     ap.add_argument("--learned-model", default=None,
                     help="the 8^3 learned form's network: loaded from this file if it "
