@@ -406,7 +406,8 @@ rt_status rt_batch_autotune(rt_ctx ctx, int n_cases, const rt_case* cases,
  * normalised over the training spectra.  It is trained on spectra of the
  * exact line sum (Eqs. (1)-(2)) for the current line list and spectral
  * grid.  rt_compute_kappa in RT_KAPPA_SURROGATE mode fills the kappa table
- * from it, recomputes with the line sum every cell outside the training
+ * from it (a last chunk that the spectrum ends inside is summed exactly
+ * instead when fewer than 256 lines meet a 512-point tile), recomputes with the line sum every cell outside the training
  * box, checks every chunk against the line sum on `check_cells` sampled
  * cells and recomputes the whole chunk for all cells when the relative error
  * of the chunk's absorptance along one cell edge h,
@@ -436,12 +437,18 @@ typedef struct {
   double infer_ms, check_ms, fallback_ms;  /* device times of the last
                                  inference when it ran with phase timing on
                                  (rt_surrogate_time_phases), else 0: the
-                                 network; from the network's end to the end
-                                 of the check (whose exact line
-                                 sum runs beside the network on a second
-                                 stream); the fallback                       */
+                                 network's launch (with the check's exact
+                                 rows, unless a long line list puts them on a
+                                 second stream, the exact last chunk and the
+                                 walls' row); from its end to the end of the
+                                 check; the fallback                         */
   double train_loss;          /* mean squared normalised error, last epoch   */
   double param_count;
+  int exact_chunks;           /* last inference: 1 when the spectrum ends
+                                 inside the last chunk and the line list is
+                                 light, the chunk's points then summed exactly
+                                 beside the network (never counted as a
+                                 fallback), else 0                           */
 } rt_surrogate_stats;
 
 /* Trains a new surrogate for the current line list and spectral grid

@@ -792,7 +792,9 @@ rt_status rt_compute_kappa(rt_ctx c, int mode, float* kappa_dev, float* planck_d
     RT_HIP(c, rt::launch_kappa(c, mode == RT_KAPPA_COMPENSATED));
   }
   if (rt_status s = record_end(c, c->kappa_events)) return s;
-  RT_HIP(c, rt::launch_planck(c));  // wall row always; cell table if requested
+  // wall row always (the learned form writes it in its first launch); cell
+  // table if requested
+  if (mode != RT_KAPPA_SURROGATE || c->planck) RT_HIP(c, rt::launch_planck(c));
   if (mode == RT_KAPPA_TABLE16) {
     double lines = c->lines.n;
     for (const auto& g : c->gas)

@@ -41,6 +41,7 @@ struct Surrogate {
   // last inference
   double check_error = 0;       // largest checked relative L1 error of a chunk
   int fallback_chunks = 0;      // chunks recomputed with the line sum
+  int exact_chunks = 0;  // last inference: chunks summed exactly beside the network
   int fallback_cells = 0;       // out-of-range cells recomputed
   double infer_ms = 0, check_ms = 0, fallback_ms = 0;
   double train_loss = 0;
@@ -50,7 +51,6 @@ struct Surrogate {
   int inf_check = 0, inf_chunks = 0;
   unsigned* d_cell_flag = nullptr;   // = epoch: cell outside the training box
   unsigned* d_group_flag = nullptr;  // = epoch: its line-sum group of cells
-  float4* d_cell_feat = nullptr;     // per cell: the three state features and u
   unsigned epoch = 0;                // inference calls so far
   float* d_err = nullptr;            // checked error per chunk
   int32_t* d_check = nullptr;   // sampled cells

@@ -326,26 +326,6 @@ __device__ __forceinline__ double gas_density(double T, double x, double p) {
   return x * p * kAtm / (kBoltzmann * T) * 1e-6;
 }
 
-// Per cell, once per inference: the three state features and u (the
-// network's rows of one cell share them), and the marks of a cell outside
-// the training box and of its line-sum group.
-__global__ void cell_features_kernel(const double* __restrict__ T, const double* __restrict__ x,
-                                     const double* __restrict__ p, int64_t n_cells, Box bx,
-                                     double T_lo, double T_hi, double x_lo, double x_hi,
-                                     double p_lo, double p_hi, unsigned epoch,
-                                     unsigned* cell_flag, unsigned* group_flag, float4* feat) {
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= n_cells) return;
-  const double t = T[cell], xc = x[cell], pc = p[cell];
-  float f[4];
-  features(bx, t, xc, pc, 0, f);
-  feat[cell] = make_float4(f[0], f[1], f[2], (float)gas_density(t, xc, pc));
-  if (!(t >= T_lo && t <= T_hi && xc >= x_lo && xc <= x_hi && pc >= p_lo && pc <= p_hi)) {
-    cell_flag[cell] = epoch;
-    group_flag[cell / dev::kKappaCells] = epoch;
-  }
-}
-
 // ------------------------------------------------------------ fused inference
 // One block of 8 wavefronts takes 32 RT rows (RT = 2 or 3) through all four
 // layers.  The hidden activations stay in LDS as BF16 (each row padded by 8
@@ -382,9 +362,18 @@ struct FusedArgs {
   const bf16* wt4;
   const float* b4;
   int64_t rows;
-  int64_t n_cells;  // FROM_STATE: rows = n_chunks x n_cells
+  int64_t n_cells;  // FROM_STATE: rows = (chunks given to the network) x n_cells
   const float* X0;  // [rows][4] features
-  const float4* cell_feat;  // per cell: three state features and u
+  // FROM_STATE: the cells' gas states, the training box, and the marks of
+  // the cells outside it (and of their line-sum groups) with this call's
+  // epoch, set by the rows of chunk 0
+  const double* T;
+  const double* x;
+  const double* p;
+  double T_lo, T_hi, x_lo, x_hi, p_lo, p_hi;
+  unsigned epoch;
+  unsigned* cell_flag;
+  unsigned* group_flag;
   Box bx;
   float* P;         // [rows][256]
   const float* mean;
@@ -392,7 +381,31 @@ struct FusedArgs {
   float* kappa;
   int64_t ld;
   int n_nu;
+  // TO_KAPPA: the blocks past the network's, in this order, on the CUs the
+  // network's blocks leave free:
+  //   x_blocks = x_groups x x_tiles: the exact rows of the sampled cells (xt);
+  //   tail_blocks: the exact line sum of every cell over the last chunk when
+  //     the spectrum ends inside it (tt, 256-point tiles at tail_j0);
+  //   wall_blocks: the walls' row B(nu_j, T_wall) of Eq. (4), 512 points each
+  //     (theta = c2 / T_wall as an FP32 pair, zero for cold walls).
+  int64_t net_blocks;
+  dev::KappaTile xt;
+  int x_tiles;
+  int64_t x_blocks;
+  dev::KappaTile tt;
+  int tail_j0;
+  int64_t tail_blocks;
+  int64_t wall_blocks;
+  float2 w_theta, w_nu0, w_dnu;
+  float w_c1;
+  float* wall;
 };
+
+// Points per lane of the exact rows computed beside the network (tiles of
+// 256 kExactPoints points): few, long blocks, one per free CU.
+constexpr int kExactPoints = 4;
+static_assert(sizeof(bf16) * 64 * kLdsRow >= sizeof(float) * dev::kLineTile * dev::kLineRec,
+              "the line-sum blocks stage their line records in the activations' LDS");
 
 // The transposed product of one layer, Z^T += W^T H^T over K = 512, for RT
 // row tiles x NT column tiles: the weights are the MFMA's A operand, the
@@ -515,7 +528,7 @@ __device__ __forceinline__ void split3(float x, bf16& hi, bf16& mid, bf16& lo) {
 template <int RT, bool FROM_STATE, bool TO_KAPPA>
 __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
   constexpr int kFuseRows = 32 * RT;
-  __shared__ bf16 H[kFuseRows * kLdsRow];
+  __shared__ __align__(16) bf16 H[kFuseRows * kLdsRow];
   __shared__ __align__(16) float F[kFuseRows][4];
   __shared__ float U[kFuseRows];
   __shared__ int64_t RowBase[kFuseRows];  // kappa offset of the row's chunk (-1: no row)
@@ -526,12 +539,51 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * kFuseRows;
   const int n_chunks = a.bx.n_chunks;
   const int h = lane >> 5;
+  if (TO_KAPPA && (int64_t)blockIdx.x >= a.net_blocks) {
+    int64_t xb = (int64_t)blockIdx.x - a.net_blocks;
+    if (xb >= a.x_blocks + a.tail_blocks) {  // the walls' row
+      const int64_t wb = xb - a.x_blocks - a.tail_blocks;
+      if (a.net_blocks == 0) {
+        // no network block clears the pitch columns [n_chunks 256, ld): these
+        // blocks do, an equal share of the cells each
+        const int64_t pad0 = (int64_t)n_chunks * kMlpWidth;
+        const int64_t share = (a.n_cells + a.wall_blocks - 1) / a.wall_blocks;
+        const int64_t c0 = wb * share, c1 = min(a.n_cells, c0 + share);
+        for (int64_t c = c0; c < c1; ++c)
+          for (int64_t j = pad0 + tid; j < a.ld; j += kFuseThreads) a.kappa[c * a.ld + j] = 0.f;
+      }
+      const int64_t j = wb * kFuseThreads + tid;
+      if (j < a.ld) {
+        float v = 0.f;
+        if (j < a.n_nu && a.w_theta.x > 0.f)
+          v = dev::planck_f32(dev::nu_at(j, dev::pair_of(a.w_nu0), dev::pair_of(a.w_dnu)),
+                              dev::pair_of(a.w_theta), a.w_c1);
+        a.wall[j] = v;
+      }
+      return;
+    }
+    // a line-sum block (Eq. (2)) over one tile of 8 cells, by its first four
+    // wavefronts (the line sum's block shape; the others end here, and a
+    // barrier waits only for the wavefronts still running), with the line
+    // records staged in H
+    if (wave >= dev::kKappaThreads / 64) return;
+    float* lds = reinterpret_cast<float*>(H);
+    if (xb < a.x_blocks) {
+      const int tile = (int)(xb % a.x_tiles);
+      dev::kappa_tile<false, false, kExactPoints>(a.xt, tile * dev::kKappaThreads * kExactPoints,
+                                                  (xb / a.x_tiles) * dev::kKappaCells, lds);
+    } else {
+      dev::kappa_tile<false, false, 1>(a.tt, a.tail_j0, (xb - a.x_blocks) * dev::kKappaCells,
+                                       lds);
+    }
+    return;
+  }
   if (TO_KAPPA) {
     // the pitch columns [n_chunks 256, ld) of every cell are zero: each block
     // clears those of an equal share of the cells (no block is left with
     // more than a few rows of them)
     const int64_t pad0 = (int64_t)n_chunks * kMlpWidth;
-    const int64_t share = (a.n_cells + gridDim.x - 1) / gridDim.x;
+    const int64_t share = (a.n_cells + a.net_blocks - 1) / a.net_blocks;
     const int64_t c0 = (int64_t)blockIdx.x * share, c1 = min(a.n_cells, c0 + share);
     for (int64_t c = c0; c < c1; ++c)
       for (int64_t j = pad0 + tid; j < a.ld; j += kFuseThreads) a.kappa[c * a.ld + j] = 0.f;
@@ -546,13 +598,15 @@ __global__ __launch_bounds__(kFuseThreads) void mlp_fused_kernel(FusedArgs a) {
       if (FROM_STATE) {
         k = (int)(row / a.n_cells);
         const int64_t cell = row - (int64_t)k * a.n_cells;
-        const float4 cf = a.cell_feat[cell];
-        f[0] = cf.x;
-        f[1] = cf.y;
-        f[2] = cf.z;
-        f[3] = chunk_feature(a.bx, k);
-        u = cf.w;
+        const double t = a.T[cell], xc = a.x[cell], pc = a.p[cell];
+        features(a.bx, t, xc, pc, k, f);
+        u = (float)gas_density(t, xc, pc);
         base = cell * a.ld + (int64_t)k * kMlpWidth;
+        if (k == 0 && !(t >= a.T_lo && t <= a.T_hi && xc >= a.x_lo && xc <= a.x_hi &&
+                        pc >= a.p_lo && pc <= a.p_hi)) {
+          a.cell_flag[cell] = a.epoch;
+          a.group_flag[cell / dev::kKappaCells] = a.epoch;
+        }
       } else {
         for (int q = 0; q < 4; ++q) f[q] = a.X0[4 * row + q];
         base = row * kMlpWidth;
@@ -742,8 +796,9 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(float* __restrict__ x, i
 }
 
 // One block of 1024 threads per chunk: thread t owns point k * 256 + t % 256
-// of the sampled cells t / 256, t / 256 + 4, ...; the block's sums are
-// reduced in a fixed tree.
+// of the sampled cells t / 256, t / 256 + 4, ...; each wavefront sums its
+// lanes with a fixed butterfly, and thread 0 adds the 16 wavefront sums in
+// order (the same order on every call).
 constexpr int kCheckThreads = 1024;
 __global__ __launch_bounds__(kCheckThreads) void check_kernel(
     const float* __restrict__ kappa, int64_t ld, const float* __restrict__ exact, int64_t ld_e,
@@ -752,8 +807,9 @@ __global__ __launch_bounds__(kCheckThreads) void check_kernel(
   const int k = blockIdx.x;  // chunk
   const int t = threadIdx.x;
   constexpr int kGroups = kCheckThreads / kMlpWidth;
+  constexpr int kWaves = kCheckThreads / 64;
   __shared__ int64_t row[kMaxCheckCells];  // kappa row offset, -1: left out
-  __shared__ float rd[kCheckThreads], rs[kCheckThreads];
+  __shared__ float rd[kWaves], rs[kWaves];
   for (int ci = t; ci < n_check; ci += kCheckThreads) {
     const int cell = cells[ci];
     row[ci] = cell_flag[cell] == epoch ? -1 : (int64_t)cell * ld;
@@ -762,25 +818,55 @@ __global__ __launch_bounds__(kCheckThreads) void check_kernel(
   const int j = k * kMlpWidth + (t % kMlpWidth);
   float d = 0, s = 0;
   if (j < n_nu) {
-    for (int ci = t / kMlpWidth; ci < n_check; ci += kGroups) {
-      if (row[ci] < 0) continue;
-      const float e = -expm1f(-exact[(int64_t)ci * ld_e + j] * l_cm);
-      const float g = -expm1f(-kappa[row[ci] + j] * l_cm);
-      d += g - e;
-      s += e;
+    // kU cells at a time, their loads issued together
+    constexpr int kU = 8;
+    for (int c0 = t / kMlpWidth; c0 < n_check; c0 += kGroups * kU) {
+      float ev[kU], gv[kU];
+      bool on[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int ci = c0 + u * kGroups;
+        on[u] = ci < n_check && row[ci] >= 0;
+        ev[u] = on[u] ? exact[(int64_t)ci * ld_e + j] : 0.f;
+        gv[u] = on[u] ? kappa[row[ci] + j] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (!on[u]) continue;
+        const float e = -expm1f(-ev[u] * l_cm);
+        const float g = -expm1f(-gv[u] * l_cm);
+        d += g - e;
+        s += e;
+      }
     }
   }
-  rd[t] = d;
-  rs[t] = s;
-  __syncthreads();
-  for (int off = kCheckThreads / 2; off > 0; off >>= 1) {
-    if (t < off) { rd[t] += rd[t + off]; rs[t] += rs[t + off]; }
-    __syncthreads();
+  // every lane ends with the same sums (a + b == b + a)
+  for (int off = 32; off > 0; off >>= 1) {
+    d += __shfl_xor(d, off);
+    s += __shfl_xor(s, off);
   }
-  if (t == 0) err[k] = rs[0] > 0 ? fabsf(rd[0]) / rs[0] : (rd[0] != 0 ? 1e30f : 0.0f);
+  if ((t & 63) == 0) {
+    rd[t >> 6] = d;
+    rs[t >> 6] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    float D = 0, S = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      D += rd[w];
+      S += rs[w];
+    }
+    err[k] = S > 0 ? fabsf(D) / S : (D != 0 ? 1e30f : 0.0f);
+  }
 }
 
 int64_t grid1(int64_t n) { return (n + 255) / 256; }
+
+// v as an FP32 pair hi + lo.
+float2 host_pair(double v) {
+  const float h = (float)v;
+  return make_float2(h, (float)(v - (double)h));
+}
 
 
 // deterministic 64-bit generator for weight init and shuffles (splitmix64)
@@ -988,17 +1074,37 @@ void pack_weights(const Surrogate& S, hipStream_t s) {
 
 // The fused kernel over `rows` rows: features X0 or gas states in, raw
 // outputs P or the kappa table out.
+// What an inference launch does besides the network (see FusedArgs).
+struct InferJob {
+  int64_t n_cells;
+  unsigned epoch;
+  const dev::KappaTile* xt = nullptr;  // exact rows of the sampled cells
+  int64_t x_groups = 0;
+  const dev::KappaTile* tt = nullptr;  // the last chunk's exact line sum
+  int tail_j0 = 0;
+  int64_t tail_groups = 0;
+};
+
+// job null: the network alone on given features, raw outputs into P.
+// Otherwise inference from the cells' states into the kappa table, with the
+// job's line-sum blocks and the walls' row in the same launch.
 void launch_fused(rt_ctx c, const Surrogate& S, int64_t rows, const float* X0, float* P,
-                  bool to_kappa, hipStream_t s) {
+                  hipStream_t s, const InferJob* job) {
   FusedArgs a;
   a.W1k = S.wk[0]; a.b1 = S.b[0];
   a.wt2 = S.wf[1]; a.b2 = S.b[1];
   a.wt3 = S.wf[2]; a.b3 = S.b[2];
   a.wt4 = S.wf[3]; a.b4 = S.b[3];
   a.rows = rows;
-  a.n_cells = S.n_chunks > 0 ? rows / S.n_chunks : 0;
+  a.n_cells = job ? job->n_cells : 0;
   a.X0 = X0;
-  a.cell_feat = S.d_cell_feat;
+  a.T = c->d_T; a.x = c->d_x; a.p = c->d_p;
+  a.T_lo = S.T_min; a.T_hi = S.T_max;
+  a.x_lo = S.x_min; a.x_hi = S.x_max;
+  a.p_lo = S.p_min; a.p_hi = S.p_max;
+  a.epoch = job ? job->epoch : 0;
+  a.cell_flag = S.d_cell_flag;
+  a.group_flag = S.d_group_flag;
   a.bx = make_box(S);
   a.P = P;
   a.mean = S.mean; a.stdv = S.stdv;
@@ -1015,10 +1121,33 @@ void launch_fused(rt_ctx c, const Surrogate& S, int64_t rows, const float* X0, f
     if (cost < best_cost) { best_cost = cost; best = rt; }
   }
   const dim3 t(kFuseThreads);
+  a.x_tiles = 1;
+  a.x_blocks = a.tail_blocks = a.wall_blocks = 0;
+  if (job) {
+    if (job->xt && job->x_groups > 0) {
+      a.xt = *job->xt;
+      a.x_tiles = (int)((c->ld + dev::kKappaThreads * kExactPoints - 1) /
+                        (dev::kKappaThreads * kExactPoints));
+      a.x_blocks = job->x_groups * a.x_tiles;
+    }
+    if (job->tt && job->tail_groups > 0) {
+      a.tt = *job->tt;
+      a.tail_j0 = job->tail_j0;
+      a.tail_blocks = job->tail_groups;
+    }
+    a.wall_blocks = (c->ld + kFuseThreads - 1) / kFuseThreads;
+    a.w_theta = c->T_wall > 0.0 ? host_pair(second_radiation_cm_K() / c->T_wall)
+                                : make_float2(0.f, 0.f);
+    a.w_nu0 = host_pair(c->nu0);
+    a.w_dnu = host_pair(c->dnu);
+    a.w_c1 = (float)first_radiation_wavenumber();
+    a.wall = c->d_bwall;
+  }
   auto go = [&](auto rt_tag) {
     constexpr int RT = decltype(rt_tag)::value;
-    const dim3 g((unsigned)((rows + 32 * RT - 1) / (32 * RT)));
-    if (to_kappa) hipLaunchKernelGGL((mlp_fused_kernel<RT, true, true>), g, t, 0, s, a);
+    a.net_blocks = (rows + 32 * RT - 1) / (32 * RT);
+    const dim3 g((unsigned)(a.net_blocks + a.x_blocks + a.tail_blocks + a.wall_blocks));
+    if (job) hipLaunchKernelGGL((mlp_fused_kernel<RT, true, true>), g, t, 0, s, a);
     else hipLaunchKernelGGL((mlp_fused_kernel<RT, false, false>), g, t, 0, s, a);
   };
   if (best == 2) go(std::integral_constant<int, 2>());
@@ -1036,7 +1165,7 @@ void free_surrogate(rt_ctx c) {
   }
   dfree(S.mean); dfree(S.stdv);
   dfree(S.d_cell_flag); dfree(S.d_group_flag); dfree(S.d_err); dfree(S.d_check);
-  dfree(S.d_exact); dfree(S.d_cell_feat);
+  dfree(S.d_exact);
   for (auto& e : S.ev)
     if (e) (void)hipEventDestroy(e);
   if (S.fork) (void)hipEventDestroy(S.fork);
@@ -1063,15 +1192,31 @@ bool surrogate_ready(rt_ctx c) {
 // that a few sampled cells do not leave most of the GPU idle, but no share
 // under about 128 lines (a tile's window meets n (512 + 2K) / n_nu lines on
 // average), and at most 32.
+// Lines whose window meets a line-sum tile of kKappaTilePoints points, on
+// average over the spectrum.
+double lines_per_tile(rt_ctx c) {
+  return (double)c->lines.n * (dev::kKappaTilePoints + 2.0 * c->K) / std::max(1, c->n_nu);
+}
+
 int check_parts(rt_ctx c, int n_check) {
   const int64_t tiles = (c->ld + dev::kKappaTilePoints - 1) / dev::kKappaTilePoints;
   const int64_t blocks = (int64_t)((n_check + dev::kKappaCells - 1) / dev::kKappaCells) * tiles;
   if (blocks <= 0) return 1;
-  const double per_tile = (double)c->lines.n * (dev::kKappaTilePoints + 2.0 * c->K) /
-                          std::max(1, c->n_nu);
-  const int64_t by_lines = (int64_t)(per_tile / 128.0);
+  const int64_t by_lines = (int64_t)(lines_per_tile(c) / 128.0);
   const int64_t by_blocks = (2048 + blocks - 1) / blocks;
   return (int)std::max<int64_t>(1, std::min<int64_t>(32, std::min(by_lines, by_blocks)));
+}
+
+// 1 when the spectrum ends inside the last 256-point chunk and the line
+// list is light (fewer than 256 lines meet a tile, as when the check's exact
+// rows run in the network's launch): that chunk is then summed exactly beside
+// the network; else 0 (with many lines per point its blocks would outlast
+// the network).
+int exact_tail_chunks(rt_ctx c, const Surrogate& S) {
+  return S.n_chunks > 0 && (int64_t)S.n_chunks * kMlpWidth > c->n_nu &&
+                 lines_per_tile(c) < 256.0
+             ? 1
+             : 0;
 }
 
 // The counts and timings are read back lazily by rt_surrogate_get_stats.
@@ -1089,9 +1234,8 @@ rt_status surrogate_kappa(rt_ctx c) {
   if (S.inf_cells != n_cells || S.inf_ld != c->ld || S.inf_check != n_check ||
       S.inf_chunks != S.n_chunks || !S.d_cell_flag) {
     dfree(S.d_cell_flag); dfree(S.d_group_flag); dfree(S.d_err); dfree(S.d_check);
-    dfree(S.d_exact); dfree(S.d_cell_feat);
+    dfree(S.d_exact);
     ok = chk(dalloc(&S.d_cell_flag, n_cells)) && chk(dalloc(&S.d_group_flag, groups_all)) &&
-         chk(dalloc(&S.d_cell_feat, n_cells)) &&
          chk(dalloc(&S.d_err, S.n_chunks)) && chk(dalloc(&S.d_check, std::max(1, n_check))) &&
          chk(dalloc(&S.d_exact, std::max<int64_t>(1, (int64_t)check_parts(c, n_check) * n_check * c->ld)));
     // marks start at 0, which no call uses as its epoch
@@ -1149,11 +1293,18 @@ rt_status surrogate_kappa(rt_ctx c) {
   t.col_end = c->ld;
   const int tiles_all = (int)((c->ld + dev::kKappaTilePoints - 1) / dev::kKappaTilePoints);
 
-  // the exact rows of the sampled cells do not depend on the network: they
-  // are summed on the side stream while the network runs.  The fork is
-  // recorded first, but the side stream's launches are issued after the
-  // network's, so that the handle's stream starts at once (issuing them
-  // takes the host longer than the side stream's work takes the GPU)
+  // The exact rows of the sampled cells do not depend on the network, so they
+  // are summed while it runs.  When they are few and light (one line share
+  // per tile), extra blocks of the network's own launch compute them on the
+  // CUs its blocks leave free; otherwise (long line lists, many blocks) they
+  // run on a second stream, forked before the network and joined before the
+  // check.  The fork is recorded first, but the side stream's launches are
+  // issued after the network's, so that the handle's stream starts at once.
+  // When the spectrum ends inside the last chunk and the line list is light,
+  // that chunk's few points are not given to the network (its check, over
+  // those few points, is the noisiest): extra blocks of the same launch sum
+  // them exactly for every cell.  The same launch also writes the walls' row
+  // of Eq. (4).
   // Phase times, when asked for, come from events recorded between the
   // kernels (before and after the network, after the check and after the
   // fallback); each costs the call several microseconds, so by default none
@@ -1162,39 +1313,48 @@ rt_status surrogate_kappa(rt_ctx c) {
   auto mark = [&](int i) {
     if (S.time_phases) (void)hipEventRecord(S.ev[i], s);
   };
-  if (ok && n_check > 0) ok = chk(hipEventRecord(S.fork, s));
-  if (n_cells > 0)
-    hipLaunchKernelGGL(cell_features_kernel, dim3((unsigned)grid1(n_cells)), dim3(256), 0, s,
-                       c->d_T, c->d_x, c->d_p, n_cells, make_box(S), S.T_min, S.T_max, S.x_min,
-                       S.x_max, S.p_min, S.p_max, S.epoch, S.d_cell_flag, S.d_group_flag,
-                       S.d_cell_feat);
+  dev::KappaTile te = t;
+  te.cell_list = S.d_check;
+  te.n_cells = n_check;
+  te.out = S.d_exact;
+  te.compact_rows = 1;
+  const int64_t check_groups = (n_check + dev::kKappaCells - 1) / dev::kKappaCells;
+  const int parts = n_check > 0 ? check_parts(c, n_check) : 1;
+  const bool side = n_check > 0 && parts > 1;
+  if (ok && side) ok = chk(hipEventRecord(S.fork, s));
+  const int net_chunks = S.n_chunks - exact_tail_chunks(c, S);
+  S.exact_chunks = S.n_chunks - net_chunks;
+  InferJob job;
+  job.n_cells = n_cells;
+  job.epoch = S.epoch;
+  if (n_check > 0 && !side) {
+    job.xt = &te;
+    job.x_groups = check_groups;
+  }
+  if (net_chunks < S.n_chunks) {
+    job.tt = &t;
+    job.tail_j0 = net_chunks * kMlpWidth;
+    job.tail_groups = groups_all;
+  }
   mark(0);
-  launch_fused(c, S, rows, nullptr, nullptr, true, s);
+  launch_fused(c, S, n_cells * net_chunks, nullptr, nullptr, s, &job);
   mark(1);
   ok = ok && chk(hipGetLastError());
-  if (ok && n_check > 0) {
-    ok = chk(hipStreamWaitEvent(S.side, S.fork, 0));
-    dev::KappaTile te = t;
-    te.cell_list = S.d_check;
-    te.n_cells = n_check;
-    te.out = S.d_exact;
-    te.compact_rows = 1;
-    const int parts = check_parts(c, n_check);
+  if (ok && side) {
     const int64_t part_stride = (int64_t)n_check * c->ld;
-    ok = ok && chk(launch_kappa_tiles(c, te, (n_check + dev::kKappaCells - 1) / dev::kKappaCells,
-                                      0, tiles_all, false, S.side, dev::TileGate(), parts,
-                                      part_stride));
-    if (ok && parts > 1)
+    ok = chk(hipStreamWaitEvent(S.side, S.fork, 0)) &&
+         chk(launch_kappa_tiles(c, te, check_groups, 0, tiles_all, false, S.side,
+                                dev::TileGate(), parts, part_stride));
+    if (ok)
       hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)grid1(part_stride)), dim3(256), 0,
                          S.side, S.d_exact, part_stride, parts, part_stride);
-    ok = ok && chk(hipGetLastError()) && chk(hipEventRecord(S.join, S.side));
+    ok = ok && chk(hipGetLastError()) && chk(hipEventRecord(S.join, S.side)) &&
+         chk(hipStreamWaitEvent(s, S.join, 0));
   }
   if (ok && n_check > 0) {
-    ok = chk(hipStreamWaitEvent(s, S.join, 0));
-    if (ok)
-      hipLaunchKernelGGL(check_kernel, dim3(S.n_chunks), dim3(kCheckThreads), 0, s, c->kappa, c->ld,
-                         S.d_exact, c->ld, S.d_check, n_check, c->n_nu,
-                         (float)(c->cell_m * 100.0), S.d_cell_flag, S.epoch, S.d_err);
+    hipLaunchKernelGGL(check_kernel, dim3(S.n_chunks), dim3(kCheckThreads), 0, s, c->kappa, c->ld,
+                       S.d_exact, c->ld, S.d_check, n_check, c->n_nu,
+                       (float)(c->cell_m * 100.0), S.d_cell_flag, S.epoch, S.d_err);
   } else if (ok) {
     hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(S.n_chunks)), dim3(256), 0, s, S.d_err,
                        (int64_t)S.n_chunks);
@@ -1438,7 +1598,7 @@ rt_status rt_surrogate_forward(rt_ctx c, int n_rows, const float* inputs, float*
   if (e == hipSuccess)
     e = hipMemcpyAsync(X0, inputs, (size_t)n_rows * 16, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) {
-    launch_fused(c, S, n_rows, X0, P, false, c->stream);
+    launch_fused(c, S, n_rows, X0, P, c->stream, nullptr);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
@@ -1486,6 +1646,7 @@ rt_status rt_surrogate_get_stats(rt_ctx c, rt_surrogate_stats* out) {
   out->fallback_ms = S.fallback_ms;
   out->train_loss = S.train_loss;
   out->param_count = (double)S.param_count;
+  out->exact_chunks = S.exact_chunks;
   return RT_OK;
 }
 

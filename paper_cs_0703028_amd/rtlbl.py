@@ -84,7 +84,8 @@ class SurrogateStats(C.Structure):
     _fields_ = [("check_error", C.c_double), ("fallback_chunks", C.c_int),
                 ("fallback_cells", C.c_int), ("n_chunks", C.c_int), ("infer_ms", C.c_double),
                 ("check_ms", C.c_double), ("fallback_ms", C.c_double),
-                ("train_loss", C.c_double), ("param_count", C.c_double)]
+                ("train_loss", C.c_double), ("param_count", C.c_double),
+                ("exact_chunks", C.c_int)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -132,10 +132,16 @@ def test_trained_network_drives_the_march(rt, bench_trained):
                 if not np.array_equal(k1[:, 256 * k:min(256 * (k + 1), nz)],
                                       k0[:, 256 * k:min(256 * (k + 1), nz)])]
     print(f"chunks whose kappa comes from the network: {len(from_net)}", flush=True)
+    # the spectrum (10,000 points) ends inside the last 256-point chunk: its
+    # 16 points are summed exactly beside the network, bit for bit as the
+    # plain line sum
+    assert st["exact_chunks"] == (1 if nz % 256 else 0)
+    last = 256 * (st["n_chunks"] - 1)
+    assert np.array_equal(k1[:, last:nz], k0[:, last:nz])
     # the fallback recomputes exactly the chunks over tolerance (each
     # line-sum wavefront covers points of one chunk), bit for bit as the
     # plain line sum; every other chunk keeps the network's values
-    assert len(from_net) == st["n_chunks"] - st["fallback_chunks"] > 0
+    assert len(from_net) == st["n_chunks"] - st["fallback_chunks"] - st["exact_chunks"] > 0
     t.reset_tally()
     t.trace_rays(w.seed, w.n_rays)
     a1, e1, _ = t.tally()
@@ -387,7 +393,12 @@ def test_corrupted_model_trips_the_check_and_falls_back(rt, trained, tmp_path):
         assert np.array_equal(k1[:, 256 * k:256 * (k + 1)], k0[:, 256 * k:256 * (k + 1)])
     assert st["fallback_chunks"] == len(bad)
     # every clean chunk keeps the network's values, the neighbours that share
-    # a 512-point line-sum tile with a corrupted chunk included
-    for k in range(n_chunks):
+    # a 512-point line-sum tile with a corrupted chunk included; a last chunk
+    # that the spectrum ends inside is summed exactly
+    nz = w.lines.n_nu
+    assert st["exact_chunks"] == (1 if nz % 256 else 0)
+    assert np.array_equal(k1[:, 256 * (n_chunks - 1):nz], k0[:, 256 * (n_chunks - 1):nz]) \
+        or not st["exact_chunks"]
+    for k in range(n_chunks - st["exact_chunks"]):
         if k not in bad:
             assert not np.array_equal(k1[:, 256 * k:256 * (k + 1)], k0[:, 256 * k:256 * (k + 1)])
