@@ -402,3 +402,46 @@ def test_corrupted_model_trips_the_check_and_falls_back(rt, trained, tmp_path):
     for k in range(n_chunks - st["exact_chunks"]):
         if k not in bad:
             assert not np.array_equal(k1[:, 256 * k:256 * (k + 1)], k0[:, 256 * k:256 * (k + 1)])
+
+
+def test_long_line_list_checks_on_a_second_stream(rt):
+    """With 20,000 lines over the 8^3 workload's 100 cm^-1, about 3,000 lines
+    meet each line-sum tile: the check's exact rows are then summed on a
+    second stream in line shares instead of in the network's launch, and the
+    last, partial chunk is left to the network (exact_chunks 0).  Every chunk
+    holds either the network's values or the line sum's bit for bit, the
+    latter exactly the chunks counted as fallen back, and the tallies stay
+    within the learned form's 1e-3 of the plain path."""
+    w = I.plain_8cube()
+    dense = I.line_list(20000, 1000.0, 1100.0, n_nu=w.lines.n_nu)
+    w = I.with_lines(w, **vars(dense))
+    t = rt.Tracer(0)
+    t.setup_grid(w.grid)
+    t.setup_lines(w.lines)
+    # trained well enough for the bar: on this list the check is nearly blind
+    # (most points are saturated over a cell edge), and a network trained on
+    # 4,096 states (loss 4e-2) passed it everywhere at 1.3e-3 per cell
+    T, x, p = I.surrogate_samples(1 << 15, seed=2)
+    print("training a surrogate on 20,000 lines (2^15 states, 40 epochs)", flush=True)
+    t.surrogate_train(T, x, p, I.SURROGATE_BOX, epochs=40, batch=1024, lr=2e-3, seed=5,
+                      check_cells=32, tolerance=5e-4)
+    kap, _ = t.alloc_tables()
+    t.compute_kappa(rt.KAPPA_SURROGATE, kap, None)
+    st = t.surrogate_stats()
+    print("surrogate stats", st, flush=True)
+    assert st["exact_chunks"] == 0 and st["fallback_cells"] == 0
+    k1 = kap.cpu().numpy()
+    a0, e0, k0 = _plain_run(rt, w)
+    nz = w.lines.n_nu
+    same = sum(np.array_equal(k1[:, 256 * k:min(256 * (k + 1), nz)],
+                              k0[:, 256 * k:min(256 * (k + 1), nz)])
+               for k in range(st["n_chunks"]))
+    assert same == st["fallback_chunks"]
+    t.reset_tally()
+    t.trace_rays(w.seed, w.n_rays)
+    a1, e1, _ = t.tally()
+    t.close()
+    ra = np.abs(a1 - a0)[a0 > 0] / a0[a0 > 0]
+    re_ = np.abs(e1 - e0)[e0 > 0] / e0[e0 > 0]
+    print(f"per-cell absorbed rel err max {ra.max():.3e}, emitted {re_.max():.3e}", flush=True)
+    assert ra.max() <= 1e-3 and re_.max() <= 1e-3
