@@ -57,9 +57,10 @@ struct Surrogate {
   float* d_exact = nullptr;     // their exact rows
   uint64_t pick_epoch = ~0ull;  // grid the sampled cells were drawn for
   hipEvent_t ev[4] = {};
-  // the check's exact line sum runs on a second stream of the handle's
-  // device (default priority), beside the network: forked after the
-  // previous work of the handle's stream and joined before the check
+  // with long line lists the check's exact line sum runs on a second
+  // stream of the handle's device (default priority), beside the network:
+  // forked after the previous work of the handle's stream and joined before
+  // the check
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   bool stats_pending = false;   // counts of the last inference not read yet

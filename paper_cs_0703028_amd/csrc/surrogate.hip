@@ -15,8 +15,8 @@
 //
 // Inference fills the kappa table; cells outside the training box are
 // recomputed with the line sum; every chunk is checked against the line
-// sum on a few sampled cells and recomputed for all cells when its relative
-// L1 error exceeds the tolerance.
+// sum on a few sampled cells and recomputed for all cells when the relative
+// error of its summed absorptance exceeds the tolerance.
 #include <algorithm>
 #include <type_traits>
 #include <cmath>
@@ -1181,12 +1181,14 @@ bool surrogate_ready(rt_ctx c) {
 
 // Learned kappa into c->kappa, stream-ordered launches with every decision
 // taken on the device (no host round trip):
-//   1. the fused network writes kappa and marks cells outside the training
-//      box (and their line-sum groups) with this call's epoch;
-//   2. exact rows of the sampled cells, on the side stream beside step 1
-//      (forked after the handle's stream's earlier work, joined before 3);
-//   3. the checked error per chunk (marked cells left out);
-//   4. the line sum over every tile that touches a chunk over tolerance or a
+//   1. one launch: the fused network writes kappa and marks cells outside
+//      the training box (and their line-sum groups) with this call's epoch;
+//      beside it, on the CUs its blocks leave free, the exact rows of the
+//      sampled cells (with long line lists: on a second stream instead,
+//      forked before the launch and joined before 2), a last chunk that the
+//      spectrum ends inside (light line lists) and the walls' row;
+//   2. the checked error per chunk (marked cells left out);
+//   3. the line sum over every tile that touches a chunk over tolerance or a
 //      marked group of cells.
 // Line shares per tile of the check's line sum: enough blocks (about 2,048)
 // that a few sampled cells do not leave most of the GPU idle, but no share
