@@ -1,9 +1,11 @@
-"""The Python binding's ctypes mirrors of the public structs of
-include/rtlbl.h have the C compiler's layout: a C program built with gcc
-against the header prints each struct's size and the offset of every field
-the binding names, and they must equal the ctypes ones.  (A field added to
-the header but not to the binding, or in another place, changes a size or an
-offset; a field the header lacks fails to compile.)  Host only."""
+"""The Python binding agrees with include/rtlbl.h, as the C compiler reads
+it (small C programs built with gcc against the header print the values):
+* its ctypes mirrors of the public structs have the C layout: each struct's
+  size and the offset of every field the binding names (a field added to
+  the header but not to the binding, or in another place, changes a size or
+  an offset; a field the header lacks fails to compile);
+* its integer constants equal the header's enumerators and macros.
+Host only."""
 import ctypes as C
 import os
 import shutil
@@ -60,3 +62,55 @@ def test_ctypes_layouts_match_the_header(tmp_path):
         assert got[(py, "size")] == C.sizeof(cls), py
         for name, _ in cls._fields_:
             assert got[(py, name)] == getattr(cls, name).offset, (py, name)
+
+
+def _binding_constants():
+    """The binding's top-level integer constants and its arithmetic-op codes,
+    read from its source with literal evaluation only."""
+    import ast
+    src = open(os.path.join(ROOT, "paper_cs_0703028_amd", "rtlbl.py")).read()
+    out = {}
+    for node in ast.parse(src).body:
+        if not isinstance(node, ast.Assign) or len(node.targets) != 1:
+            continue
+        tgt = node.targets[0]
+        try:
+            val = ast.literal_eval(node.value)
+        except ValueError:
+            continue
+        if isinstance(tgt, ast.Name) and isinstance(val, int):
+            out[tgt.id] = val
+        elif isinstance(tgt, ast.Tuple) and isinstance(val, tuple):
+            for e, v in zip(tgt.elts, val):
+                out[e.id] = v
+        elif isinstance(tgt, ast.Name) and tgt.id == "ARITH_OPS":
+            for name, (code, _) in val.items():
+                out["AR_" + name.upper()] = code
+    return out
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="no gcc")
+def test_binding_constants_match_the_header(tmp_path):
+    """Status codes, kappa modes, tally precisions, batch modes, the
+    arithmetic-op codes and the two macros, as the header defines them."""
+    consts = _binding_constants()
+    # binding name -> header name
+    names = {k: k for k in ("RT_OK", "RT_EINVAL", "RT_ENOMEM", "RT_EDEVICE", "RT_ESTATE",
+                            "RT_EUNSUPPORTED", "RT_NO_DEVICE")}
+    names.update({k: "RT_" + k for k in consts
+                  if k.startswith(("KAPPA_", "TALLY_", "BATCH_", "AR_"))})
+    names["ADAPTIVE_GROUP"] = "RT_ADAPTIVE_GROUP"
+    lines = ["#include <stdio.h>", '#include "rtlbl.h"', "int main(void) {"]
+    for py, h in names.items():
+        lines.append(f'  printf("{py} %d\\n", (int)({h}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "consts.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict((a, int(b)) for a, b in (line.split() for line in out.splitlines()))
+    assert len(got) >= 30
+    for py in names:
+        assert got[py] == consts[py], py
