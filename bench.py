@@ -385,7 +385,9 @@ def form_learned(rtlbl, I, epochs=LEARNED_EPOCHS, n_lines=None, model_path=None)
     ra = np.abs(a1 - a0)[a0 > 0] / a0[a0 > 0]
     re_ = np.abs(e1 - e0)[e0 > 0] / e0[e0 > 0]
     # the network's rows: every chunk but a last one the spectrum ends inside
-    # (summed exactly in the same launch)
+    # (summed exactly in the same launch).  infer_ms times that whole launch,
+    # whose line-sum blocks (the check's exact rows, the last chunk) run on
+    # the CUs the network leaves free, so the rate is the launch's
     flops = 2.0 * MLP_WEIGHTS * w.grid.n_cells * (st["n_chunks"] - st["exact_chunks"])
     return {
         "workload": w.name,
